@@ -1,0 +1,186 @@
+"""Pins of the oracle's Newton-CG homogenization solve (paper Sec. 2-4) to exact
+solutions and to properties the continuous problem fixes: homogeneous and
+single-voxel RVEs, planar laminates (exact under ComBo, Sec. 4.1), Hill-Mandel,
+<F> = Fbar, frame invariance, mirror symmetry, the effective tangent against
+finite differences, and the Voigt/Reuss bounds."""
+import numpy as np
+import pytest
+from scipy import optimize
+
+from oracle import material, solver
+from paper_2204_13624_amd import synth
+
+MATS = ((1.0, 2.0), (10.0, 20.0))
+TIGHT = solver.Options(tol_newton=1e-12, tol_cg=1e-12)
+
+
+def problem(ms, mats=MATS):
+    return solver.Problem(ms.n, ms.l, ms.phase, ms.c, ms.N, mats)
+
+
+def rotation(rng):
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    return q
+
+
+def exact_laminate(Fbar, phi, N, mats):
+    """Rank-one laminate with inclusion fraction phi and normal N: traction
+    continuity solved by scipy, F+- built here from the Hadamard condition."""
+    N = np.asarray(N, float)
+
+    def parts(a):
+        Fp = Fbar + np.outer(a, N) / phi
+        Fm = Fbar - np.outer(a, N) / (1 - phi)
+        return material.stress(Fp[None], *mats[1])[0], material.stress(Fm[None], *mats[0])[0]
+
+    sol = optimize.root(lambda a: (parts(a)[0] - parts(a)[1]) @ N, np.zeros(3), method="hybr", tol=1e-15)
+    Pp, Pm = parts(sol.x)
+    return phi * Pp + (1 - phi) * Pm
+
+
+FBAR = np.array([[1.08, 0.12, -0.03], [0.05, 0.97, 0.04], [-0.02, 0.06, 1.02]])
+
+
+def test_homogeneous_rve_is_exact():
+    for ph in (0, 1):
+        ms = synth.homogeneous((4, 5, 3), phase_id=ph)
+        r = solver.solve(problem(ms), FBAR, TIGHT)
+        assert r["stats"]["newton_iters"] == 0
+        assert np.abs(r["F"] - FBAR[:, :, None, None, None]).max() <= 1e-15
+        assert np.abs(r["Pbar"] - material.stress(FBAR[None], *MATS[ph])[0]).max() <= 1e-14
+
+
+def test_single_composite_voxel_and_uniform_composite():
+    from oracle import laminate
+    N = np.array([0.3, -0.5, 0.8])
+    N /= np.linalg.norm(N)
+    ref = laminate.solve(FBAR[None], np.array([0.37]), N[None], MATS[0], MATS[1])["P"][0]
+    for n in ((1, 1, 1), (3, 4, 5)):
+        ms = synth.uniform_composite(n, 0.37, N)
+        r = solver.solve(problem(ms), FBAR, TIGHT)
+        assert r["stats"]["newton_iters"] == 0
+        assert np.abs(r["F"] - FBAR[:, :, None, None, None]).max() <= 1e-15
+        assert np.abs(r["Pbar"] - ref).max() <= 1e-14 * 10
+
+
+@pytest.mark.parametrize("n,l,axis,interfaces", [
+    ((9, 3, 4), (1.0, 1.0, 1.0), 0, (-0.5 + 2 / 9, -0.5 + 6 / 9)),        # odd n along N, pure voxels
+    ((8, 2, 3), (1.0, 1.0, 1.0), 0, (-0.25, 0.25)),                      # even n, even layer widths
+    ((3, 9, 2), (0.5, 1.5, 2.0), 1, (-0.75 + 1.5 / 9, -0.75 + 5 * 1.5 / 9)),  # boxels, normal e2
+    ((2, 3, 7), (1.0, 0.7, 1.4), 2, (-0.7 + 1.4 * 3 / 7, 0.7 - 1.4 / 7)),   # normal e3
+])
+def test_grid_aligned_laminate_is_exact(n, l, axis, interfaces):
+    ms = synth.layered(n, l, axis, interfaces)
+    assert ms.n_composite == 0
+    phi = float(ms.c.mean())
+    N = np.eye(3)[axis]
+    r = solver.solve(problem(ms), FBAR, TIGHT)
+    ref = exact_laminate(FBAR, phi, N, MATS)
+    assert np.abs(r["Pbar"] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,interfaces", [((9, 2, 3), (-0.5 + 2.25 / 9, -0.5 + 6.5 / 9)),
+                                          ((7, 3, 2), (-0.5 + 1.75 / 7, -0.5 + 4.75 / 7))])
+def test_laminate_through_composite_columns_is_exact(n, interfaces):
+    """Planar interfaces inside composite voxels: ComBo reproduces the laminate."""
+    ms = synth.layered(n, (1.0, 1.0, 1.0), 0, interfaces)
+    assert ms.n_composite > 0
+    phi = float(ms.c.mean())
+    r = solver.solve(problem(ms), FBAR, TIGHT)
+    ref = exact_laminate(FBAR, phi, np.eye(3)[0], MATS)
+    assert np.abs(r["Pbar"] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def _sphere8():
+    return synth.single_sphere((8, 8, 8), radius=0.3, center=(0.05, -0.02, 0.03))
+
+
+def test_hill_mandel_mean_and_equilibrium():
+    ms = _sphere8()
+    r = solver.solve(problem(ms), FBAR, TIGHT)
+    F, P = r["F"], r["P"]
+    assert np.abs(F.mean(axis=(2, 3, 4)) - FBAR).max() <= 1e-14
+    hm = np.sum(P * F) / ms.nvox
+    assert hm == pytest.approx(np.sum(r["Pbar"] * FBAR), rel=1e-11)
+    assert r["stats"]["eta"][-1] <= 1e-12
+
+
+def test_frame_invariance_of_effective_stress():
+    rng = np.random.default_rng(3)
+    ms = _sphere8()
+    r = solver.solve(problem(ms), FBAR, TIGHT)
+    Q = rotation(rng)
+    rq = solver.solve(problem(ms), Q @ FBAR, TIGHT)
+    assert np.abs(rq["Pbar"] - Q @ r["Pbar"]).max() <= 1e-11 * np.abs(r["Pbar"]).max()
+
+
+def test_centred_sphere_mirror_symmetry():
+    ms, lc = synth.workload_single_sphere_16()
+    r = solver.solve(problem(ms, lc.mats), lc.Fbar, solver.Options(tol_newton=1e-10, tol_cg=1e-12))
+    Pb = r["Pbar"]
+    off = [Pb[0, 1], Pb[1, 0], Pb[0, 2], Pb[2, 0], Pb[1, 2], Pb[2, 1]]
+    assert np.abs(off).max() <= 1e-12 * abs(Pb[0, 0])
+    assert Pb[1, 1] == pytest.approx(Pb[2, 2], rel=1e-10)
+
+
+def test_load_path_independence():
+    ms = _sphere8()
+    r1 = solver.solve(problem(ms), FBAR, TIGHT)
+    o3 = solver.Options(tol_newton=1e-12, tol_cg=1e-12, n_increments=3)
+    r3 = solver.solve(problem(ms), FBAR, o3)
+    assert r3["stats"]["increments"] == 3
+    assert np.abs(r1["Pbar"] - r3["Pbar"]).max() <= 1e-11 * np.abs(r1["Pbar"]).max()
+
+
+def test_effective_tangent_matches_finite_differences_and_is_symmetric():
+    ms = synth.single_sphere((6, 6, 6), radius=0.3)
+    opts = solver.Options(tol_newton=1e-13, tol_cg=1e-13, want_tangent=True)
+    r = solver.solve(problem(ms), FBAR, opts)
+    A = r["Abar"]
+    h = 1e-5
+    Afd = np.zeros((9, 9))
+    o = solver.Options(tol_newton=1e-13, tol_cg=1e-13)
+    for kL in range(9):
+        E = np.zeros((3, 3))
+        E[kL // 3, kL % 3] = h
+        Pp = solver.solve(problem(ms), FBAR + E, o)["Pbar"]
+        Pm = solver.solve(problem(ms), FBAR - E, o)["Pbar"]
+        Afd[:, kL] = ((Pp - Pm) / (2 * h)).reshape(9)
+    assert np.abs(A - Afd).max() <= 1e-6 * np.abs(A).max()
+    assert np.abs(A - A.T).max() <= 1e-10 * np.abs(A).max()
+
+
+def _mandel(C9):
+    """Restrict a 9x9 tangent with minor symmetries to the 6x6 Mandel form."""
+    idx = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    w = [1, 1, 1, np.sqrt(2), np.sqrt(2), np.sqrt(2)]
+    C = C9.reshape(3, 3, 3, 3)
+    return np.array([[w[a] * w[b] * C[idx[a] + idx[b]] for b in range(6)] for a in range(6)])
+
+
+def test_effective_tangent_at_identity_within_voigt_reuss():
+    ms = _sphere8()
+    opts = solver.Options(tol_newton=1e-12, tol_cg=1e-13, want_tangent=True)
+    r = solver.solve(problem(ms), np.eye(3), opts)
+    A6 = _mandel(r["Abar"])
+    phi = float(ms.c.mean())
+    Cm = _mandel(material.isotropic_stiffness(*MATS[0]))
+    Cp = _mandel(material.isotropic_stiffness(*MATS[1]))
+    CV = phi * Cp + (1 - phi) * Cm
+    CR = np.linalg.inv(phi * np.linalg.inv(Cp) + (1 - phi) * np.linalg.inv(Cm))
+    ev_v = np.linalg.eigvalsh(CV - A6)
+    ev_r = np.linalg.eigvalsh(A6 - CR)
+    assert ev_v.min() > 0 and ev_r.min() > 0
+
+
+def test_failure_injection():
+    ms = _sphere8()
+    with pytest.raises(solver.SolveError) as e:
+        solver.solve(problem(ms), np.diag([1.0, 1.0, -1.0]))
+    assert e.value.status == solver.E_INADMISSIBLE
+    with pytest.raises(solver.SolveError) as e:
+        solver.solve(problem(ms), FBAR, solver.Options(max_cg=1))
+    assert e.value.status == solver.E_NOCONV
