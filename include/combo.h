@@ -1,0 +1,191 @@
+/*
+ * combo.h -- C-ABI of libcombo: FFT-based finite-strain homogenization with
+ * composite boxels (ComBo) on one AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the periodic homogenization problem of the paper
+ * (Keshav, Fritzen, Kabel: "FFT-based homogenization at finite strains using
+ * composite boxels", Sec. 2 eqs. Pbar, hom:start, equilibrium): given the
+ * macroscopic deformation gradient Fbar, find the deformation gradient field
+ * F = Fbar + Grad(periodic fluctuation) with Div P(F) = 0, where P is the
+ * compressible Neo-Hookean law (Sec. 6.1) in pure voxels and the rank-one
+ * laminate law of Sec. 4 (Alg. 1 Newton-Raphson for the jump vector with the
+ * selective back-projection of Alg. 2, stress eq. Peff:Seff and the
+ * consistent tangent that follows it) in composite voxels.  The equation
+ * solved is the Lippmann-Schwinger equation (Sec. 3, eq. nonlinearLSE) by
+ * Newton's method with a conjugate-gradient linear solver on the spectral
+ * (Moulinec-Suquet) discretization.
+ *
+ * Conventions
+ *   - Tensors are 3x3, stored row-major: component (i, J) at index 3*i + J
+ *     (paper Sec. 1.5).  4th-order tangents are 9x9 row-major (row 3i+J,
+ *     column 3k+L).
+ *   - Grids are n1 x n2 x n3 voxels of a box l1 x l2 x l3 (boxels allowed);
+ *     fields are structure-of-arrays [9][n3][n2][n1] (x fastest); scalar
+ *     fields [n3][n2][n1]; normals [3][n3][n2][n1].
+ *   - phase: 0 = matrix ("-"), 1 = inclusion ("+"), 2 = composite boxel.
+ *     c = inclusion volume fraction c+ of a composite boxel, 0 < c < 1.
+ *     N = unit interface normal pointing out of the inclusion (Sec. 2, 5.1).
+ *     c and N are read only where phase == 2.
+ *   - Materials: index 0 = matrix, 1 = inclusion, each (mu, lambda).
+ *   - Every grid axis must be 1 or a product of 2s and 3s, at most 768
+ *     (COMBO_E_SIZE otherwise).
+ *
+ * Ownership: the caller owns every pointer it passes.  set_* calls copy their
+ * inputs; no caller pointer is kept after a call returns.  Output buffers are
+ * written in place.  mem_kind tells whether caller pointers are host memory
+ * (COMBO_MEM_HOST) or device memory of the context's GPU (COMBO_MEM_DEVICE).
+ * The context owns all device memory it allocates; combo_destroy frees it.
+ *
+ * Errors: every call returns a status (COMBO_OK or a negative COMBO_E_*); no
+ * exception crosses the ABI.  combo_last_error() gives a message.  Inputs are
+ * validated on the host before any GPU work.  After a failed solve the output
+ * buffers are unspecified, but stats (if given) is filled.
+ *
+ * Streams and threads: all GPU work of a context runs on its stream; calls
+ * block until their results are ready.  A context is not thread-safe;
+ * different contexts may be used from different threads.
+ */
+#ifndef COMBO_H
+#define COMBO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COMBO_ABI_VERSION 1
+
+typedef struct combo_ctx combo_ctx;
+typedef struct combo_batch combo_batch;
+
+enum combo_status {
+    COMBO_OK = 0,
+    COMBO_E_INVAL = -1,        /* invalid argument (null pointer, bad value) */
+    COMBO_E_NOMEM = -2,        /* device or host allocation failed */
+    COMBO_E_HIP = -3,          /* HIP runtime error / no usable GPU */
+    COMBO_E_SIZE = -4,         /* grid size not supported */
+    COMBO_E_NOCONV = -5,       /* Newton, CG or laminate did not converge */
+    COMBO_E_INADMISSIBLE = -6, /* det F <= 0 (macroscopic or unrecoverable local) */
+    COMBO_E_NUMERIC = -7,      /* NaN/Inf input or CG breakdown */
+    COMBO_E_STATE = -8         /* call out of order (e.g. solve before set_grid) */
+};
+
+enum combo_mem { COMBO_MEM_HOST = 0, COMBO_MEM_DEVICE = 1 };
+
+/* Precision of the conjugate-gradient linear solves (FFT, Green operator,
+ * tangent action, CG vectors).  The material law, the laminate Newton, the
+ * deformation and stress fields and the Newton residual are always FP64. */
+enum combo_precision { COMBO_FP64 = 0, COMBO_MIXED = 1 };
+
+enum combo_green { COMBO_GREEN_GAMMA0 = 0, COMBO_GREEN_G = 1 };
+
+typedef struct {
+    double mu;
+    double lambda;
+} combo_material;
+
+typedef struct {
+    int precision;            /* COMBO_FP64 or COMBO_MIXED */
+    double tol_newton;        /* eta = |G[P]|_2 / (sqrt(n) |Pbar|_F) <= tol_newton */
+    double tol_cg;            /* |r|_C0 / |b|_C0 <= tol_cg (mixed mode: at least 1e-5) */
+    int max_newton;           /* Newton iterations per increment */
+    int max_cg;               /* CG iterations per linear solve */
+    int max_laminate;         /* laminate Newton updates per voxel (<= 64) */
+    int n_increments;         /* load increments from <F_init> (or I) to Fbar */
+    double mu0, kappa0;       /* reference medium C0 = mu0 Id + kappa0 I(x)I; <= 0: default */
+    int warm_start_laminate;  /* start each laminate solve from the last accepted a */
+    int want_tangent;         /* compute the effective tangent Abar */
+    int max_step_halvings;    /* Newton step control */
+    int max_cutbacks;         /* increment halvings */
+    int graph_chunk;          /* CG iterations per captured HIP graph replay; 0 = plain launches */
+} combo_options;
+
+typedef struct {
+    int status;
+    int newton_iters;
+    int cg_iters_total;       /* Newton solves only */
+    int cg_iters_tangent;     /* effective-tangent solves */
+    int increments_done;
+    int step_halvings;
+    int cutbacks;
+    int laminate_iters_max;
+    long long laminate_iters_total;
+    long long laminate_backprojections;
+    long long laminate_failures;
+    double eta_final;
+    double time_ms_total;
+    double time_ms_cg;
+    double time_ms_material;
+    double time_ms_residual;
+    double time_ms_tangent;
+} combo_stats;
+
+/* Library identification and messages ------------------------------------ */
+int combo_abi_version(void);
+const char* combo_strerror(int status);
+/* Fill opt with the defaults: FP64, tol_newton 1e-8, tol_cg 1e-10, max_newton 30,
+ * max_cg 5000, max_laminate 50, 1 increment, default C0, warm start on,
+ * no tangent, 10 step halvings, 5 cutbacks, graph_chunk 0. */
+void combo_default_options(combo_options* opt);
+
+/* Host-only validation of a microstructure (no GPU needed).  Checks phase ids,
+ * 0 < c < 1 and |N| = 1 (within 1e-6) where phase == 2, finite values.
+ * Host pointers only.  Returns COMBO_OK or COMBO_E_INVAL; msg (may be NULL,
+ * msg_len bytes) receives a description of the first problem. */
+int combo_validate_microstructure(int n1, int n2, int n3, const uint8_t* phase, const double* c,
+                                  const double* N, char* msg, int msg_len);
+/* Returns COMBO_OK if n is 1 or a product of 2s and 3s not above 768. */
+int combo_check_size(int n);
+
+/* Context ------------------------------------------------------------------ */
+/* Create a context on GPU `device` using `hip_stream` (a hipStream_t; NULL =
+ * a stream the context creates and owns).  COMBO_E_HIP if no usable GPU. */
+int combo_create(combo_ctx** out, int device, void* hip_stream);
+int combo_destroy(combo_ctx* ctx);
+/* Message of the last failed call on ctx; owned by ctx, valid until the next call. */
+const char* combo_last_error(const combo_ctx* ctx);
+
+/* Grid and box (paper Sec. 2: the RVE [-l1/2, l1/2] x ...).  Resets the microstructure. */
+int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2, double l3);
+/* Materials (mu, lambda) for phase 0 (matrix) and 1 (inclusion); mu > 0, lambda >= 0. */
+int combo_set_materials(combo_ctx* ctx, const combo_material mats[2]);
+/* Per-voxel ComBo data (paper Sec. 4: volume fraction and laminate normal).
+ * phase [n], c [n], N [3][n] in the layout above; mem_kind as documented. */
+int combo_set_microstructure(combo_ctx* ctx, const uint8_t* phase, const double* c, const double* N,
+                             int mem_kind);
+int combo_set_options(combo_ctx* ctx, const combo_options* opt);
+
+/* Solve HOM for the macroscopic deformation gradient Fbar (host, 9 doubles,
+ * det > 0).  Starts from F_init ([9][n], or NULL for F = I) and follows
+ * n_increments load steps to Fbar.  Outputs (each may be NULL): F_out and
+ * P_out [9][n] in mem_kind memory; Pbar (host, 9) = <P> (eq. Pbar); Abar
+ * (host, 81) = dPbar/dFbar when opt.want_tangent; Pbar_phase (host, 18) =
+ * volume averages of P over the inclusion (first 9) and matrix (last 9),
+ * counting c+ P+ and c- P- inside composite voxels; stats (host). */
+int combo_solve(combo_ctx* ctx, const double Fbar[9], const double* F_init, double* F_out, double* P_out,
+                double Pbar[9], double Abar[81], double Pbar_phase[18], combo_stats* stats, int mem_kind);
+
+/* Diagnostics used by the test-suite ------------------------------------- */
+/* Evaluate the pointwise law (Sec. 6.1 in pure voxels, Sec. 4 Alg. 1 + 2 in
+ * composite voxels, cold start a = 0) at the field F [9][n].  Writes P [9][n]
+ * (may be NULL), the tangent dP/dF A [81][n] (may be NULL; FP64), the jump
+ * vector a [3][n] (may be NULL; 0 in pure voxels) and laminate updates
+ * iters [n] (may be NULL; int32, 0 in pure voxels).  Also leaves the tangent
+ * state of the current precision in the context for combo_apply_operator.
+ * Returns COMBO_E_INADMISSIBLE if any voxel has det F <= 0 or a laminate
+ * fails (outputs still written). */
+int combo_eval_law(combo_ctx* ctx, const double* F, double* P, double* A, double* a, int* iters, int mem_kind);
+/* out = Gamma0[tau] (which = COMBO_GREEN_GAMMA0, reference medium of the
+ * options) or G[tau] (COMBO_GREEN_G) for a real field tau [9][n] (Sec. 3,
+ * eq. Gamma0; zero mean and Nyquist modes), computed in `precision`. */
+int combo_apply_green(combo_ctx* ctx, int which, int precision, const double* tau, double* out, int mem_kind);
+/* q = Gamma0[A : p] with the tangent state of the last combo_eval_law, for a
+ * compatible zero-mean field p [9][n]; the linear operator of each Newton step. */
+int combo_apply_operator(combo_ctx* ctx, int precision, const double* p, double* q, int mem_kind);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COMBO_H */

@@ -1,0 +1,58 @@
+// Shared device/host definitions of the ComBo HIP path (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+namespace combo {
+
+constexpr int kBlock = 256;          // threads per workgroup of the FFT passes
+// complex elements held in LDS by one FFT workgroup (32 KiB of data either way)
+template <typename T> __host__ __device__ constexpr int max_elems() { return sizeof(T) == 4 ? 4096 : 2048; }
+constexpr int kMaxAxis = 768;        // largest supported grid axis
+constexpr int kMaxPasses = 8;
+
+template <typename T> struct cpx_t;
+template <> struct cpx_t<float> { using type = float2; };
+template <> struct cpx_t<double> { using type = double2; };
+template <typename T> using cpx = typename cpx_t<T>::type;
+
+template <typename T> __host__ __device__ inline cpx<T> mk(T x, T y) { cpx<T> r; r.x = x; r.y = y; return r; }
+template <typename C> __host__ __device__ inline C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename C> __host__ __device__ inline C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename C> __host__ __device__ inline C cmul(C a, C b) {
+    C r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+template <typename C> __host__ __device__ inline C cconj(C a) { C r; r.x = a.x; r.y = -a.y; return r; }
+template <typename C, typename T> __host__ __device__ inline C cscale(C a, T s) { C r; r.x = a.x * s; r.y = a.y * s; return r; }
+// multiply by +i (s = +1) or -i (s = -1)
+template <int S, typename C> __host__ __device__ inline C cmul_i(C a) {
+    C r;
+    if (S > 0) { r.x = -a.y; r.y = a.x; } else { r.x = a.y; r.y = -a.x; }
+    return r;
+}
+
+// Radix plan of one axis: L = prod(radix[0..npass)).  Twiddles W_L^m = exp(-2 pi i m / L)
+// are read from a table of L entries (forward); the inverse uses their conjugates.
+struct AxisPlan {
+    int L;
+    int npass;
+    int radix[kMaxPasses];
+};
+
+// Geometry of one RVE as the kernels see it.
+struct Grid {
+    int n1, n2, n3;       // voxels per axis
+    int nh;               // stored x frequencies: n1/2 (even n1, Nyquist dropped) or (n1+1)/2
+    long long n;          // n1*n2*n3
+    long long nspec;      // nh*n2*n3 (complex values per spectral component)
+    double xs1, xs2, xs3; // 2 pi / l_d: xi_d(k) = xs_d * k
+};
+
+__host__ __device__ inline int freq_of(int j, int n) { return (j < (n + 1) / 2) ? j : j - n; }
+// true if index j is the Nyquist index of an even axis of length n
+__host__ __device__ inline bool is_nyquist(int j, int n) { return (n % 2 == 0) && (j == n / 2) && n > 1; }
+
+}  // namespace combo

@@ -1,0 +1,99 @@
+// Internal state of a libcombo context (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "combo.h"
+#include "common.h"
+#include "kernels.h"
+#include "material.h"
+
+namespace combo {
+
+// Owning device allocation that only grows.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t nbytes) {
+        if (nbytes <= bytes && p) return hipSuccess;
+        release();
+        if (nbytes == 0) nbytes = 16;
+        hipError_t e = hipMalloc(&p, nbytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        bytes = nbytes;
+        return hipSuccess;
+    }
+    template <typename X> X* as() const { return static_cast<X*>(p); }
+};
+
+// Host-visible scalars copied back once per material / residual evaluation.
+struct HostScalars {
+    CGState cg;
+    double sums[kSumsLen];
+};
+
+// Captured CG iteration chunk (one per precision).
+struct CGGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int iters = 0;
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        iters = 0;
+    }
+};
+
+}  // namespace combo
+
+struct combo_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    size_t lds_limit = 65536;
+
+    // grid
+    bool has_grid = false;
+    combo::Grid g{};
+    double l[3] = {1, 1, 1};
+    combo::AxisPlan plan[3]{};
+    combo::DevBuf tw32[3], tw64[3];
+
+    // materials and options
+    bool has_mats = false;
+    combo_material mats[2]{};
+    combo_options opt{};
+
+    // microstructure
+    bool has_ms = false;
+    int nc = 0;
+    double n_mat = 0, n_incl = 0, sum_c = 0;
+    combo::DevBuf slot, comp_vox, comp_c, comp_N, a_prev, a_trial;
+
+    // fields (FP64) and work buffers
+    combo::DevBuf F_cur, F_trial, F_save, dF, P;
+    combo::DevBuf specA, specB;           // spectra, sized for FP64
+    combo::DevBuf ux, ur, up, uq;         // CG vectors, sized for FP64
+    combo::DevBuf Sinv, sm, Acomp;        // tangent state, sized for FP64
+    int state_prec = -1;                  // precision the tangent state was written in
+    combo::DevBuf part1, part2, sums, cgst;
+    combo::HostScalars* hs = nullptr;     // pinned host copy of the device scalars
+    combo::CGGraph graph[2];
+};

@@ -1,0 +1,817 @@
+// FFT passes of the Lippmann-Schwinger operator on gfx950.
+//
+// A compatible field F = Fbar + Grad u is represented by the displacement
+// coefficients u_hat (3 complex numbers per frequency): FFT(F - Fbar) = u_hat (x) xi
+// (unnormalised FFT, xi_d = 2 pi k_d / l_d).  The Green operator of the paper
+// (Sec. 3, eq. Gamma0) is then  Gamma0_hat tau_hat = (K^{-1} tau_hat xi) (x) xi  with the
+// acoustic tensor K = mu0 |xi|^2 I + kappa0 xi (x) xi of the reference medium, so
+// only the three components of tau_hat xi are ever needed.  The three grid axes
+// are transformed in separate passes and the xi_J factors are applied axis by
+// axis, which shrinks the spectral data between passes:
+//
+//   forward  x: 9 real comps -> R2C, comps (i,1) times xi_1           9 complex
+//            y: FFT, a_i = (xi_1 tau_i1)^ + xi_2 tau_i2^               9 -> 6
+//            z: FFT, v_i = a_i + xi_3 tau_i3^, then K^{-1} v          6 -> 3
+//   inverse  z: u_i and xi_3 u_i, IFFT                                3 -> 6
+//            y: IFFT of u_i, xi_2 u_i, xi_3 u_i                       6 -> 9
+//            x: comps (i,1) times xi_1, C2R                           9 real comps
+//
+// In the CG operator the x inverse pass, the tangent action and the x forward
+// pass are one kernel, so the real-space field never reaches HBM.  Frequencies
+// on a Nyquist plane of an even axis and the zero frequency are projected out;
+// the x Nyquist bin is not stored at all (half spectrum of n1/2 values).
+//
+// Real transforms along x pack two real components into one complex FFT:
+// z = a + i b, A_k = (Z_k + conj Z_{n-k})/2, B_k = (Z_k - conj Z_{n-k})/(2i).
+#include "fft_lds.h"
+#include "kernels.h"
+
+namespace combo {
+
+// ------------------------------------------------------------------------------
+// block reduction of one double per thread; result valid in thread 0
+// ------------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) r += sh[w];
+    }
+    return r;
+}
+
+// ------------------------------------------------------------------------------
+// tangent action tau = A : p
+// ------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void tangent_apply(const TangentState<T>& ts, long long vox, const T* p, T* tau) {
+    const int slot = ts.slot[vox];
+    if (slot >= 0) {
+        const T* A = ts.Acomp + (long long)slot * 45;
+        T a[45];
+#pragma unroll
+        for (int i = 0; i < 45; ++i) a[i] = A[i];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            T acc = T(0);
+#pragma unroll
+            for (int s = 0; s < 9; ++s) {
+                const int lo = r < s ? r : s, hi = r < s ? s : r;
+                acc += a[lo * 9 - (lo * (lo - 1)) / 2 + (hi - lo)] * p[s];
+            }
+            tau[r] = acc;
+        }
+        return;
+    }
+    const int ph = (slot == -1) ? 0 : 1;
+    const T mu = ts.mu[ph], lam = ts.lam[ph];
+    T fi[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) fi[c] = ts.Sinv[c * ts.n + vox];
+    const T m = ts.sm[vox];
+    // B = F^{-1} p, C = B F^{-1};  tau_iJ = mu p_iJ + lam tr(B) Finv_Ji + m C_Ji
+    T B[9];
+#pragma unroll
+    for (int J = 0; J < 3; ++J)
+#pragma unroll
+        for (int L = 0; L < 3; ++L) B[3 * J + L] = fi[3 * J + 0] * p[0 + L] + fi[3 * J + 1] * p[3 + L] + fi[3 * J + 2] * p[6 + L];
+    const T tr = B[0] + B[4] + B[8];
+    T C[9];
+#pragma unroll
+    for (int J = 0; J < 3; ++J)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) C[3 * J + i] = B[3 * J + 0] * fi[0 + i] + B[3 * J + 1] * fi[3 + i] + B[3 * J + 2] * fi[6 + i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) tau[3 * i + J] = mu * p[3 * i + J] + lam * tr * fi[3 * J + i] + m * C[3 * J + i];
+}
+
+// ------------------------------------------------------------------------------
+// x pass
+// ------------------------------------------------------------------------------
+// Sequences s = 0..4 pack components (2s, 2s+1), the last one component 8 alone.
+__device__ __forceinline__ bool xi1_comp(int c) { return c == 0 || c == 3 || c == 6; }
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_xpass(XArgs<T> a) {
+    using C = cpx<T>;
+    if (MODE == X_CG && a.st->done) return;
+    extern __shared__ char smem_raw[];
+    const int L = a.g.n1, nh = a.g.nh, R = a.R;
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    C* buf = tw + L;                   // [5R][L], column-major (each sequence contiguous)
+    __shared__ double red[16];
+    const long long nrows = (long long)a.g.n2 * a.g.n3;
+    const long long row0 = (long long)blockIdx.x * R;
+    const int tid = threadIdx.x;
+    const T xs1 = T(a.g.xs1);
+    load_twiddles<T>(tw, a.tw, L);
+
+    constexpr bool HAS_INV = (MODE == X_CG || MODE == X_AVG || MODE == X_INV_REAL);
+    constexpr bool HAS_FWD = (MODE == X_CG || MODE == X_RHS_E || MODE == X_FWD_REAL);
+
+    if (HAS_INV) {
+        // unpack half spectra into full-length sequences
+        const int items = 5 * R * nh;
+        for (int it = tid; it < items; it += kBlock) {
+            const int k = it % nh;
+            const int sr = it / nh;
+            const int rr = sr % R, s = sr / R;
+            const long long row = row0 + rr;
+            C ha = mk<T>(0, 0), hb = mk<T>(0, 0);
+            if (row < nrows) {
+                const long long off = row * nh + k;
+                const int ca = 2 * s, cb = 2 * s + 1;
+                ha = a.in[ca * a.g.nspec + off];
+                if (s < 4) hb = a.in[cb * a.g.nspec + off];
+                const T x1 = xs1 * T(k);
+                if (xi1_comp(ca)) ha = cscale(ha, x1);
+                if (s < 4 && xi1_comp(cb)) hb = cscale(hb, x1);
+            }
+            C* col = buf + (s * R + rr) * L;
+            if (k == 0) {
+                col[0] = mk<T>(ha.x, hb.x);
+            } else {
+                col[k] = mk<T>(ha.x - hb.y, ha.y + hb.x);
+                col[L - k] = mk<T>(ha.x + hb.y, hb.x - ha.y);
+            }
+            if ((L % 2 == 0) && k == nh - 1 && L > 1) col[L / 2] = mk<T>(0, 0);
+        }
+        __syncthreads();
+        fft_lds<+1, true, T>(buf, a.plan, 5 * R, tw);
+    }
+
+    // pointwise stage
+    double acc[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+    {
+        const int items = R * L;
+        for (int it = tid; it < items; it += kBlock) {
+            const int x = it % L, rr = it / L;
+            const long long row = row0 + rr;
+            if (row >= nrows) {
+                if (HAS_FWD) {
+#pragma unroll
+                    for (int s = 0; s < 5; ++s) buf[(s * R + rr) * L + x] = mk<T>(0, 0);
+                }
+                continue;
+            }
+            const long long vox = row * L + x;
+            T p[9];
+            if (MODE == X_RHS_E) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) p[c] = T(a.E[c]);
+            } else if (MODE == X_FWD_REAL) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) p[c] = T(a.real_in[c * a.g.n + vox]);
+            } else {
+#pragma unroll
+                for (int s = 0; s < 5; ++s) {
+                    const C z = buf[(s * R + rr) * L + x];
+                    p[2 * s] = z.x;
+                    if (s < 4) p[2 * s + 1] = z.y;
+                }
+            }
+            if (MODE == X_INV_REAL) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) a.real_out[c * a.g.n + vox] = double(p[c]) * a.scale;
+                continue;
+            }
+            if (MODE == X_AVG) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) p[c] = T(double(p[c]) * a.scale + a.E[c]);
+            }
+            T tau[9];
+            if (MODE == X_FWD_REAL) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) tau[c] = p[c];
+            } else {
+                tangent_apply<T>(a.ts, vox, p, tau);
+            }
+            if (MODE == X_AVG) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) acc[c] += double(tau[c]);
+                continue;
+            }
+#pragma unroll
+            for (int s = 0; s < 5; ++s) buf[(s * R + rr) * L + x] = mk<T>(tau[2 * s], s < 4 ? tau[2 * s + 1] : T(0));
+        }
+    }
+    if (MODE == X_AVG) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const double t = block_sum(acc[c], red);
+            if (tid == 0) a.partials[(long long)blockIdx.x * 9 + c] = t;
+        }
+        return;
+    }
+    if (!HAS_FWD) return;
+    __syncthreads();
+    fft_lds<-1, true, T>(buf, a.plan, 5 * R, tw);
+    // pack: half spectra of both real components of every sequence
+    const int items = 5 * R * nh;
+    for (int it = tid; it < items; it += kBlock) {
+        const int k = it % nh;
+        const int sr = it / nh;
+        const int rr = sr % R, s = sr / R;
+        const long long row = row0 + rr;
+        if (row >= nrows) continue;
+        const C* col = buf + (s * R + rr) * L;
+        const C zk = col[k];
+        const C zm = col[(L - k) % L];
+        C ha = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+        C hb = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
+        const long long off = row * nh + k;
+        const int ca = 2 * s, cb = 2 * s + 1;
+        const T x1 = xs1 * T(k);
+        if (xi1_comp(ca)) ha = cscale(ha, x1);
+        if (xi1_comp(cb)) hb = cscale(hb, x1);
+        a.out[ca * a.g.nspec + off] = ha;
+        if (s < 4) a.out[cb * a.g.nspec + off] = hb;
+    }
+}
+
+// ------------------------------------------------------------------------------
+// y passes: tile = TX consecutive x frequencies of one z plane, all y
+// ------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void y_load(const YArgs<T>& a, cpx<T>* buf, int comp, int z, int kx0, int TX) {
+    const int n2 = a.g.n2, nh = a.g.nh;
+    const int items = n2 * TX;
+    for (int e = threadIdx.x; e < items; e += kBlock) {
+        const int y = e / TX, t = e - y * TX;
+        const int kx = kx0 + t;
+        buf[e] = (kx < nh) ? a.in[comp * a.g.nspec + ((long long)z * n2 + y) * nh + kx] : mk<T>(0, 0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void y_store(const YArgs<T>& a, const cpx<T>* buf, int comp, int z, int kx0, int TX) {
+    const int n2 = a.g.n2, nh = a.g.nh;
+    const int items = n2 * TX;
+    for (int e = threadIdx.x; e < items; e += kBlock) {
+        const int y = e / TX, t = e - y * TX;
+        const int kx = kx0 + t;
+        if (kx < nh) a.out[comp * a.g.nspec + ((long long)z * n2 + y) * nh + kx] = buf[e];
+    }
+}
+
+// forward: in 9 comps (row-major (i,J), comps (i,1) already times xi_1) -> out 6:
+// out_i = FFT(in_i1) + xi_2 FFT(in_i2), out_{3+i} = FFT(in_i3)   (1-based J in the comments)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ypass_fwd(YArgs<T> a) {
+    using C = cpx<T>;
+    if (a.st && a.st->done) return;
+    extern __shared__ char smem_raw[];
+    const int L = a.g.n2, TX = a.TX;
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    C* buf = tw + L;
+    const int z = blockIdx.x / a.ntile;
+    const int kx0 = (blockIdx.x % a.ntile) * TX;
+    load_twiddles<T>(tw, a.tw, L);
+    constexpr int Q = max_elems<T>() / kBlock;
+    C acc[Q];
+    const int items = L * TX;
+    const T xs2 = T(a.g.xs2);
+    for (int i = 0; i < 3; ++i) {
+        y_load(a, buf, 3 * i + 0, z, kx0, TX);
+        __syncthreads();
+        fft_lds<-1, false, T>(buf, a.plan, TX, tw);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            if (e < items) acc[q] = buf[e];
+        }
+        __syncthreads();
+        y_load(a, buf, 3 * i + 1, z, kx0, TX);
+        __syncthreads();
+        fft_lds<-1, false, T>(buf, a.plan, TX, tw);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            if (e < items) {
+                const int y = e / TX, t = e - y * TX;
+                const T x2 = xs2 * T(freq_of(y, L));
+                const C v = cadd(acc[q], cscale(buf[e], x2));
+                const int kx = kx0 + t;
+                if (kx < a.g.nh) a.out[i * a.g.nspec + ((long long)z * L + y) * a.g.nh + kx] = v;
+            }
+        }
+        __syncthreads();
+        y_load(a, buf, 3 * i + 2, z, kx0, TX);
+        __syncthreads();
+        fft_lds<-1, false, T>(buf, a.plan, TX, tw);
+        y_store(a, buf, 3 + i, z, kx0, TX);
+        __syncthreads();
+    }
+}
+
+// inverse: in 6 comps [A_i, B_i] -> out 9: (i,1) = IFFT(A_i), (i,2) = IFFT(xi_2 A_i), (i,3) = IFFT(B_i)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ypass_inv(YArgs<T> a) {
+    using C = cpx<T>;
+    if (a.st && a.st->done) return;
+    extern __shared__ char smem_raw[];
+    const int L = a.g.n2, TX = a.TX;
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    C* buf = tw + L;
+    const int z = blockIdx.x / a.ntile;
+    const int kx0 = (blockIdx.x % a.ntile) * TX;
+    load_twiddles<T>(tw, a.tw, L);
+    constexpr int Q = max_elems<T>() / kBlock;
+    C av[Q];
+    const int items = L * TX;
+    const T xs2 = T(a.g.xs2);
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            if (e < items) {
+                const int y = e / TX, t = e - y * TX;
+                const int kx = kx0 + t;
+                av[q] = (kx < a.g.nh) ? a.in[i * a.g.nspec + ((long long)z * L + y) * a.g.nh + kx] : mk<T>(0, 0);
+                buf[e] = av[q];
+            }
+        }
+        __syncthreads();
+        fft_lds<+1, false, T>(buf, a.plan, TX, tw);
+        y_store(a, buf, 3 * i + 0, z, kx0, TX);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            if (e < items) {
+                const int y = e / TX;
+                buf[e] = cscale(av[q], xs2 * T(freq_of(y, L)));
+            }
+        }
+        __syncthreads();
+        fft_lds<+1, false, T>(buf, a.plan, TX, tw);
+        y_store(a, buf, 3 * i + 1, z, kx0, TX);
+        __syncthreads();
+        y_load(a, buf, 3 + i, z, kx0, TX);
+        __syncthreads();
+        fft_lds<+1, false, T>(buf, a.plan, TX, tw);
+        y_store(a, buf, 3 * i + 2, z, kx0, TX);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------
+// z passes: tile = TX consecutive elements m of the (y, x) frequency plane, all z
+// ------------------------------------------------------------------------------
+struct Freq {
+    double x1, x2, x3, s;   // xi and |xi|^2
+    bool zero;              // zero mode or Nyquist plane: projected out
+    double w;               // Parseval weight of the half spectrum (1 or 2)
+};
+
+__device__ __forceinline__ Freq freq_at(const Grid& g, long long m, int z) {
+    Freq f;
+    const int ky = (int)(m / g.nh);
+    const int kx = (int)(m - (long long)ky * g.nh);
+    const int fy = freq_of(ky, g.n2), fz = freq_of(z, g.n3);
+    f.x1 = g.xs1 * kx;
+    f.x2 = g.xs2 * fy;
+    f.x3 = g.xs3 * fz;
+    f.s = f.x1 * f.x1 + f.x2 * f.x2 + f.x3 * f.x3;
+    f.zero = (kx == 0 && fy == 0 && fz == 0) || is_nyquist(ky, g.n2) || is_nyquist(z, g.n3);
+    f.w = (kx == 0) ? 1.0 : 2.0;
+    return f;
+}
+
+// w = K^{-1} v with K = mu0 |xi|^2 I + kappa0 xi (x) xi
+template <typename C, typename T>
+__device__ __forceinline__ void kinv(const Freq& f, T mu0, T kappa0, const C* v, C* w) {
+    const T x1 = T(f.x1), x2 = T(f.x2), x3 = T(f.x3), s = T(f.s);
+    const T theta = kappa0 / (mu0 + kappa0);
+    C xv;
+    xv.x = x1 * v[0].x + x2 * v[1].x + x3 * v[2].x;
+    xv.y = x1 * v[0].y + x2 * v[1].y + x3 * v[2].y;
+    const T inv = T(1) / (mu0 * s);
+    const T t = theta / s;
+    const T xx[3] = {x1, x2, x3};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        w[i].x = (v[i].x - t * xx[i] * xv.x) * inv;
+        w[i].y = (v[i].y - t * xx[i] * xv.y) * inv;
+    }
+}
+
+// K u for a CG vector u (used in the C0 inner products)
+template <typename C>
+__device__ __forceinline__ void kmul(const Freq& f, double mu0, double kappa0, const C* u, double* kr, double* ki) {
+    const double xu_r = f.x1 * double(u[0].x) + f.x2 * double(u[1].x) + f.x3 * double(u[2].x);
+    const double xu_i = f.x1 * double(u[0].y) + f.x2 * double(u[1].y) + f.x3 * double(u[2].y);
+    const double xx[3] = {f.x1, f.x2, f.x3};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        kr[i] = mu0 * f.s * double(u[i].x) + kappa0 * xx[i] * xu_r;
+        ki[i] = mu0 * f.s * double(u[i].y) + kappa0 * xx[i] * xu_i;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void z_load(const cpx<T>* in, const Grid& g, cpx<T>* buf, int comp, long long m0, int TX) {
+    const long long M = (long long)g.n2 * g.nh;
+    const int items = g.n3 * TX;
+    for (int e = threadIdx.x; e < items; e += kBlock) {
+        const int z = e / TX, t = e - z * TX;
+        const long long m = m0 + t;
+        buf[e] = (m < M) ? in[comp * g.nspec + (long long)z * M + m] : mk<T>(0, 0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void z_store(cpx<T>* out, const Grid& g, const cpx<T>* buf, int comp, long long m0, int TX) {
+    const long long M = (long long)g.n2 * g.nh;
+    const int items = g.n3 * TX;
+    for (int e = threadIdx.x; e < items; e += kBlock) {
+        const int z = e / TX, t = e - z * TX;
+        const long long m = m0 + t;
+        if (m < M) out[comp * g.nspec + (long long)z * M + m] = buf[e];
+    }
+}
+
+// forward z pass: v_i = FFT(in_i) + xi_3 FFT(in_{3+i}) and then, by mode,
+//   Z_CG:   q = K^{-1} v / n, partial sum of <p, q>_K = sum w Re(p^H v)/n
+//   Z_RHS:  r = b = -K^{-1} v, x = 0, partials of <b, b>_K and of |G P|^2 = |v|^2/|xi|^2
+//   Z_PROJ: x = K^{-1} v
+template <typename T, typename TU, int MODE>
+__global__ void __launch_bounds__(kBlock) k_zpass_fwd(ZArgs<T, TU> a) {
+    using C = cpx<T>;
+    using CU = cpx<TU>;
+    if (MODE == Z_CG && a.st->done) return;
+    extern __shared__ char smem_raw[];
+    __shared__ double red[16];
+    const int L = a.g.n3, TX = a.TX;
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    C* buf = tw + L;
+    const long long m0 = (long long)blockIdx.x * TX;
+    const long long M = (long long)a.g.n2 * a.g.nh;
+    load_twiddles<T>(tw, a.tw, L);
+    constexpr int Q = max_elems<T>() / kBlock;
+    C v[3][Q];
+    const int items = L * TX;
+    const T xs3 = T(a.g.xs3);
+    for (int i = 0; i < 3; ++i) {
+        z_load<T>(a.in, a.g, buf, i, m0, TX);
+        __syncthreads();
+        fft_lds<-1, false, T>(buf, a.plan, TX, tw);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            if (e < items) v[i][q] = buf[e];
+        }
+        __syncthreads();
+        z_load<T>(a.in, a.g, buf, 3 + i, m0, TX);
+        __syncthreads();
+        fft_lds<-1, false, T>(buf, a.plan, TX, tw);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            if (e < items) {
+                const int z = e / TX;
+                v[i][q] = cadd(v[i][q], cscale(buf[e], xs3 * T(freq_of(z, L))));
+            }
+        }
+        __syncthreads();
+    }
+    double s1 = 0.0, s2 = 0.0;
+    const T mu0 = T(a.mu0), kappa0 = T(a.kappa0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int e = threadIdx.x + q * kBlock;
+        if (e >= items) continue;
+        const int z = e / TX, t = e - z * TX;
+        const long long m = m0 + t;
+        if (m >= M) continue;
+        const Freq f = freq_at(a.g, m, z);
+        const long long idx = (long long)z * M + m;
+        C vv[3] = {v[0][q], v[1][q], v[2][q]};
+        C w[3];
+        if (f.zero) {
+            w[0] = w[1] = w[2] = mk<T>(0, 0);
+        } else {
+            kinv(f, mu0, kappa0, vv, w);
+        }
+        if (MODE == Z_CG) {
+            const T sc = T(a.inv_n);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                CU qi;
+                qi.x = TU(w[i].x * sc);
+                qi.y = TU(w[i].y * sc);
+                a.q[i * a.g.nspec + idx] = qi;
+                if (!f.zero) {
+                    const CU pi = a.p[i * a.g.nspec + idx];
+                    s1 += f.w * (double(pi.x) * double(vv[i].x) + double(pi.y) * double(vv[i].y)) * a.inv_n;
+                }
+            }
+        } else if (MODE == Z_RHS) {
+            CU b[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                b[i].x = TU(-w[i].x);
+                b[i].y = TU(-w[i].y);
+                a.r[i * a.g.nspec + idx] = b[i];
+                a.x[i * a.g.nspec + idx] = CU{TU(0), TU(0)};
+            }
+            if (!f.zero) {
+                double kr[3], ki[3];
+                kmul(f, a.mu0, a.kappa0, b, kr, ki);
+                double bb = 0.0, vv2 = 0.0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    bb += double(b[i].x) * kr[i] + double(b[i].y) * ki[i];
+                    vv2 += double(vv[i].x) * double(vv[i].x) + double(vv[i].y) * double(vv[i].y);
+                }
+                s1 += f.w * bb;
+                s2 += f.w * vv2 / f.s;
+            }
+        } else {  // Z_PROJ
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                CU o;
+                o.x = TU(w[i].x);
+                o.y = TU(w[i].y);
+                a.x[i * a.g.nspec + idx] = o;
+            }
+        }
+    }
+    if (MODE == Z_CG || MODE == Z_RHS) {
+        const double t1 = block_sum(s1, red);
+        if (threadIdx.x == 0) a.partials[blockIdx.x] = t1;
+    }
+    if (MODE == Z_RHS) {
+        const double t2 = block_sum(s2, red);
+        if (threadIdx.x == 0) a.partials2[blockIdx.x] = t2;
+    }
+}
+
+// inverse z pass: source vector u (Z_INV_CG: p = r + beta p first, p = r on the
+// first iteration; Z_INV_PLAIN: u = x), out_i = IFFT(u_i), out_{3+i} = IFFT(xi_3 u_i)
+template <typename T, typename TU, int MODE>
+__global__ void __launch_bounds__(kBlock) k_zpass_inv(ZArgs<T, TU> a) {
+    using C = cpx<T>;
+    using CU = cpx<TU>;
+    if (MODE == Z_INV_CG && a.st->done) return;
+    extern __shared__ char smem_raw[];
+    const int L = a.g.n3, TX = a.TX;
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    C* buf = tw + L;
+    const long long m0 = (long long)blockIdx.x * TX;
+    const long long M = (long long)a.g.n2 * a.g.nh;
+    load_twiddles<T>(tw, a.tw, L);
+    constexpr int Q = max_elems<T>() / kBlock;
+    const int items = L * TX;
+    const T xs3 = T(a.g.xs3);
+    double beta = 0.0;
+    bool first = true;
+    if (MODE == Z_INV_CG) {
+        beta = a.st->beta;
+        first = (a.st->iter == 0);
+    }
+    for (int i = 0; i < 3; ++i) {
+        C u[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            u[q] = mk<T>(0, 0);
+            if (e < items) {
+                const int z = e / TX, t = e - z * TX;
+                const long long m = m0 + t;
+                if (m < M) {
+                    const long long idx = i * a.g.nspec + (long long)z * M + m;
+                    if (MODE == Z_INV_CG) {
+                        const CU ri = a.r[idx];
+                        CU pn;
+                        if (first) {
+                            pn = ri;
+                        } else {
+                            const CU pi = a.p[idx];
+                            pn.x = TU(double(ri.x) + beta * double(pi.x));
+                            pn.y = TU(double(ri.y) + beta * double(pi.y));
+                        }
+                        a.p[idx] = pn;
+                        u[q] = mk<T>(T(pn.x), T(pn.y));
+                    } else {
+                        const CU xi = a.x[idx];
+                        u[q] = mk<T>(T(xi.x), T(xi.y));
+                    }
+                }
+                buf[e] = u[q];
+            }
+        }
+        __syncthreads();
+        fft_lds<+1, false, T>(buf, a.plan, TX, tw);
+        z_store<T>(a.out, a.g, buf, i, m0, TX);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            if (e < items) {
+                const int z = e / TX;
+                buf[e] = cscale(u[q], xs3 * T(freq_of(z, L)));
+            }
+        }
+        __syncthreads();
+        fft_lds<+1, false, T>(buf, a.plan, TX, tw);
+        z_store<T>(a.out, a.g, buf, 3 + i, m0, TX);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------
+// CG update: x += alpha p, r -= alpha q, partial <r, r>_K
+// ------------------------------------------------------------------------------
+template <typename TU>
+__global__ void __launch_bounds__(kBlock) k_cg_update(UArgs<TU> a) {
+    using CU = cpx<TU>;
+    if (a.st->done) return;
+    __shared__ double red[16];
+    const double alpha = a.st->alpha;
+    const long long M = (long long)a.g.n2 * a.g.nh;
+    double s = 0.0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < a.g.nspec;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(idx / M);
+        const long long m = idx - (long long)z * M;
+        CU rr[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const long long o = i * a.g.nspec + idx;
+            CU xi = a.x[o];
+            const CU pi = a.p[o];
+            CU ri = a.r[o];
+            const CU qi = a.q[o];
+            xi.x = TU(double(xi.x) + alpha * double(pi.x));
+            xi.y = TU(double(xi.y) + alpha * double(pi.y));
+            ri.x = TU(double(ri.x) - alpha * double(qi.x));
+            ri.y = TU(double(ri.y) - alpha * double(qi.y));
+            a.x[o] = xi;
+            a.r[o] = ri;
+            rr[i] = ri;
+        }
+        const Freq f = freq_at(a.g, m, z);
+        if (!f.zero) {
+            double kr[3], ki[3];
+            kmul(f, a.mu0, a.kappa0, rr, kr, ki);
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) t += double(rr[i].x) * kr[i] + double(rr[i].y) * ki[i];
+            s += f.w * t;
+        }
+    }
+    const double tot = block_sum(s, red);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
+}
+
+// ------------------------------------------------------------------------------
+// finalisers: one workgroup, fixed summation order (deterministic)
+// ------------------------------------------------------------------------------
+__device__ __forceinline__ double ordered_sum(const double* p, int count, double* sh) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) s += p[i];
+    return block_sum(s, sh);
+}
+
+__global__ void __launch_bounds__(kBlock) k_finalize(int mode, CGState* st, const double* partials,
+                                                     const double* partials2, int count, double tol2, int maxit) {
+    __shared__ double red[16];
+    if (mode != FIN_RHS && st->done) return;
+    const double s1 = ordered_sum(partials, count, red);
+    double s2 = 0.0;
+    if (mode == FIN_RHS) s2 = ordered_sum(partials2, count, red);
+    if (threadIdx.x != 0) return;
+    if (mode == FIN_RHS) {
+        st->rho0 = s1;
+        st->rho = s1;
+        st->tol2 = tol2;
+        st->maxit = maxit;
+        st->eta2 = s2;
+        st->iter = 0;
+        st->beta = 0.0;
+        st->alpha = 0.0;
+        st->status = 0;
+        st->done = (s1 > 0.0) ? 0 : 1;
+    } else if (mode == FIN_ALPHA) {
+        if (!(s1 > 0.0)) {
+            st->status = 1;
+            st->done = 1;
+        } else {
+            st->alpha = st->rho / s1;
+        }
+    } else {  // FIN_BETA
+        st->iter += 1;
+        if (!(s1 == s1)) {
+            st->status = 1;
+            st->done = 1;
+        } else if (s1 <= st->tol2 * st->rho0) {
+            st->done = 1;
+        } else if (st->iter >= st->maxit) {
+            st->status = 2;
+            st->done = 1;
+        }
+        st->beta = s1 / st->rho;
+        st->rho = s1;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_reduce_columns(const double* partials, int rows, int cols, double* out) {
+    __shared__ double red[16];
+    for (int c = 0; c < cols; ++c) {
+        double s = 0.0;
+        for (int r = threadIdx.x; r < rows; r += blockDim.x) s += partials[(long long)r * cols + c];
+        const double t = block_sum(s, red);
+        if (threadIdx.x == 0) out[c] = t;
+    }
+}
+
+// ------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------
+int blocks_x(const Grid& g, int R) { return (int)(((long long)g.n2 * g.n3 + R - 1) / R); }
+int blocks_y(const Grid& g, int TX) { return g.n3 * ((g.nh + TX - 1) / TX); }
+int blocks_z(const Grid& g, int TX) { return (int)(((long long)g.n2 * g.nh + TX - 1) / TX); }
+int blocks_u(const Grid& g) {
+    long long b = (g.nspec + kBlock - 1) / kBlock;
+    return (int)(b < 4096 ? b : 4096);
+}
+
+template <typename T>
+hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb) {
+    const int nblk = blocks_x(a.g, a.R);
+    if (nb) *nb = nblk;
+    const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n1 + (size_t)5 * a.R * a.g.n1);
+    switch (mode) {
+        case X_CG: hipLaunchKernelGGL((k_xpass<T, X_CG>), dim3(nblk), dim3(kBlock), lds, s, a); break;
+        case X_RHS_E: hipLaunchKernelGGL((k_xpass<T, X_RHS_E>), dim3(nblk), dim3(kBlock), lds, s, a); break;
+        case X_AVG: hipLaunchKernelGGL((k_xpass<T, X_AVG>), dim3(nblk), dim3(kBlock), lds, s, a); break;
+        case X_FWD_REAL: hipLaunchKernelGGL((k_xpass<T, X_FWD_REAL>), dim3(nblk), dim3(kBlock), lds, s, a); break;
+        default: hipLaunchKernelGGL((k_xpass<T, X_INV_REAL>), dim3(nblk), dim3(kBlock), lds, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_y(int dir, const YArgs<T>& a, hipStream_t s) {
+    const int nblk = a.g.n3 * a.ntile;
+    const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n2 + (size_t)a.g.n2 * a.TX);
+    if (dir < 0) hipLaunchKernelGGL(k_ypass_fwd<T>, dim3(nblk), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL(k_ypass_inv<T>, dim3(nblk), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, typename TU>
+hipError_t launch_z(int mode, const ZArgs<T, TU>& a, hipStream_t s, int* nb) {
+    const int nblk = blocks_z(a.g, a.TX);
+    if (nb) *nb = nblk;
+    const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n3 + (size_t)a.g.n3 * a.TX);
+    switch (mode) {
+        case Z_CG: hipLaunchKernelGGL((k_zpass_fwd<T, TU, Z_CG>), dim3(nblk), dim3(kBlock), lds, s, a); break;
+        case Z_RHS: hipLaunchKernelGGL((k_zpass_fwd<T, TU, Z_RHS>), dim3(nblk), dim3(kBlock), lds, s, a); break;
+        case Z_PROJ: hipLaunchKernelGGL((k_zpass_fwd<T, TU, Z_PROJ>), dim3(nblk), dim3(kBlock), lds, s, a); break;
+        case Z_INV_CG: hipLaunchKernelGGL((k_zpass_inv<T, TU, Z_INV_CG>), dim3(nblk), dim3(kBlock), lds, s, a); break;
+        default: hipLaunchKernelGGL((k_zpass_inv<T, TU, Z_INV_PLAIN>), dim3(nblk), dim3(kBlock), lds, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename TU>
+hipError_t launch_update(const UArgs<TU>& a, hipStream_t s, int* nb) {
+    const int nblk = blocks_u(a.g);
+    if (nb) *nb = nblk;
+    hipLaunchKernelGGL(k_cg_update<TU>, dim3(nblk), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(int mode, CGState* st, const double* partials, const double* partials2, int count,
+                           hipStream_t s, double tol2, int maxit) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, mode, st, partials, partials2, count, tol2, maxit);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_columns(const double* partials, int rows, int cols, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_columns, dim3(1), dim3(kBlock), 0, s, partials, rows, cols, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_x<float>(int, const XArgs<float>&, hipStream_t, int*);
+template hipError_t launch_x<double>(int, const XArgs<double>&, hipStream_t, int*);
+template hipError_t launch_y<float>(int, const YArgs<float>&, hipStream_t);
+template hipError_t launch_y<double>(int, const YArgs<double>&, hipStream_t);
+template hipError_t launch_z<float, float>(int, const ZArgs<float, float>&, hipStream_t, int*);
+template hipError_t launch_z<double, double>(int, const ZArgs<double, double>&, hipStream_t, int*);
+template hipError_t launch_z<double, float>(int, const ZArgs<double, float>&, hipStream_t, int*);
+template hipError_t launch_update<float>(const UArgs<float>&, hipStream_t, int*);
+template hipError_t launch_update<double>(const UArgs<double>&, hipStream_t, int*);
+
+}  // namespace combo

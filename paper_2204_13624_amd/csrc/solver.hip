@@ -1,0 +1,1104 @@
+// Host driver of the ComBo Lippmann-Schwinger Newton-CG solve and the C-ABI.
+//
+// Newton-Raphson on the Lippmann-Schwinger equation (paper Sec. 3, eq.
+// nonlinearLSE) at fixed macroscopic deformation: with F - Fbar compatible and
+// zero-mean, each Newton step solves  Gamma0[A : dF] = -Gamma0[P]  by conjugate
+// gradients in the C0 inner product.  On the GPU the unknown dF = Grad du is
+// carried by its displacement coefficients du_hat (see fft_kernels.hip); the
+// inner product <x, y>_C0 = sum mu0 x:y + kappa0 tr x tr y becomes
+// sum_xi u^H K(xi) v by Parseval, so the CG iterates are those of the
+// field formulation.
+//
+// Readings of the paper used here (where it is silent):
+//   - reference medium C0 = mu0 Id + kappa0 I(x)I, default mu0 = sqrt(mu_min mu_max),
+//     kappa0 = sqrt((lambda+mu)_min (lambda+mu)_max);
+//   - Newton test eta = |G[P]|_2 / (sqrt(n) |Pbar|_F) <= tol_newton;
+//   - CG test |r|_C0 <= tol_cg |b|_C0 (at least 1e-5 in mixed precision);
+//   - load path Fbar_k = Fbar_0 + (k/K)(Fbar - Fbar_0) with the homogeneous
+//     predictor F += Fbar_k - Fbar_{k-1};
+//   - step control: F + s dF, s halved while any voxel has det F <= 0 or a
+//     laminate fails; then the increment is halved;
+//   - Nyquist planes of even axes and the zero mode are projected out;
+//   - effective tangent column kL: solve Gamma0[A:dF] = -Gamma0[A:E_kL] and
+//     average A:(E_kL + dF).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "combo.h"
+#include "context.h"
+
+using namespace combo;
+
+namespace {
+
+int set_err(combo_ctx* ctx, int status, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return status;
+}
+
+#define HIP_OR_FAIL(...)                                                                                    \
+    do {                                                                                                    \
+        hipError_t e__ = (__VA_ARGS__);                                                                     \
+        if (e__ != hipSuccess)                                                                              \
+            return set_err(ctx, e__ == hipErrorOutOfMemory ? COMBO_E_NOMEM : COMBO_E_HIP,                   \
+                           std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e__));                      \
+    } while (0)
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0) { return std::chrono::duration<double, std::milli>(clk::now() - t0).count(); }
+
+bool size_ok(int n) {
+    if (n < 1 || n > 384) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+AxisPlan make_plan(int L) {
+    AxisPlan p{};
+    p.L = L;
+    p.npass = 0;
+    int m = L;
+    while (m % 16 == 0) { p.radix[p.npass++] = 16; m /= 16; }
+    while (m % 8 == 0) { p.radix[p.npass++] = 8; m /= 8; }
+    while (m % 4 == 0) { p.radix[p.npass++] = 4; m /= 4; }
+    while (m % 2 == 0) { p.radix[p.npass++] = 2; m /= 2; }
+    while (m % 3 == 0) { p.radix[p.npass++] = 3; m /= 3; }
+    return p;
+}
+
+template <typename T> const cpx<T>* twid(const combo_ctx* c, int axis) {
+    return sizeof(T) == 4 ? static_cast<const cpx<T>*>(c->tw32[axis].p) : static_cast<const cpx<T>*>(c->tw64[axis].p);
+}
+
+template <typename T> PassShape shape_for(const combo_ctx* c) {
+    const int maxE = max_elems<T>();
+    PassShape s;
+    s.xR = std::max(1, maxE / (5 * c->g.n1));
+    s.xR = (int)std::min<long long>(s.xR, (long long)c->g.n2 * c->g.n3);
+    s.yTX = std::max(1, std::min(c->g.nh, maxE / c->g.n2));
+    s.zTX = (int)std::max<long long>(1, std::min<long long>((long long)c->g.n2 * c->g.nh, maxE / c->g.n3));
+    return s;
+}
+
+void mean_field_host(const double* F, long long n, double out[9]) {
+    for (int c = 0; c < 9; ++c) {
+        long double s = 0;
+        for (long long v = 0; v < n; ++v) s += F[c * n + v];
+        out[c] = (double)(s / n);
+    }
+}
+
+__global__ void k_fill_identity(double* F, long long n) {
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x)
+        for (int c = 0; c < 9; ++c) F[c * n + v] = (c % 4 == 0) ? 1.0 : 0.0;
+}
+
+__global__ void k_colsum9(const double* F, long long n, double* partials) {
+    __shared__ double sh[4];
+    for (int c = 0; c < 9; ++c) {
+        double s = 0.0;
+        for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+             v += (long long)gridDim.x * blockDim.x)
+            s += F[c * n + v];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) partials[blockIdx.x * 9 + c] = sh[0] + sh[1] + sh[2] + sh[3];
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero_state(CGState* st) {
+    if (threadIdx.x == 0) {
+        st->rho = st->rho0 = st->alpha = st->beta = st->tol2 = st->eta2 = 0.0;
+        st->iter = st->maxit = st->done = st->status = 0;
+    }
+}
+
+double frob9(const double* a) {
+    double s = 0;
+    for (int i = 0; i < 9; ++i) s += a[i] * a[i];
+    return std::sqrt(s);
+}
+
+// ------------------------------------------------------------------------------
+// work buffers
+// ------------------------------------------------------------------------------
+int ensure_work(combo_ctx* ctx) {
+    const long long n = ctx->g.n, ns = ctx->g.nspec;
+    const size_t f9 = sizeof(double) * 9 * (size_t)n;
+    HIP_OR_FAIL(ctx->F_cur.ensure(f9));
+    HIP_OR_FAIL(ctx->F_trial.ensure(f9));
+    HIP_OR_FAIL(ctx->F_save.ensure(f9));
+    HIP_OR_FAIL(ctx->dF.ensure(f9));
+    HIP_OR_FAIL(ctx->P.ensure(f9));
+    HIP_OR_FAIL(ctx->specA.ensure(sizeof(double2) * 9 * (size_t)ns));
+    HIP_OR_FAIL(ctx->specB.ensure(sizeof(double2) * 9 * (size_t)ns));
+    const size_t u3 = sizeof(double2) * 3 * (size_t)ns;
+    HIP_OR_FAIL(ctx->ux.ensure(u3));
+    HIP_OR_FAIL(ctx->ur.ensure(u3));
+    HIP_OR_FAIL(ctx->up.ensure(u3));
+    HIP_OR_FAIL(ctx->uq.ensure(u3));
+    HIP_OR_FAIL(ctx->Sinv.ensure(sizeof(double) * 9 * (size_t)n));
+    HIP_OR_FAIL(ctx->sm.ensure(sizeof(double) * (size_t)n));
+    HIP_OR_FAIL(ctx->Acomp.ensure(sizeof(double) * 45 * (size_t)std::max(ctx->nc, 1)));
+    HIP_OR_FAIL(ctx->a_prev.ensure(sizeof(double) * 3 * (size_t)std::max(ctx->nc, 1)));
+    HIP_OR_FAIL(ctx->a_trial.ensure(sizeof(double) * 3 * (size_t)std::max(ctx->nc, 1)));
+    // partial sums: the largest consumer over all kernels
+    size_t np = 0;
+    for (int prec = 0; prec < 2; ++prec) {
+        PassShape s = prec ? shape_for<float>(ctx) : shape_for<double>(ctx);
+        np = std::max(np, (size_t)blocks_x(ctx->g, s.xR) * 9);
+        np = std::max(np, (size_t)blocks_z(ctx->g, s.zTX));
+    }
+    np = std::max(np, (size_t)blocks_u(ctx->g));
+    np = std::max(np, (size_t)material_blocks_pure(n) * 19);
+    np = std::max(np, (size_t)material_blocks_laminate(ctx->nc) * 31);
+    np = std::max(np, (size_t)2048 * 9);
+    HIP_OR_FAIL(ctx->part1.ensure(sizeof(double) * np));
+    HIP_OR_FAIL(ctx->part2.ensure(sizeof(double) * np));
+    HIP_OR_FAIL(ctx->sums.ensure(sizeof(double) * (kSumsLen + 16)));
+    HIP_OR_FAIL(ctx->cgst.ensure(sizeof(CGState)));
+    if (!ctx->hs) {
+        HIP_OR_FAIL(hipHostMalloc((void**)&ctx->hs, sizeof(HostScalars), hipHostMallocDefault));
+        memset(ctx->hs, 0, sizeof(HostScalars));
+    }
+    return COMBO_OK;
+}
+
+void reference_medium(const combo_ctx* ctx, double& mu0, double& kappa0) {
+    const double mu_m = ctx->mats[0].mu, mu_p = ctx->mats[1].mu;
+    const double k_m = ctx->mats[0].lambda + mu_m, k_p = ctx->mats[1].lambda + mu_p;
+    mu0 = ctx->opt.mu0 > 0 ? ctx->opt.mu0 : std::sqrt(mu_m * mu_p);
+    kappa0 = ctx->opt.kappa0 > 0 ? ctx->opt.kappa0 : std::sqrt(k_m * k_p);
+}
+
+// ------------------------------------------------------------------------------
+// building blocks
+// ------------------------------------------------------------------------------
+template <typename T>
+TangentState<T> tangent_state(const combo_ctx* ctx) {
+    TangentState<T> ts{};
+    ts.slot = ctx->slot.as<int>();
+    ts.Sinv = ctx->Sinv.as<T>();
+    ts.sm = ctx->sm.as<T>();
+    ts.Acomp = ctx->Acomp.as<T>();
+    for (int p = 0; p < 2; ++p) {
+        ts.mu[p] = T(ctx->mats[p].mu);
+        ts.lam[p] = T(ctx->mats[p].lambda);
+    }
+    ts.n = ctx->g.n;
+    return ts;
+}
+
+template <typename T>
+XArgs<T> xargs(const combo_ctx* ctx) {
+    XArgs<T> a{};
+    a.g = ctx->g;
+    a.plan = ctx->plan[0];
+    a.R = shape_for<T>(ctx).xR;
+    a.tw = twid<T>(ctx, 0);
+    a.ts = tangent_state<T>(ctx);
+    a.scale = 1.0 / (double)ctx->g.n;
+    a.partials = ctx->part1.as<double>();
+    a.st = ctx->cgst.as<CGState>();
+    return a;
+}
+
+template <typename T>
+YArgs<T> yargs(const combo_ctx* ctx, const void* in, void* out, bool use_state) {
+    YArgs<T> a{};
+    a.g = ctx->g;
+    a.plan = ctx->plan[1];
+    a.TX = shape_for<T>(ctx).yTX;
+    a.ntile = (ctx->g.nh + a.TX - 1) / a.TX;
+    a.tw = twid<T>(ctx, 1);
+    a.in = static_cast<const cpx<T>*>(in);
+    a.out = static_cast<cpx<T>*>(out);
+    a.st = use_state ? ctx->cgst.as<CGState>() : nullptr;
+    return a;
+}
+
+template <typename T, typename TU>
+ZArgs<T, TU> zargs(const combo_ctx* ctx, double mu0, double kappa0) {
+    ZArgs<T, TU> a{};
+    a.g = ctx->g;
+    a.plan = ctx->plan[2];
+    a.TX = shape_for<T>(ctx).zTX;
+    a.tw = twid<T>(ctx, 2);
+    a.x = ctx->ux.as<cpx<TU>>();
+    a.r = ctx->ur.as<cpx<TU>>();
+    a.p = ctx->up.as<cpx<TU>>();
+    a.q = ctx->uq.as<cpx<TU>>();
+    a.mu0 = mu0;
+    a.kappa0 = kappa0;
+    a.inv_n = 1.0 / (double)ctx->g.n;
+    a.partials = ctx->part1.as<double>();
+    a.partials2 = ctx->part2.as<double>();
+    a.st = ctx->cgst.as<CGState>();
+    return a;
+}
+
+// material law at F = F_old + s dF + dFbar -> F_trial, P, tangent state (precision T), a_trial.
+template <typename T>
+int material(combo_ctx* ctx, const double* F_old, const double* dF, double s, const double dFbar[9], double* F_new,
+             bool cold, double* A_full, double* a_full, int* it_full) {
+    MatArgs<T> m{};
+    m.n = ctx->g.n;
+    m.nc = ctx->nc;
+    m.F_old = F_old;
+    m.dF = dF;
+    m.s = s;
+    for (int c = 0; c < 9; ++c) m.dFbar[c] = dFbar ? dFbar[c] : 0.0;
+    m.F_new = F_new;
+    m.P = ctx->P.as<double>();
+    m.slot = ctx->slot.as<int>();
+    for (int p = 0; p < 2; ++p) {
+        m.mu[p] = ctx->mats[p].mu;
+        m.lam[p] = ctx->mats[p].lambda;
+    }
+    m.comp_vox = ctx->comp_vox.as<int>();
+    m.cc = ctx->comp_c.as<double>();
+    m.NN = ctx->comp_N.as<double>();
+    m.a_prev = ctx->a_prev.as<double>();
+    m.a_out = ctx->a_trial.as<double>();
+    m.warm = (!cold && ctx->opt.warm_start_laminate) ? 1 : 0;
+    m.maxit = ctx->opt.max_laminate;
+    m.Sinv = ctx->Sinv.as<T>();
+    m.sm = ctx->sm.as<T>();
+    m.Acomp = ctx->Acomp.as<T>();
+    m.A_full = A_full;
+    m.a_full = a_full;
+    m.iters_full = it_full;
+    m.partials = ctx->part1.as<double>();
+    m.partials2 = ctx->part2.as<double>();
+    const int nbp = material_blocks_pure(m.n), nbl = material_blocks_laminate(m.nc);
+    HIP_OR_FAIL(launch_material<T>(m, nbp, nbl, ctx->sums.as<double>(), ctx->stream));
+    HIP_OR_FAIL(hipMemcpyAsync(ctx->hs->sums, ctx->sums.p, sizeof(double) * kSumsLen, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    ctx->state_prec = sizeof(T) == 4 ? COMBO_MIXED : COMBO_FP64;
+    return COMBO_OK;
+}
+
+double material_failures(const combo_ctx* ctx) { return ctx->hs->sums[18] + ctx->hs->sums[46]; }
+
+void material_pbar(const combo_ctx* ctx, double Pbar[9]) {
+    const double* s = ctx->hs->sums;
+    for (int c = 0; c < 9; ++c) Pbar[c] = (s[c] + s[9 + c] + s[19 + c]) / (double)ctx->g.n;
+}
+
+// forward x and y passes of a real FP64 field into specB (6 components)
+template <typename T>
+int forward_xy_real(combo_ctx* ctx, const double* field) {
+    XArgs<T> xa = xargs<T>(ctx);
+    xa.real_in = field;
+    xa.out = ctx->specA.as<cpx<T>>();
+    HIP_OR_FAIL(launch_x<T>(X_FWD_REAL, xa, ctx->stream));
+    HIP_OR_FAIL(launch_y<T>(-1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, false), ctx->stream));
+    return COMBO_OK;
+}
+
+// residual of P (FP64): eta, and the right-hand side r = b = -K^{-1}(P_hat xi), x = 0 (precision TU)
+template <typename TU>
+int residual(combo_ctx* ctx, double mu0, double kappa0, double tol_cg, double& eta) {
+    int st = forward_xy_real<double>(ctx, ctx->P.as<double>());
+    if (st) return st;
+    ZArgs<double, TU> za = zargs<double, TU>(ctx, mu0, kappa0);
+    za.in = ctx->specB.as<double2>();
+    int nb = 0;
+    HIP_OR_FAIL(launch_z<double, TU>(Z_RHS, za, ctx->stream, &nb));
+    HIP_OR_FAIL(launch_finalize(FIN_RHS, ctx->cgst.as<CGState>(), ctx->part1.as<double>(), ctx->part2.as<double>(), nb,
+                                ctx->stream, tol_cg * tol_cg, ctx->opt.max_cg));
+    HIP_OR_FAIL(hipMemcpyAsync(&ctx->hs->cg, ctx->cgst.p, sizeof(CGState), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    double Pbar[9];
+    material_pbar(ctx, Pbar);
+    const double den = (double)ctx->g.n * std::max(frob9(Pbar), 1e-300);
+    eta = std::sqrt(std::max(ctx->hs->cg.eta2, 0.0)) / den;
+    return COMBO_OK;
+}
+
+// one CG iteration (8 launches)
+template <typename T>
+int cg_iteration(combo_ctx* ctx, double mu0, double kappa0) {
+    hipStream_t s = ctx->stream;
+    ZArgs<T, T> za = zargs<T, T>(ctx, mu0, kappa0);
+    za.out = ctx->specA.as<cpx<T>>();
+    HIP_OR_FAIL(launch_z<T, T>(Z_INV_CG, za, s));
+    HIP_OR_FAIL(launch_y<T>(+1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true), s));
+    XArgs<T> xa = xargs<T>(ctx);
+    xa.in = ctx->specB.as<cpx<T>>();
+    xa.out = ctx->specA.as<cpx<T>>();
+    HIP_OR_FAIL(launch_x<T>(X_CG, xa, s));
+    HIP_OR_FAIL(launch_y<T>(-1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true), s));
+    za.in = ctx->specB.as<cpx<T>>();
+    za.out = nullptr;
+    int nbz = 0;
+    HIP_OR_FAIL(launch_z<T, T>(Z_CG, za, s, &nbz));
+    HIP_OR_FAIL(launch_finalize(FIN_ALPHA, ctx->cgst.as<CGState>(), ctx->part1.as<double>(), nullptr, nbz, s));
+    UArgs<T> ua{};
+    ua.g = ctx->g;
+    ua.x = ctx->ux.as<cpx<T>>();
+    ua.r = ctx->ur.as<cpx<T>>();
+    ua.p = ctx->up.as<cpx<T>>();
+    ua.q = ctx->uq.as<cpx<T>>();
+    ua.mu0 = mu0;
+    ua.kappa0 = kappa0;
+    ua.partials = ctx->part2.as<double>();
+    ua.st = ctx->cgst.as<CGState>();
+    int nbu = 0;
+    HIP_OR_FAIL(launch_update<T>(ua, s, &nbu));
+    HIP_OR_FAIL(launch_finalize(FIN_BETA, ctx->cgst.as<CGState>(), ctx->part2.as<double>(), nullptr, nbu, s));
+    return COMBO_OK;
+}
+
+// CG solve on the right-hand side already in r (x = 0, FIN_RHS done); returns iterations
+template <typename T>
+int cg_solve(combo_ctx* ctx, double mu0, double kappa0, int& iters) {
+    const int chunk = ctx->opt.graph_chunk > 0 ? ctx->opt.graph_chunk : 8;
+    const bool use_graph = ctx->opt.graph_chunk > 0;
+    CGGraph& gr = ctx->graph[sizeof(T) == 4 ? 1 : 0];
+    if (use_graph && (!gr.exec || gr.iters != chunk)) {
+        gr.reset();
+        HIP_OR_FAIL(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        int st = COMBO_OK;
+        for (int k = 0; k < chunk && st == COMBO_OK; ++k) st = cg_iteration<T>(ctx, mu0, kappa0);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+        if (st) return st;
+        HIP_OR_FAIL(e);
+        gr.graph = g;
+        HIP_OR_FAIL(hipGraphInstantiate(&gr.exec, g, nullptr, nullptr, 0));
+        gr.iters = chunk;
+    }
+    const int max_rounds = ctx->opt.max_cg / chunk + 2;
+    for (int round = 0; round < max_rounds; ++round) {
+        HIP_OR_FAIL(hipMemcpyAsync(&ctx->hs->cg, ctx->cgst.p, sizeof(CGState), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+        if (ctx->hs->cg.done) break;
+        if (use_graph) {
+            HIP_OR_FAIL(hipGraphLaunch(gr.exec, ctx->stream));
+        } else {
+            for (int k = 0; k < chunk; ++k) {
+                int st = cg_iteration<T>(ctx, mu0, kappa0);
+                if (st) return st;
+            }
+        }
+    }
+    iters = ctx->hs->cg.iter;
+    if (!ctx->hs->cg.done)
+        return set_err(ctx, COMBO_E_NOCONV, "CG did not terminate");
+    if (ctx->hs->cg.status == 1)
+        return set_err(ctx, COMBO_E_NUMERIC, "CG breakdown (<p, A p> <= 0 or NaN)");
+    if (ctx->hs->cg.status == 2)
+        return set_err(ctx, COMBO_E_NOCONV, "CG did not converge in max_cg iterations");
+    return COMBO_OK;
+}
+
+// dF (FP64 field) from the CG solution x (precision TU)
+template <typename TU>
+int newton_direction(combo_ctx* ctx) {
+    ZArgs<double, TU> za = zargs<double, TU>(ctx, 1.0, 0.0);
+    za.out = ctx->specA.as<double2>();
+    HIP_OR_FAIL(launch_z<double, TU>(Z_INV_PLAIN, za, ctx->stream));
+    HIP_OR_FAIL(launch_y<double>(+1, yargs<double>(ctx, ctx->specA.p, ctx->specB.p, false), ctx->stream));
+    XArgs<double> xa = xargs<double>(ctx);
+    xa.in = ctx->specB.as<double2>();
+    xa.real_out = ctx->dF.as<double>();
+    HIP_OR_FAIL(launch_x<double>(X_INV_REAL, xa, ctx->stream));
+    return COMBO_OK;
+}
+
+// effective tangent column by column (precision T of the linear solves)
+template <typename T>
+int effective_tangent(combo_ctx* ctx, double mu0, double kappa0, double tol_cg, double Abar[81], int& cg_total) {
+    cg_total = 0;
+    for (int kL = 0; kL < 9; ++kL) {
+        XArgs<T> xa = xargs<T>(ctx);
+        for (int c = 0; c < 9; ++c) xa.E[c] = (c == kL) ? 1.0 : 0.0;
+        xa.out = ctx->specA.as<cpx<T>>();
+        HIP_OR_FAIL(launch_x<T>(X_RHS_E, xa, ctx->stream));
+        HIP_OR_FAIL(launch_y<T>(-1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, false), ctx->stream));
+        ZArgs<T, T> za = zargs<T, T>(ctx, mu0, kappa0);
+        za.in = ctx->specB.as<cpx<T>>();
+        int nb = 0;
+        HIP_OR_FAIL(launch_z<T, T>(Z_RHS, za, ctx->stream, &nb));
+        HIP_OR_FAIL(launch_finalize(FIN_RHS, ctx->cgst.as<CGState>(), ctx->part1.as<double>(), ctx->part2.as<double>(),
+                                    nb, ctx->stream, tol_cg * tol_cg, ctx->opt.max_cg));
+        int it = 0;
+        int st = cg_solve<T>(ctx, mu0, kappa0, it);
+        if (st) return st;
+        cg_total += it;
+        ZArgs<T, T> zi = zargs<T, T>(ctx, mu0, kappa0);
+        zi.out = ctx->specA.as<cpx<T>>();
+        HIP_OR_FAIL(launch_z<T, T>(Z_INV_PLAIN, zi, ctx->stream));
+        HIP_OR_FAIL(launch_y<T>(+1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, false), ctx->stream));
+        XArgs<T> xv = xargs<T>(ctx);
+        for (int c = 0; c < 9; ++c) xv.E[c] = (c == kL) ? 1.0 : 0.0;
+        xv.in = ctx->specB.as<cpx<T>>();
+        int nbx = 0;
+        HIP_OR_FAIL(launch_x<T>(X_AVG, xv, ctx->stream, &nbx));
+        double* col = ctx->sums.as<double>() + kSumsLen;
+        HIP_OR_FAIL(launch_reduce_columns(ctx->part1.as<double>(), nbx, 9, col, ctx->stream));
+        double h[9];
+        HIP_OR_FAIL(hipMemcpyAsync(h, col, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+        for (int r = 0; r < 9; ++r) Abar[9 * r + kL] = h[r] / (double)ctx->g.n;
+    }
+    return COMBO_OK;
+}
+
+// ------------------------------------------------------------------------------
+// the full solve
+// ------------------------------------------------------------------------------
+struct SolveOut {
+    combo_stats st{};
+    double Pbar[9]{};
+    double Pp[9]{}, Pm[9]{};
+};
+
+template <typename T>
+int solve_impl(combo_ctx* ctx, const double Fbar[9], const double Fbar0[9], SolveOut& out, double Abar[81]) {
+    const auto t_start = clk::now();
+    combo_stats& S = out.st;
+    double mu0, kappa0;
+    reference_medium(ctx, mu0, kappa0);
+    double tol_cg = ctx->opt.tol_cg;
+    if (sizeof(T) == 4) tol_cg = std::max(tol_cg, 1e-5);
+    const int K = std::max(1, ctx->opt.n_increments);
+    hipMemsetAsync(ctx->a_prev.p, 0, sizeof(double) * 3 * std::max(ctx->nc, 1), ctx->stream);
+    auto load = [&](double t, int c) { return Fbar0[c] + t * (Fbar[c] - Fbar0[c]); };
+    double* Fc = ctx->F_cur.as<double>();
+    double* Ft = ctx->F_trial.as<double>();
+    const size_t f9 = sizeof(double) * 9 * (size_t)ctx->g.n;
+    double eta = 0.0;
+    for (int k = 1; k <= K; ++k) {
+        const double t0 = double(k - 1) / K, t1 = double(k) / K;
+        double dt = t1 - t0, t = t0;
+        int depth = 0;
+        while (t < t1 - 1e-15) {
+            const double tn = std::min(t1, t + dt);
+            double dFbar[9];
+            for (int c = 0; c < 9; ++c) dFbar[c] = load(tn, c) - load(t, c);
+            HIP_OR_FAIL(hipMemcpyAsync(ctx->F_save.p, Fc, f9, hipMemcpyDeviceToDevice, ctx->stream));
+            bool converged = false;
+            auto tm = clk::now();
+            int st = material<T>(ctx, Fc, nullptr, 0.0, dFbar, Ft, false, nullptr, nullptr, nullptr);
+            S.time_ms_material += ms_since(tm);
+            if (st) return st;
+            if (material_failures(ctx) == 0.0) {
+                std::swap(ctx->F_cur.p, ctx->F_trial.p);
+                std::swap(ctx->a_prev.p, ctx->a_trial.p);
+                Fc = ctx->F_cur.as<double>();
+                Ft = ctx->F_trial.as<double>();
+                for (int it_n = 0; it_n <= ctx->opt.max_newton; ++it_n) {
+                    auto tr = clk::now();
+                    st = residual<T>(ctx, mu0, kappa0, tol_cg, eta);
+                    S.time_ms_residual += ms_since(tr);
+                    if (st) return st;
+                    if (!(eta == eta)) return set_err(ctx, COMBO_E_NUMERIC, "NaN in the equilibrium residual");
+                    if (eta <= ctx->opt.tol_newton) {
+                        converged = true;
+                        break;
+                    }
+                    if (it_n == ctx->opt.max_newton) break;
+                    auto tc = clk::now();
+                    int cgit = 0;
+                    st = cg_solve<T>(ctx, mu0, kappa0, cgit);
+                    S.time_ms_cg += ms_since(tc);
+                    S.cg_iters_total += cgit;
+                    if (st) {
+                        S.eta_final = eta;
+                        return st;
+                    }
+                    S.newton_iters += 1;
+                    st = newton_direction<T>(ctx);
+                    if (st) return st;
+                    double s = 1.0;
+                    bool ok = false;
+                    for (int h = 0; h <= ctx->opt.max_step_halvings; ++h) {
+                        tm = clk::now();
+                        st = material<T>(ctx, Fc, ctx->dF.as<double>(), s, nullptr, Ft, false, nullptr, nullptr,
+                                         nullptr);
+                        S.time_ms_material += ms_since(tm);
+                        if (st) return st;
+                        if (material_failures(ctx) == 0.0) {
+                            ok = true;
+                            break;
+                        }
+                        s *= 0.5;
+                        S.step_halvings += 1;
+                    }
+                    if (!ok) break;
+                    std::swap(ctx->F_cur.p, ctx->F_trial.p);
+                    std::swap(ctx->a_prev.p, ctx->a_trial.p);
+                    Fc = ctx->F_cur.as<double>();
+                    Ft = ctx->F_trial.as<double>();
+                }
+            }
+            if (converged) {
+                const double* sm = ctx->hs->sums;
+                S.laminate_iters_total += (long long)sm[47];
+                S.laminate_backprojections += (long long)sm[48];
+                S.laminate_iters_max = std::max(S.laminate_iters_max, (int)sm[49]);
+                S.increments_done += 1;
+                t = tn;
+            } else {
+                HIP_OR_FAIL(hipMemcpyAsync(Fc, ctx->F_save.p, f9, hipMemcpyDeviceToDevice, ctx->stream));
+                S.laminate_failures += (long long)(ctx->hs->sums[46]);
+                depth += 1;
+                S.cutbacks += 1;
+                if (depth > ctx->opt.max_cutbacks) {
+                    S.eta_final = eta;
+                    return set_err(ctx, COMBO_E_NOCONV, "load increment " + std::to_string(k) + " failed after " +
+                                                            std::to_string(ctx->opt.max_cutbacks) + " cutbacks");
+                }
+                dt *= 0.5;
+            }
+        }
+    }
+    S.eta_final = eta;
+    // effective stress and phase averages from the last (accepted) evaluation
+    const double* sm = ctx->hs->sums;
+    for (int c = 0; c < 9; ++c) {
+        out.Pbar[c] = (sm[c] + sm[9 + c] + sm[19 + c]) / (double)ctx->g.n;
+        const double vp = ctx->n_incl + ctx->sum_c, vm = ctx->n_mat + ((double)ctx->nc - ctx->sum_c);
+        out.Pp[c] = vp > 0 ? (sm[9 + c] + sm[28 + c]) / vp : 0.0;
+        out.Pm[c] = vm > 0 ? (sm[c] + sm[37 + c]) / vm : 0.0;
+    }
+    if (Abar) {
+        auto tt = clk::now();
+        int it = 0;
+        int st = effective_tangent<T>(ctx, mu0, kappa0, tol_cg, Abar, it);
+        S.time_ms_tangent += ms_since(tt);
+        S.cg_iters_tangent = it;
+        if (st) return st;
+    }
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    S.time_ms_total = ms_since(t_start);
+    return COMBO_OK;
+}
+
+int require_ready(combo_ctx* ctx) {
+    if (!ctx) return COMBO_E_INVAL;
+    if (!ctx->has_grid) return set_err(ctx, COMBO_E_STATE, "combo_set_grid has not been called");
+    if (!ctx->has_mats) return set_err(ctx, COMBO_E_STATE, "combo_set_materials has not been called");
+    if (!ctx->has_ms) return set_err(ctx, COMBO_E_STATE, "combo_set_microstructure has not been called");
+    return COMBO_OK;
+}
+
+int copy_in(combo_ctx* ctx, void* dst, const void* src, size_t bytes, int mem_kind) {
+    HIP_OR_FAIL(hipMemcpyAsync(dst, src, bytes, mem_kind == COMBO_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                                             : hipMemcpyHostToDevice,
+                               ctx->stream));
+    return COMBO_OK;
+}
+
+int copy_out(combo_ctx* ctx, void* dst, const void* src, size_t bytes, int mem_kind) {
+    HIP_OR_FAIL(hipMemcpyAsync(dst, src, bytes, mem_kind == COMBO_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                                             : hipMemcpyDeviceToHost,
+                               ctx->stream));
+    return COMBO_OK;
+}
+
+bool finite9(const double* a) {
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+double det9(const double* F) {
+    return F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) + F[2] * (F[3] * F[7] - F[4] * F[6]);
+}
+
+}  // namespace
+
+// ==============================================================================
+// C-ABI
+// ==============================================================================
+extern "C" {
+
+int combo_abi_version(void) { return COMBO_ABI_VERSION; }
+
+const char* combo_strerror(int status) {
+    switch (status) {
+        case COMBO_OK: return "ok";
+        case COMBO_E_INVAL: return "invalid argument";
+        case COMBO_E_NOMEM: return "out of memory";
+        case COMBO_E_HIP: return "HIP runtime error";
+        case COMBO_E_SIZE: return "unsupported grid size";
+        case COMBO_E_NOCONV: return "no convergence";
+        case COMBO_E_INADMISSIBLE: return "inadmissible deformation (det F <= 0)";
+        case COMBO_E_NUMERIC: return "numerical failure";
+        case COMBO_E_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+void combo_default_options(combo_options* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->precision = COMBO_FP64;
+    o->tol_newton = 1e-8;
+    o->tol_cg = 1e-10;
+    o->max_newton = 30;
+    o->max_cg = 5000;
+    o->max_laminate = 50;
+    o->n_increments = 1;
+    o->mu0 = 0.0;
+    o->kappa0 = 0.0;
+    o->warm_start_laminate = 1;
+    o->want_tangent = 0;
+    o->max_step_halvings = 10;
+    o->max_cutbacks = 5;
+    o->graph_chunk = 0;
+}
+
+int combo_check_size(int n) { return size_ok(n) ? COMBO_OK : COMBO_E_SIZE; }
+
+int combo_validate_microstructure(int n1, int n2, int n3, const uint8_t* phase, const double* c, const double* N,
+                                  char* msg, int msg_len) {
+    auto say = [&](const std::string& s) {
+        if (msg && msg_len > 0) {
+            strncpy(msg, s.c_str(), (size_t)msg_len - 1);
+            msg[msg_len - 1] = 0;
+        }
+        return COMBO_E_INVAL;
+    };
+    if (n1 < 1 || n2 < 1 || n3 < 1) return say("grid dimensions must be positive");
+    if (!phase || !c || !N) return say("null microstructure pointer");
+    const long long n = (long long)n1 * n2 * n3;
+    for (long long v = 0; v < n; ++v) {
+        const int ph = phase[v];
+        if (ph > 2) return say("phase id " + std::to_string(ph) + " at voxel " + std::to_string(v) + " (must be 0, 1, 2)");
+        if (ph != 2) continue;
+        const double cv = c[v];
+        if (!(cv > 0.0 && cv < 1.0)) return say("composite voxel " + std::to_string(v) + " has c outside (0, 1)");
+        const double a = N[v], b = N[n + v], d = N[2 * n + v];
+        if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(d))
+            return say("composite voxel " + std::to_string(v) + " has a non-finite normal");
+        const double nn = std::sqrt(a * a + b * b + d * d);
+        if (std::fabs(nn - 1.0) > 1e-6) return say("composite voxel " + std::to_string(v) + " normal is not unit length");
+    }
+    if (msg && msg_len > 0) msg[0] = 0;
+    return COMBO_OK;
+}
+
+int combo_create(combo_ctx** out, int device, void* stream) {
+    if (!out) return COMBO_E_INVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return COMBO_E_HIP;
+    if (device < 0 || device >= count) return COMBO_E_INVAL;
+    if (hipSetDevice(device) != hipSuccess) return COMBO_E_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return COMBO_E_HIP;
+    if (std::string(prop.gcnArchName).find("gfx950") == std::string::npos) return COMBO_E_HIP;
+    combo_ctx* ctx = new combo_ctx();
+    ctx->device = device;
+    ctx->lds_limit = prop.sharedMemPerBlock;
+    if (stream) {
+        ctx->stream = static_cast<hipStream_t>(stream);
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return COMBO_E_HIP;
+        }
+        ctx->own_stream = true;
+    }
+    combo_default_options(&ctx->opt);
+    *out = ctx;
+    return COMBO_OK;
+}
+
+int combo_destroy(combo_ctx* ctx) {
+    if (!ctx) return COMBO_E_INVAL;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& g : ctx->graph) g.reset();
+    if (ctx->hs) (void)hipHostFree(ctx->hs);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return COMBO_OK;
+}
+
+const char* combo_last_error(const combo_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2, double l3) {
+    if (!ctx) return COMBO_E_INVAL;
+    if (!size_ok(n1) || !size_ok(n2) || !size_ok(n3))
+        return set_err(ctx, COMBO_E_SIZE, "each grid axis must be 1 or 2^a 3^b <= 384");
+    if (!(l1 > 0 && l2 > 0 && l3 > 0) || !std::isfinite(l1) || !std::isfinite(l2) || !std::isfinite(l3))
+        return set_err(ctx, COMBO_E_INVAL, "box lengths must be positive and finite");
+    HIP_OR_FAIL(hipSetDevice(ctx->device));
+    ctx->g.n1 = n1;
+    ctx->g.n2 = n2;
+    ctx->g.n3 = n3;
+    ctx->g.nh = (n1 % 2 == 0) ? n1 / 2 : (n1 + 1) / 2;
+    ctx->g.n = (long long)n1 * n2 * n3;
+    ctx->g.nspec = (long long)ctx->g.nh * n2 * n3;
+    const double twopi = 6.283185307179586476925286766559;
+    ctx->g.xs1 = twopi / l1;
+    ctx->g.xs2 = twopi / l2;
+    ctx->g.xs3 = twopi / l3;
+    ctx->l[0] = l1;
+    ctx->l[1] = l2;
+    ctx->l[2] = l3;
+    const int ns[3] = {n1, n2, n3};
+    for (int d = 0; d < 3; ++d) {
+        ctx->plan[d] = make_plan(ns[d]);
+        const int L = ns[d];
+        std::vector<double2> w64(L);
+        std::vector<float2> w32(L);
+        for (int m = 0; m < L; ++m) {
+            const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)L;
+            w64[m].x = (double)cosl(ang);
+            w64[m].y = (double)sinl(ang);
+            w32[m].x = (float)w64[m].x;
+            w32[m].y = (float)w64[m].y;
+        }
+        HIP_OR_FAIL(ctx->tw64[d].ensure(sizeof(double2) * L));
+        HIP_OR_FAIL(ctx->tw32[d].ensure(sizeof(float2) * L));
+        HIP_OR_FAIL(hipMemcpy(ctx->tw64[d].p, w64.data(), sizeof(double2) * L, hipMemcpyHostToDevice));
+        HIP_OR_FAIL(hipMemcpy(ctx->tw32[d].p, w32.data(), sizeof(float2) * L, hipMemcpyHostToDevice));
+    }
+    for (auto& gr : ctx->graph) gr.reset();
+    ctx->has_grid = true;
+    ctx->has_ms = false;
+    return COMBO_OK;
+}
+
+int combo_set_materials(combo_ctx* ctx, const combo_material mats[2]) {
+    if (!ctx || !mats) return COMBO_E_INVAL;
+    for (int p = 0; p < 2; ++p)
+        if (!(mats[p].mu > 0.0) || !(mats[p].lambda >= 0.0) || !std::isfinite(mats[p].mu) ||
+            !std::isfinite(mats[p].lambda))
+            return set_err(ctx, COMBO_E_INVAL, "materials need mu > 0 and lambda >= 0");
+    ctx->mats[0] = mats[0];
+    ctx->mats[1] = mats[1];
+    ctx->has_mats = true;
+    for (auto& gr : ctx->graph) gr.reset();
+    return COMBO_OK;
+}
+
+int combo_set_options(combo_ctx* ctx, const combo_options* o) {
+    if (!ctx || !o) return COMBO_E_INVAL;
+    if (o->precision != COMBO_FP64 && o->precision != COMBO_MIXED)
+        return set_err(ctx, COMBO_E_INVAL, "precision must be COMBO_FP64 or COMBO_MIXED");
+    if (!(o->tol_newton > 0) || !(o->tol_cg > 0) || o->max_newton < 0 || o->max_cg < 1 || o->max_laminate < 0 ||
+        o->max_laminate > 64 || o->n_increments < 1 || o->max_step_halvings < 0 || o->max_cutbacks < 0 ||
+        o->graph_chunk < 0 || o->graph_chunk > 256)
+        return set_err(ctx, COMBO_E_INVAL, "option out of range");
+    ctx->opt = *o;
+    for (auto& gr : ctx->graph) gr.reset();
+    return COMBO_OK;
+}
+
+int combo_set_microstructure(combo_ctx* ctx, const uint8_t* phase, const double* c, const double* N, int mem_kind) {
+    if (!ctx) return COMBO_E_INVAL;
+    if (!ctx->has_grid) return set_err(ctx, COMBO_E_STATE, "combo_set_grid has not been called");
+    if (!phase || !c || !N) return set_err(ctx, COMBO_E_INVAL, "null microstructure pointer");
+    if (mem_kind != COMBO_MEM_HOST && mem_kind != COMBO_MEM_DEVICE) return set_err(ctx, COMBO_E_INVAL, "bad mem_kind");
+    HIP_OR_FAIL(hipSetDevice(ctx->device));
+    const long long n = ctx->g.n;
+    std::vector<uint8_t> hp;
+    std::vector<double> hc, hN;
+    const uint8_t* P = phase;
+    const double* C = c;
+    const double* NN = N;
+    if (mem_kind == COMBO_MEM_DEVICE) {
+        hp.resize(n);
+        hc.resize(n);
+        hN.resize(3 * n);
+        HIP_OR_FAIL(hipMemcpy(hp.data(), phase, n, hipMemcpyDeviceToHost));
+        HIP_OR_FAIL(hipMemcpy(hc.data(), c, sizeof(double) * n, hipMemcpyDeviceToHost));
+        HIP_OR_FAIL(hipMemcpy(hN.data(), N, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
+        P = hp.data();
+        C = hc.data();
+        NN = hN.data();
+    }
+    char msg[256];
+    if (combo_validate_microstructure(ctx->g.n1, ctx->g.n2, ctx->g.n3, P, C, NN, msg, sizeof(msg)) != COMBO_OK)
+        return set_err(ctx, COMBO_E_INVAL, msg);
+    std::vector<int> slot(n);
+    std::vector<int> vox;
+    std::vector<double> cc, nrm;
+    double nm = 0, ni = 0, sc = 0;
+    for (long long v = 0; v < n; ++v) {
+        if (P[v] == 0) {
+            slot[v] = -1;
+            nm += 1;
+        } else if (P[v] == 1) {
+            slot[v] = -2;
+            ni += 1;
+        } else {
+            slot[v] = (int)vox.size();
+            vox.push_back((int)v);
+            cc.push_back(C[v]);
+            sc += C[v];
+        }
+    }
+    const int nc = (int)vox.size();
+    nrm.resize(3 * (size_t)std::max(nc, 1));
+    for (int i = 0; i < nc; ++i) {
+        const long long v = vox[i];
+        double a = NN[v], b = NN[n + v], d = NN[2 * n + v];
+        const double s = 1.0 / std::sqrt(a * a + b * b + d * d);
+        nrm[i] = a * s;
+        nrm[nc + i] = b * s;
+        nrm[2 * nc + i] = d * s;
+    }
+    ctx->nc = nc;
+    ctx->n_mat = nm;
+    ctx->n_incl = ni;
+    ctx->sum_c = sc;
+    HIP_OR_FAIL(ctx->slot.ensure(sizeof(int) * n));
+    HIP_OR_FAIL(ctx->comp_vox.ensure(sizeof(int) * std::max(nc, 1)));
+    HIP_OR_FAIL(ctx->comp_c.ensure(sizeof(double) * std::max(nc, 1)));
+    HIP_OR_FAIL(ctx->comp_N.ensure(sizeof(double) * 3 * std::max(nc, 1)));
+    HIP_OR_FAIL(hipMemcpy(ctx->slot.p, slot.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    if (nc) {
+        HIP_OR_FAIL(hipMemcpy(ctx->comp_vox.p, vox.data(), sizeof(int) * nc, hipMemcpyHostToDevice));
+        HIP_OR_FAIL(hipMemcpy(ctx->comp_c.p, cc.data(), sizeof(double) * nc, hipMemcpyHostToDevice));
+        HIP_OR_FAIL(hipMemcpy(ctx->comp_N.p, nrm.data(), sizeof(double) * 3 * nc, hipMemcpyHostToDevice));
+    }
+    int st = ensure_work(ctx);
+    if (st) return st;
+    for (auto& gr : ctx->graph) gr.reset();
+    ctx->state_prec = -1;
+    ctx->has_ms = true;
+    return COMBO_OK;
+}
+
+int combo_solve(combo_ctx* ctx, const double Fbar[9], const double* F_init, double* F_out, double* P_out,
+                double Pbar[9], double Abar[81], double Pbar_phase[18], combo_stats* stats, int mem_kind) {
+    int st = require_ready(ctx);
+    if (st) return st;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if (!Fbar) return set_err(ctx, COMBO_E_INVAL, "Fbar is null");
+    if (mem_kind != COMBO_MEM_HOST && mem_kind != COMBO_MEM_DEVICE) return set_err(ctx, COMBO_E_INVAL, "bad mem_kind");
+    if (!finite9(Fbar)) {
+        if (stats) stats->status = COMBO_E_NUMERIC;
+        return set_err(ctx, COMBO_E_NUMERIC, "Fbar is not finite");
+    }
+    if (!(det9(Fbar) > 0.0)) {
+        if (stats) stats->status = COMBO_E_INADMISSIBLE;
+        return set_err(ctx, COMBO_E_INADMISSIBLE, "det Fbar <= 0");
+    }
+    HIP_OR_FAIL(hipSetDevice(ctx->device));
+    const long long n = ctx->g.n;
+    const size_t f9 = sizeof(double) * 9 * (size_t)n;
+    double Fbar0[9];
+    if (F_init) {
+        if (mem_kind == COMBO_MEM_HOST) {
+            for (long long v = 0; v < 9 * n; ++v)
+                if (!std::isfinite(F_init[v])) {
+                    if (stats) stats->status = COMBO_E_NUMERIC;
+                    return set_err(ctx, COMBO_E_NUMERIC, "F_init is not finite");
+                }
+            mean_field_host(F_init, n, Fbar0);
+        }
+        st = copy_in(ctx, ctx->F_cur.p, F_init, f9, mem_kind);
+        if (st) return st;
+        if (mem_kind == COMBO_MEM_DEVICE) {
+            const int nb = 1024;
+            hipLaunchKernelGGL(k_colsum9, dim3(nb), dim3(256), 0, ctx->stream, ctx->F_cur.as<double>(), n,
+                               ctx->part1.as<double>());
+            HIP_OR_FAIL(hipGetLastError());
+            HIP_OR_FAIL(launch_reduce_columns(ctx->part1.as<double>(), nb, 9, ctx->sums.as<double>() + kSumsLen,
+                                              ctx->stream));
+            HIP_OR_FAIL(hipMemcpyAsync(Fbar0, ctx->sums.as<double>() + kSumsLen, sizeof(Fbar0), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+            HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+            for (int c = 0; c < 9; ++c) Fbar0[c] /= (double)n;
+            if (!finite9(Fbar0)) {
+                if (stats) stats->status = COMBO_E_NUMERIC;
+                return set_err(ctx, COMBO_E_NUMERIC, "F_init is not finite");
+            }
+        }
+    } else {
+        hipLaunchKernelGGL(k_fill_identity, dim3(1024), dim3(256), 0, ctx->stream, ctx->F_cur.as<double>(), n);
+        HIP_OR_FAIL(hipGetLastError());
+        for (int c = 0; c < 9; ++c) Fbar0[c] = (c % 4 == 0) ? 1.0 : 0.0;
+    }
+    hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, ctx->stream, ctx->cgst.as<CGState>());
+    SolveOut so;
+    double Atmp[81];
+    double* Aptr = (ctx->opt.want_tangent && Abar) ? Atmp : nullptr;
+    if (ctx->opt.precision == COMBO_MIXED) st = solve_impl<float>(ctx, Fbar, Fbar0, so, Aptr);
+    else st = solve_impl<double>(ctx, Fbar, Fbar0, so, Aptr);
+    so.st.status = st;
+    if (stats) *stats = so.st;
+    if (st) return st;
+    if (Pbar) memcpy(Pbar, so.Pbar, sizeof(so.Pbar));
+    if (Pbar_phase) {
+        memcpy(Pbar_phase, so.Pp, sizeof(so.Pp));
+        memcpy(Pbar_phase + 9, so.Pm, sizeof(so.Pm));
+    }
+    if (Aptr) memcpy(Abar, Atmp, sizeof(Atmp));
+    if (F_out) {
+        st = copy_out(ctx, F_out, ctx->F_cur.p, f9, mem_kind);
+        if (st) return st;
+    }
+    if (P_out) {
+        st = copy_out(ctx, P_out, ctx->P.p, f9, mem_kind);
+        if (st) return st;
+    }
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    return COMBO_OK;
+}
+
+int combo_eval_law(combo_ctx* ctx, const double* F, double* Pout, double* A, double* a, int* iters, int mem_kind) {
+    int st = require_ready(ctx);
+    if (st) return st;
+    if (!F) return set_err(ctx, COMBO_E_INVAL, "F is null");
+    if (mem_kind != COMBO_MEM_HOST && mem_kind != COMBO_MEM_DEVICE) return set_err(ctx, COMBO_E_INVAL, "bad mem_kind");
+    HIP_OR_FAIL(hipSetDevice(ctx->device));
+    const long long n = ctx->g.n;
+    const size_t f9 = sizeof(double) * 9 * (size_t)n;
+    st = copy_in(ctx, ctx->F_save.p, F, f9, mem_kind);
+    if (st) return st;
+    DevBuf dA, da, dit;
+    if (A) HIP_OR_FAIL(dA.ensure(sizeof(double) * 81 * (size_t)n));
+    if (a) HIP_OR_FAIL(da.ensure(sizeof(double) * 3 * (size_t)n));
+    if (iters) HIP_OR_FAIL(dit.ensure(sizeof(int) * (size_t)n));
+    if (ctx->opt.precision == COMBO_MIXED)
+        st = material<float>(ctx, ctx->F_save.as<double>(), nullptr, 0.0, nullptr, ctx->F_trial.as<double>(), true,
+                             dA.as<double>(), da.as<double>(), dit.as<int>());
+    else
+        st = material<double>(ctx, ctx->F_save.as<double>(), nullptr, 0.0, nullptr, ctx->F_trial.as<double>(), true,
+                              dA.as<double>(), da.as<double>(), dit.as<int>());
+    if (st) return st;
+    if (Pout && (st = copy_out(ctx, Pout, ctx->P.p, f9, mem_kind))) return st;
+    if (A && (st = copy_out(ctx, A, dA.p, sizeof(double) * 81 * (size_t)n, mem_kind))) return st;
+    if (a && (st = copy_out(ctx, a, da.p, sizeof(double) * 3 * (size_t)n, mem_kind))) return st;
+    if (iters && (st = copy_out(ctx, iters, dit.p, sizeof(int) * (size_t)n, mem_kind))) return st;
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    if (material_failures(ctx) > 0.0)
+        return set_err(ctx, COMBO_E_INADMISSIBLE, "det F <= 0 or a laminate failed in some voxel");
+    return COMBO_OK;
+}
+
+}  // extern "C"
+
+namespace {
+template <typename T>
+int apply_green_impl(combo_ctx* ctx, int which, const double* tau_dev, double* out_dev) {
+    double mu0 = 1.0, kappa0 = 0.0;
+    if (which == COMBO_GREEN_GAMMA0) reference_medium(ctx, mu0, kappa0);
+    int st = forward_xy_real<T>(ctx, tau_dev);
+    if (st) return st;
+    ZArgs<T, T> za = zargs<T, T>(ctx, mu0, kappa0);
+    za.in = ctx->specB.as<cpx<T>>();
+    HIP_OR_FAIL(launch_z<T, T>(Z_PROJ, za, ctx->stream));
+    ZArgs<T, T> zi = zargs<T, T>(ctx, mu0, kappa0);
+    zi.out = ctx->specA.as<cpx<T>>();
+    HIP_OR_FAIL(launch_z<T, T>(Z_INV_PLAIN, zi, ctx->stream));
+    HIP_OR_FAIL(launch_y<T>(+1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, false), ctx->stream));
+    XArgs<T> xa = xargs<T>(ctx);
+    xa.in = ctx->specB.as<cpx<T>>();
+    xa.real_out = out_dev;
+    HIP_OR_FAIL(launch_x<T>(X_INV_REAL, xa, ctx->stream));
+    return COMBO_OK;
+}
+
+template <typename T>
+int apply_operator_impl(combo_ctx* ctx, const double* p_dev, double* q_dev) {
+    double mu0, kappa0;
+    reference_medium(ctx, mu0, kappa0);
+    // displacement coefficients of p: u = (p_hat xi) / |xi|^2 (exact for compatible p)
+    int st = forward_xy_real<T>(ctx, p_dev);
+    if (st) return st;
+    ZArgs<T, T> za = zargs<T, T>(ctx, 1.0, 0.0);
+    za.in = ctx->specB.as<cpx<T>>();
+    HIP_OR_FAIL(launch_z<T, T>(Z_PROJ, za, ctx->stream));
+    // one application of the CG operator: x -> q
+    hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, ctx->stream, ctx->cgst.as<CGState>());
+    HIP_OR_FAIL(hipGetLastError());
+    ZArgs<T, T> zi = zargs<T, T>(ctx, mu0, kappa0);
+    zi.out = ctx->specA.as<cpx<T>>();
+    HIP_OR_FAIL(launch_z<T, T>(Z_INV_PLAIN, zi, ctx->stream));
+    HIP_OR_FAIL(launch_y<T>(+1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true), ctx->stream));
+    XArgs<T> xa = xargs<T>(ctx);
+    xa.in = ctx->specB.as<cpx<T>>();
+    xa.out = ctx->specA.as<cpx<T>>();
+    HIP_OR_FAIL(launch_x<T>(X_CG, xa, ctx->stream));
+    HIP_OR_FAIL(launch_y<T>(-1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true), ctx->stream));
+    ZArgs<T, T> zc = zargs<T, T>(ctx, mu0, kappa0);
+    zc.in = ctx->specB.as<cpx<T>>();
+    zc.p = zc.x;
+    HIP_OR_FAIL(launch_z<T, T>(Z_CG, zc, ctx->stream));
+    // q -> field
+    ZArgs<T, T> zq = zargs<T, T>(ctx, mu0, kappa0);
+    zq.x = zq.q;
+    zq.out = ctx->specA.as<cpx<T>>();
+    HIP_OR_FAIL(launch_z<T, T>(Z_INV_PLAIN, zq, ctx->stream));
+    HIP_OR_FAIL(launch_y<T>(+1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, false), ctx->stream));
+    XArgs<T> xo = xargs<T>(ctx);
+    xo.in = ctx->specB.as<cpx<T>>();
+    xo.real_out = q_dev;
+    HIP_OR_FAIL(launch_x<T>(X_INV_REAL, xo, ctx->stream));
+    return COMBO_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int combo_apply_green(combo_ctx* ctx, int which, int precision, const double* tau, double* out, int mem_kind) {
+    if (!ctx) return COMBO_E_INVAL;
+    if (!ctx->has_grid) return set_err(ctx, COMBO_E_STATE, "combo_set_grid has not been called");
+    if (which != COMBO_GREEN_GAMMA0 && which != COMBO_GREEN_G) return set_err(ctx, COMBO_E_INVAL, "bad operator id");
+    if (which == COMBO_GREEN_GAMMA0 && !ctx->has_mats && (ctx->opt.mu0 <= 0 || ctx->opt.kappa0 <= 0))
+        return set_err(ctx, COMBO_E_STATE, "Gamma0 needs materials or an explicit reference medium");
+    if (precision != COMBO_FP64 && precision != COMBO_MIXED) return set_err(ctx, COMBO_E_INVAL, "bad precision");
+    if (!tau || !out) return set_err(ctx, COMBO_E_INVAL, "null field");
+    if (mem_kind != COMBO_MEM_HOST && mem_kind != COMBO_MEM_DEVICE) return set_err(ctx, COMBO_E_INVAL, "bad mem_kind");
+    HIP_OR_FAIL(hipSetDevice(ctx->device));
+    if (!ctx->has_ms) {
+        ctx->nc = 0;
+        int st = ensure_work(ctx);
+        if (st) return st;
+    }
+    const size_t f9 = sizeof(double) * 9 * (size_t)ctx->g.n;
+    int st = copy_in(ctx, ctx->F_save.p, tau, f9, mem_kind);
+    if (st) return st;
+    if (precision == COMBO_MIXED) st = apply_green_impl<float>(ctx, which, ctx->F_save.as<double>(), ctx->dF.as<double>());
+    else st = apply_green_impl<double>(ctx, which, ctx->F_save.as<double>(), ctx->dF.as<double>());
+    if (st) return st;
+    st = copy_out(ctx, out, ctx->dF.p, f9, mem_kind);
+    if (st) return st;
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    return COMBO_OK;
+}
+
+int combo_apply_operator(combo_ctx* ctx, int precision, const double* p, double* q, int mem_kind) {
+    int st = require_ready(ctx);
+    if (st) return st;
+    if (precision != COMBO_FP64 && precision != COMBO_MIXED) return set_err(ctx, COMBO_E_INVAL, "bad precision");
+    if (ctx->state_prec != precision)
+        return set_err(ctx, COMBO_E_STATE, "no tangent state of this precision: call combo_eval_law first");
+    if (!p || !q) return set_err(ctx, COMBO_E_INVAL, "null field");
+    if (mem_kind != COMBO_MEM_HOST && mem_kind != COMBO_MEM_DEVICE) return set_err(ctx, COMBO_E_INVAL, "bad mem_kind");
+    HIP_OR_FAIL(hipSetDevice(ctx->device));
+    const size_t f9 = sizeof(double) * 9 * (size_t)ctx->g.n;
+    st = copy_in(ctx, ctx->F_save.p, p, f9, mem_kind);
+    if (st) return st;
+    if (precision == COMBO_MIXED) st = apply_operator_impl<float>(ctx, ctx->F_save.as<double>(), ctx->dF.as<double>());
+    else st = apply_operator_impl<double>(ctx, ctx->F_save.as<double>(), ctx->dF.as<double>());
+    if (st) return st;
+    st = copy_out(ctx, q, ctx->dF.p, f9, mem_kind);
+    if (st) return st;
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    return COMBO_OK;
+}
+
+}  // extern "C"
