@@ -1,0 +1,220 @@
+"""Benchmark: ComBo Lippmann-Schwinger Newton-CG solve on one MI355X.
+
+Workload (default): 256^3 RVE, 200 random spheres (radii U[0.03, 0.06] L
+rescaled to c = 0.30), composite boxels from 4^3 subsamples, Neo-Hooke matrix
+(mu, lambda) = (1, 2) and inclusions 100x stiffer, uniaxial stretch to 20 % in
+10 increments, Newton tolerance eta <= 1e-6.  One step = one full solve.
+
+value = voxel-CG-iterations per second of the mixed-precision solve (FP32
+linear solves, FP64 law and residual); the FP64 solve's time-to-solution is
+reported beside it.  Per-kernel durations come from HIP events the library
+records on its stream around every launch during the timed steps.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
+"""
+import argparse
+import json
+import os
+import platform
+import resource
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(name, n, nspec, nc, s):
+    """Algorithmic HBM bytes of one launch of a CG kernel class (s = bytes per real)."""
+    c2 = 2 * s * nspec            # one complex component of the half spectrum / one CG vector component
+    table = {
+        "xpass_cg": 18 * c2 + 4 * n + 10 * s * (n - nc) + 45 * s * nc,
+        "ypass_inv": 15 * c2,
+        "ypass_fwd": 15 * c2,
+        "zpass_inv": 15 * c2,
+        "zpass_fwd": 12 * c2,
+        "cg_update": 18 * c2,
+    }
+    return table.get(name)
+
+
+def cpu_cores_used(cpu_s, wall_s):
+    return max(1, int(round(cpu_s / max(wall_s, 1e-9))))
+
+
+def cpu_baseline(ms, lc, sub=128, iters=3):
+    """Time the FP64 oracle's CG iterations on a sub-block of the same workload."""
+    from oracle import solver as osol
+    from oracle import spectral as ospec
+    from paper_2204_13624_amd import synth
+    crop = synth.Microstructure(n=(sub, sub, sub), l=(sub / ms.n[0],) * 3,
+                                phase=np.ascontiguousarray(ms.phase[:sub, :sub, :sub]),
+                                c=np.ascontiguousarray(ms.c[:sub, :sub, :sub]),
+                                N=np.ascontiguousarray(ms.N[:, :sub, :sub, :sub]), info={})
+    prob = osol.Problem(crop.n, crop.l, crop.phase, crop.c, crop.N, lc.mats)
+    mu0, kappa0 = osol.reference_medium(lc.mats)
+    Fb1 = np.eye(3) + (lc.Fbar - np.eye(3)) / lc.n_increments
+    F = np.broadcast_to(Fb1[:, :, None, None, None], (3, 3, sub, sub, sub)).copy()
+    P, Av, ok, _, _ = osol.evaluate(F, prob)
+    b = -ospec.apply_gamma0(P, prob.n, prob.l, mu0, kappa0)
+    t0, c0 = time.perf_counter(), time.process_time()
+    try:
+        osol.cg(Av, b, prob, mu0, kappa0, 1e-30, iters)
+    except osol.SolveError:
+        pass
+    wall, cpu = time.perf_counter() - t0, time.process_time() - c0
+    nv = sub ** 3
+    return {"value": nv * iters / wall, "unit": "voxel-CG-iters/s", "cores": cpu_cores_used(cpu, wall),
+            "kind": "oracle",
+            "sample": "%d CG iterations of the FP64 numpy oracle on a %d^3 block of the same microstructure "
+                      "at the first load increment (%.1f s wall, host %s)" % (iters, sub, wall, platform.processor()
+                                                                             or platform.machine())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--tol-cg", type=float, default=1e-4)
+    ap.add_argument("--graph-chunk", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2204_13624_amd import combo, synth
+
+    t = time.time()
+    ms, lc = synth.workload_spheres_256(args.n)
+    log("workload generated in %.1f s: n=%d, composites=%d, c=%.4f" % (time.time() - t, ms.nvox, ms.n_composite,
+                                                                       ms.info["c_total"]))
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda:0")
+    ctx = combo.combo_create(0)
+    combo.combo_set_grid(ctx, *ms.n, *ms.l)
+    combo.combo_set_materials(ctx, lc.mats)
+    combo.combo_set_microstructure(ctx, torch.from_numpy(ms.phase).to(dev), torch.from_numpy(ms.c).to(dev),
+                                   torch.from_numpy(np.ascontiguousarray(ms.N)).to(dev))
+
+    def options(precision):
+        o = combo.combo_default_options()
+        o.precision = precision
+        o.tol_newton = 1e-6
+        o.tol_cg = args.tol_cg
+        o.n_increments = lc.n_increments
+        o.max_cg = 20000
+        o.graph_chunk = args.graph_chunk
+        return o
+
+    combo.combo_set_options(ctx, options(combo.COMBO_MIXED))
+    for w in range(args.warmup):
+        r = combo.combo_solve(ctx, lc.Fbar)
+        log("warmup %d: %.2f s, newton %d, cg %d" % (w, r["stats"]["time_ms_total"] / 1e3, r["stats"]["newton_iters"],
+                                                   r["stats"]["cg_iters_total"]))
+    if not args.no_profile:
+        combo.combo_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cg_total = 0
+    results = []
+    for k in range(args.steps):
+        r = combo.combo_solve(ctx, lc.Fbar)
+        cg_total += r["stats"]["cg_iters_total"]
+        results.append(r)
+        log("step %d: %.2f s, newton %d, cg %d, eta %.2e" % (k, r["stats"]["time_ms_total"] / 1e3,
+                                                            r["stats"]["newton_iters"], r["stats"]["cg_iters_total"],
+                                                            r["stats"]["eta_final"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = combo.combo_profile_all(ctx) if not args.no_profile else {}
+    combo.combo_profile_enable(ctx, False)
+    n = ms.nvox
+    nh = ms.n[0] // 2 if ms.n[0] % 2 == 0 else (ms.n[0] + 1) // 2
+    nspec = nh * ms.n[1] * ms.n[2]
+    nc = ms.n_composite
+    value = n * cg_total / elapsed
+    Pbar_mixed = results[-1]["Pbar"]
+
+    # roofline of the dominant CG kernel
+    roof = None
+    kernels = {}
+    for name, (msec, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        avg = msec / cnt
+        b = kernel_bytes(name, n, nspec, nc, 4)
+        kernels[name] = {"ms_total": round(msec, 3), "launches": cnt, "avg_us": round(avg * 1e3, 2)}
+        if b is not None:
+            kernels[name]["GBps"] = round(b / (avg * 1e-3) / 1e9, 1)
+            kernels[name]["bytes_per_launch"] = b
+    cg_kernels = {k: v for k, v in kernels.items() if "GBps" in v}
+    if cg_kernels:
+        dom = max(cg_kernels, key=lambda k: cg_kernels[k]["ms_total"])
+        ach = cg_kernels[dom]["GBps"]
+        roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": cg_kernels[dom]["bytes_per_launch"], "avg_us": cg_kernels[dom]["avg_us"]}
+    b_cg = sum(kernel_bytes(k, n, nspec, nc, 4) for k in
+               ("xpass_cg", "ypass_inv", "ypass_fwd", "zpass_inv", "zpass_fwd", "cg_update")) / n
+
+    out = {
+        "metric": "voxel-CG-iters/s at 256³ + time-to-solution (rel. residual 1e-6), mixed vs FP64",
+        "value": value,
+        "unit": "voxel-CG-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 linear solves (FFT, Green operator, tangent action, CG) + f64 law, laminate, residual",
+        "data": "synthetic",
+        "config": {"workload": "spheres_256: %d^3 RVE, 200 spheres c=0.30 (RSA, radii U[0.03,0.06]L rescaled), "
+                               "4^3-subsample composite boxels, Neo-Hooke (1,2) / contrast 100, uniaxial stretch "
+                               "to 20%% in 10 increments, eta<=1e-6, tol_cg %.0e" % (args.n, args.tol_cg),
+                   "n_vox": n, "n_composite": nc, "precision": "mixed", "parallelism": "1 GPU"},
+        "cg_iters_per_step": cg_total / args.steps,
+        "newton_iters_per_step": results[-1]["stats"]["newton_iters"],
+        "bytes_per_voxel_cg_iter": round(b_cg, 1),
+        "hbm_frac_whole_cg": round(value * b_cg / (HBM_PEAK_GBS * 1e9), 4),
+        "kernels": kernels,
+        "roofline": roof,
+        "time_to_solution_s": {"mixed": results[-1]["stats"]["time_ms_total"] / 1e3},
+    }
+    if not args.no_fp64:
+        combo.combo_set_options(ctx, options(combo.COMBO_FP64))
+        r64 = combo.combo_solve(ctx, lc.Fbar)
+        out["time_to_solution_s"]["fp64"] = r64["stats"]["time_ms_total"] / 1e3
+        out["fp64_cg_iters"] = r64["stats"]["cg_iters_total"]
+        out["fp64_voxel_cg_iters_per_s"] = n * r64["stats"]["cg_iters_total"] / (r64["stats"]["time_ms_total"] / 1e3)
+        out["pbar_rel_diff_mixed_vs_fp64"] = float(np.abs(Pbar_mixed - r64["Pbar"]).max() /
+                                                   np.abs(r64["Pbar"]).max())
+        log("fp64: %.2f s, cg %d" % (out["time_to_solution_s"]["fp64"], r64["stats"]["cg_iters_total"]))
+    combo.combo_destroy(ctx)
+    if not args.no_cpu:
+        t = time.time()
+        out["cpu_baseline"] = cpu_baseline(ms, lc)
+        log("cpu baseline in %.1f s" % (time.time() - t))
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

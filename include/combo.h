@@ -27,7 +27,7 @@
  *     N = unit interface normal pointing out of the inclusion (Sec. 2, 5.1).
  *     c and N are read only where phase == 2.
  *   - Materials: index 0 = matrix, 1 = inclusion, each (mu, lambda).
- *   - Every grid axis must be 1 or a product of 2s and 3s, at most 768
+ *   - Every grid axis must be 1 or a product of 2s and 3s, at most 384
  *     (COMBO_E_SIZE otherwise).
  *
  * Ownership: the caller owns every pointer it passes.  set_* calls copy their
@@ -135,7 +135,7 @@ void combo_default_options(combo_options* opt);
  * msg_len bytes) receives a description of the first problem. */
 int combo_validate_microstructure(int n1, int n2, int n3, const uint8_t* phase, const double* c,
                                   const double* N, char* msg, int msg_len);
-/* Returns COMBO_OK if n is 1 or a product of 2s and 3s not above 768. */
+/* Returns COMBO_OK if n is 1 or a product of 2s and 3s not above 384. */
 int combo_check_size(int n);
 
 /* Context ------------------------------------------------------------------ */
@@ -183,6 +183,28 @@ int combo_apply_green(combo_ctx* ctx, int which, int precision, const double* ta
 /* q = Gamma0[A : p] with the tangent state of the last combo_eval_law, for a
  * compatible zero-mean field p [9][n]; the linear operator of each Newton step. */
 int combo_apply_operator(combo_ctx* ctx, int precision, const double* p, double* q, int mem_kind);
+
+/* Per-kernel timing ---------------------------------------------------------
+ * With profiling on, the context records a HIP event pair on its stream around
+ * every launch of the kernel classes below (the CG iterations then run as
+ * plain launches, not as captured graphs) and accumulates the elapsed time.
+ * Reading does not reset; combo_profile_enable(ctx, 1) resets the counters. */
+enum combo_kernel {
+    COMBO_K_XPASS_CG = 0,     /* x pass of the CG operator: C2R, tangent action, R2C */
+    COMBO_K_YPASS_INV = 1,    /* y pass, inverse (6 -> 9 components) */
+    COMBO_K_YPASS_FWD = 2,    /* y pass, forward (9 -> 6 components) */
+    COMBO_K_ZPASS_INV = 3,    /* z pass, inverse, with the search-direction update */
+    COMBO_K_ZPASS_FWD = 4,    /* z pass, forward, with the Green projection and <p, A p> */
+    COMBO_K_CG_UPDATE = 5,    /* x += alpha p, r -= alpha q, <r, r> */
+    COMBO_K_CG_FINALIZE = 6,  /* the two one-workgroup scalar reductions of a CG iteration */
+    COMBO_K_MATERIAL = 7,     /* pure-voxel law + laminate law + their reductions */
+    COMBO_K_RESIDUAL = 8,     /* FP64 x, y, z forward passes of P, residual norm, right-hand side */
+    COMBO_K_NEWTON_DIR = 9,   /* FP64 inverse passes giving dF */
+    COMBO_K_COUNT = 10
+};
+int combo_profile_enable(combo_ctx* ctx, int enable);
+/* Accumulated milliseconds and number of timed launches of one kernel class. */
+int combo_profile_read(combo_ctx* ctx, int kernel, double* ms_total, long long* launches);
 
 #ifdef __cplusplus
 }

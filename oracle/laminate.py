@@ -107,6 +107,7 @@ def solve(Fbox, c, N, mat_minus, mat_plus, backprojection=True, maxit=MAX_ITERS,
     Fsafe = np.where(good[:, None, None], Fbox, np.eye(3))
     mb, beta_p, beta_m = admissibility_data(Fsafe, c, N)
     D = jump_matrix(N)
+    DT = np.swapaxes(D, 1, 2)
     a = np.zeros((m, 3)) if a_init is None else np.array(a_init, float)
     iters = np.zeros(m, dtype=int)
     nbp = np.zeros(m, dtype=int)
@@ -133,7 +134,7 @@ def solve(Fbox, c, N, mat_minus, mat_plus, backprojection=True, maxit=MAX_ITERS,
         active &= ~done
         if not active.any():
             break
-        Delta = np.einsum("mpi,mpq,mqk->mik", D, Ap / cp[:, None, None] + Am / cm[:, None, None], D)
+        Delta = DT @ (Ap / cp[:, None, None] + Am / cm[:, None, None]) @ D
         da = np.zeros_like(a)
         da[active] = np.linalg.solve(Delta[active], f[active][..., None])[..., 0]
         # stagnation at round-off: the Newton correction is negligible against a
@@ -155,11 +156,11 @@ def solve(Fbox, c, N, mat_minus, mat_plus, backprojection=True, maxit=MAX_ITERS,
         if trace:
             history.append(a.copy())
     Pbox = cp[:, None, None] * Pp + cm[:, None, None] * Pm
-    Delta = np.einsum("mpi,mpq,mqk->mik", D, Ap / cp[:, None, None] + Am / cm[:, None, None], D)
+    Delta = DT @ (Ap / cp[:, None, None] + Am / cm[:, None, None]) @ D
     dA = Ap - Am
     with np.errstate(invalid="ignore"):
         Dinv = np.linalg.inv(np.where(np.isfinite(Delta), Delta, np.eye(3)))
-    corr = np.einsum("mpq,mqi,mik,mrk,mrs->mps", dA, D, Dinv, D, dA)
+    corr = dA @ D @ Dinv @ DT @ dA
     Abox = cp[:, None, None] * Ap + cm[:, None, None] * Am - corr
     out = dict(P=Pbox, A=Abox, a=a, iters=iters, n_backproj=nbp, status=status,
                Pp=Pp, Pm=Pm, Fp=Fp, Fm=Fm)

@@ -100,7 +100,12 @@ _SIGS = {
     "combo_eval_law": (_I, [_P, _P, _P, _P, _P, _P, _I]),
     "combo_apply_green": (_I, [_P, _I, _I, _P, _P, _I]),
     "combo_apply_operator": (_I, [_P, _I, _P, _P, _I]),
+    "combo_profile_enable": (_I, [_P, _I]),
+    "combo_profile_read": (_I, [_P, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
 }
+
+KERNEL_NAMES = ["xpass_cg", "ypass_inv", "ypass_fwd", "zpass_inv", "zpass_fwd", "cg_update", "cg_finalize",
+                "material", "residual", "newton_dir"]
 
 _lib = None
 
@@ -281,6 +286,22 @@ def combo_apply_operator(ctx, precision, p, q):
     pp, k1 = _ptr(p, np.float64)
     qp, k2 = _ptr(q, np.float64)
     _check(ctx, load_library().combo_apply_operator(ctx, int(precision), pp, qp, _mem_kind(k1, k2)))
+
+
+def combo_profile_enable(ctx, enable=True):
+    _check(ctx, load_library().combo_profile_enable(ctx, 1 if enable else 0))
+
+
+def combo_profile_read(ctx, kernel):
+    """(milliseconds, launches) accumulated for one kernel class."""
+    ms = ctypes.c_double()
+    nl = ctypes.c_longlong()
+    _check(ctx, load_library().combo_profile_read(ctx, int(kernel), ctypes.byref(ms), ctypes.byref(nl)))
+    return ms.value, nl.value
+
+
+def combo_profile_all(ctx):
+    return {name: combo_profile_read(ctx, k) for k, name in enumerate(KERNEL_NAMES)}
 
 
 # ---- convenience object ----------------------------------------------------------

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "combo.h"
 #include "common.h"
@@ -96,4 +97,12 @@ struct combo_ctx {
     combo::DevBuf part1, part2, sums, cgst;
     combo::HostScalars* hs = nullptr;     // pinned host copy of the device scalars
     combo::CGGraph graph[2];
+
+    // per-kernel event timing
+    bool profile = false;
+    struct ProfRec { int kernel; hipEvent_t start, stop; };
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    double prof_ms[COMBO_K_COUNT] = {};
+    long long prof_n[COMBO_K_COUNT] = {};
 };

@@ -23,6 +23,8 @@
 //
 // Real transforms along x pack two real components into one complex FFT:
 // z = a + i b, A_k = (Z_k + conj Z_{n-k})/2, B_k = (Z_k - conj Z_{n-k})/(2i).
+#include <algorithm>
+
 #include "fft_lds.h"
 #include "kernels.h"
 
@@ -631,7 +633,66 @@ __global__ void __launch_bounds__(kBlock) k_zpass_inv(ZArgs<T, TU> a) {
 
 // ------------------------------------------------------------------------------
 // CG update: x += alpha p, r -= alpha q, partial <r, r>_K
+//
+// On the stored half spectrum the x = 0 frequency plane holds both members of
+// each conjugate pair (0, ky, kz) / (0, -ky, -kz).  A displacement coefficient
+// field of a real deformation is anti-Hermitian there, u(-k) = -conj(u(k)); its
+// Hermitian part is discarded by the real inverse transform along x and is
+// therefore a null space of the CG operator.  Round-off would feed it and CG
+// would grow it once the right-hand side is small, so r is projected back on
+// the anti-Hermitian part in that plane; the thread owning the lower index of a
+// pair updates both members.
 // ------------------------------------------------------------------------------
+__device__ __forceinline__ long long kx0_partner(const Grid& g, long long M, int z, int ky) {
+    const int z2 = (g.n3 - z) % g.n3, ky2 = (g.n2 - ky) % g.n2;
+    return (long long)z2 * M + (long long)ky2 * g.nh;
+}
+
+template <typename CU>
+__device__ __forceinline__ void antiherm_pair(CU& a, CU& b) {
+    // a <- (a - conj b)/2, b <- -conj(a_new)
+    using TU = decltype(a.x);
+    const double ax = 0.5 * (double(a.x) - double(b.x));
+    const double ay = 0.5 * (double(a.y) + double(b.y));
+    a.x = TU(ax);
+    a.y = TU(ay);
+    b.x = TU(-ax);
+    b.y = TU(ay);
+}
+
+template <typename TU>
+__device__ __forceinline__ double cg_update_one(const UArgs<TU>& a, long long idx, double alpha, cpx<TU>* rr) {
+    using CU = cpx<TU>;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const long long o = i * a.g.nspec + idx;
+        CU xi = a.x[o];
+        const CU pi = a.p[o];
+        CU ri = a.r[o];
+        const CU qi = a.q[o];
+        xi.x = TU(double(xi.x) + alpha * double(pi.x));
+        xi.y = TU(double(xi.y) + alpha * double(pi.y));
+        ri.x = TU(double(ri.x) - alpha * double(qi.x));
+        ri.y = TU(double(ri.y) - alpha * double(qi.y));
+        a.x[o] = xi;
+        rr[i] = ri;
+    }
+    return 0.0;
+}
+
+template <typename TU>
+__device__ __forceinline__ double rkr(const UArgs<TU>& a, const cpx<TU>* rr, long long M, long long idx) {
+    const int z = (int)(idx / M);
+    const Freq f = freq_at(a.g, idx - (long long)z * M, z);
+    if (f.zero) return 0.0;
+    double kr[3], ki[3];
+    kmul(f, a.mu0, a.kappa0, rr, kr, ki);
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) t += double(rr[i].x) * kr[i] + double(rr[i].y) * ki[i];
+    return f.w * t;
+}
+
 template <typename TU>
 __global__ void __launch_bounds__(kBlock) k_cg_update(UArgs<TU> a) {
     using CU = cpx<TU>;
@@ -644,34 +705,63 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(UArgs<TU> a) {
          idx += (long long)gridDim.x * blockDim.x) {
         const int z = (int)(idx / M);
         const long long m = idx - (long long)z * M;
-        CU rr[3];
+        const int ky = (int)(m / a.g.nh);
+        const int kx = (int)(m - (long long)ky * a.g.nh);
+        CU r1[3];
+        if (kx != 0) {
+            cg_update_one(a, idx, alpha, r1);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const long long o = i * a.g.nspec + idx;
-            CU xi = a.x[o];
-            const CU pi = a.p[o];
-            CU ri = a.r[o];
-            const CU qi = a.q[o];
-            xi.x = TU(double(xi.x) + alpha * double(pi.x));
-            xi.y = TU(double(xi.y) + alpha * double(pi.y));
-            ri.x = TU(double(ri.x) - alpha * double(qi.x));
-            ri.y = TU(double(ri.y) - alpha * double(qi.y));
-            a.x[o] = xi;
-            a.r[o] = ri;
-            rr[i] = ri;
+            for (int i = 0; i < 3; ++i) a.r[i * a.g.nspec + idx] = r1[i];
+            s += rkr(a, r1, M, idx);
+            continue;
         }
-        const Freq f = freq_at(a.g, m, z);
-        if (!f.zero) {
-            double kr[3], ki[3];
-            kmul(f, a.mu0, a.kappa0, rr, kr, ki);
-            double t = 0.0;
+        const long long idx2 = kx0_partner(a.g, M, z, ky);
+        if (idx2 < idx) continue;   // the partner's thread owns this pair
+        cg_update_one(a, idx, alpha, r1);
+        if (idx2 == idx) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) t += double(rr[i].x) * kr[i] + double(rr[i].y) * ki[i];
-            s += f.w * t;
+            for (int i = 0; i < 3; ++i) r1[i].x = TU(0);   // self-conjugate: purely imaginary
+        } else {
+            CU r2[3];
+            cg_update_one(a, idx2, alpha, r2);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                antiherm_pair(r1[i], r2[i]);
+                a.r[i * a.g.nspec + idx2] = r2[i];
+            }
+            s += rkr(a, r2, M, idx2);
         }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) a.r[i * a.g.nspec + idx] = r1[i];
+        s += rkr(a, r1, M, idx);
     }
     const double tot = block_sum(s, red);
     if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
+}
+
+// anti-Hermitian projection of the x = 0 plane of one CG vector (right-hand sides)
+template <typename TU>
+__global__ void __launch_bounds__(kBlock) k_antiherm_kx0(cpx<TU>* u, Grid g) {
+    const long long M = (long long)g.n2 * g.nh;
+    const long long npl = (long long)g.n2 * g.n3;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < npl; t += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(t / g.n2), ky = (int)(t - (long long)z * g.n2);
+        const long long idx = (long long)z * M + (long long)ky * g.nh;
+        const long long idx2 = kx0_partner(g, M, z, ky);
+        if (idx2 < idx) continue;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            cpx<TU> a = u[i * g.nspec + idx];
+            if (idx2 == idx) {
+                a.x = TU(0);
+            } else {
+                cpx<TU> b = u[i * g.nspec + idx2];
+                antiherm_pair(a, b);
+                u[i * g.nspec + idx2] = b;
+            }
+            u[i * g.nspec + idx] = a;
+        }
+    }
 }
 
 // ------------------------------------------------------------------------------
@@ -793,6 +883,14 @@ hipError_t launch_update(const UArgs<TU>& a, hipStream_t s, int* nb) {
     return hipGetLastError();
 }
 
+template <typename TU>
+hipError_t launch_antiherm(cpx<TU>* u, const Grid& g, hipStream_t s) {
+    long long npl = (long long)g.n2 * g.n3;
+    int nb = (int)std::min<long long>((npl + kBlock - 1) / kBlock, 1024);
+    hipLaunchKernelGGL(k_antiherm_kx0<TU>, dim3(nb), dim3(kBlock), 0, s, u, g);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(int mode, CGState* st, const double* partials, const double* partials2, int count,
                            hipStream_t s, double tol2, int maxit) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, mode, st, partials, partials2, count, tol2, maxit);
@@ -813,5 +911,7 @@ template hipError_t launch_z<double, double>(int, const ZArgs<double, double>&, 
 template hipError_t launch_z<double, float>(int, const ZArgs<double, float>&, hipStream_t, int*);
 template hipError_t launch_update<float>(const UArgs<float>&, hipStream_t, int*);
 template hipError_t launch_update<double>(const UArgs<double>&, hipStream_t, int*);
+template hipError_t launch_antiherm<float>(cpx<float>*, const Grid&, hipStream_t);
+template hipError_t launch_antiherm<double>(cpx<double>*, const Grid&, hipStream_t);
 
 }  // namespace combo

@@ -114,6 +114,8 @@ enum ZMode { Z_CG = 0, Z_RHS = 1, Z_INV_CG = 2, Z_INV_PLAIN = 3, Z_PROJ = 4 };
 template <typename T, typename TU> hipError_t launch_z(int mode, const ZArgs<T, TU>& a, hipStream_t s,
                                                        int* nblocks_out = nullptr);
 template <typename TU> hipError_t launch_update(const UArgs<TU>& a, hipStream_t s, int* nblocks_out = nullptr);
+// anti-Hermitian projection of the x = 0 frequency plane of a CG vector
+template <typename TU> hipError_t launch_antiherm(cpx<TU>* u, const Grid& g, hipStream_t s);
 // finalisers (one workgroup): reduce `count` partials in fixed order
 enum FinMode { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RHS = 2 };
 hipError_t launch_finalize(int mode, CGState* st, const double* partials, const double* partials2, int count,

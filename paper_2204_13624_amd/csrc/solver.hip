@@ -27,6 +27,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -50,6 +51,16 @@ int set_err(combo_ctx* ctx, int status, const std::string& msg) {
             return set_err(ctx, e__ == hipErrorOutOfMemory ? COMBO_E_NOMEM : COMBO_E_HIP,                   \
                            std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e__));                      \
     } while (0)
+
+// COMBO_VERBOSE=1 in the environment traces Newton and CG progress on stderr.
+bool verbose() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("COMBO_VERBOSE");
+        v = (e && e[0] && e[0] != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
 
 using clk = std::chrono::steady_clock;
 double ms_since(clk::time_point t0) { return std::chrono::duration<double, std::milli>(clk::now() - t0).count(); }
@@ -128,6 +139,55 @@ double frob9(const double* a) {
     for (int i = 0; i < 9; ++i) s += a[i] * a[i];
     return std::sqrt(s);
 }
+
+// ------------------------------------------------------------------------------
+// per-kernel event timing (no-ops unless profiling is on)
+// ------------------------------------------------------------------------------
+hipEvent_t prof_event(combo_ctx* ctx) {
+    if (!ctx->prof_pool.empty()) {
+        hipEvent_t e = ctx->prof_pool.back();
+        ctx->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int prof_begin(combo_ctx* ctx, int kernel) {
+    if (!ctx->profile) return -1;
+    combo_ctx::ProfRec r{kernel, prof_event(ctx), prof_event(ctx)};
+    if (!r.start || !r.stop) return -1;
+    (void)hipEventRecord(r.start, ctx->stream);
+    ctx->prof_pending.push_back(r);
+    return (int)ctx->prof_pending.size() - 1;
+}
+
+void prof_end(combo_ctx* ctx, int idx) {
+    if (idx < 0) return;
+    (void)hipEventRecord(ctx->prof_pending[idx].stop, ctx->stream);
+}
+
+// call after the stream has been synchronised
+void prof_harvest(combo_ctx* ctx) {
+    for (auto& r : ctx->prof_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+            ctx->prof_ms[r.kernel] += ms;
+            ctx->prof_n[r.kernel] += 1;
+        }
+        ctx->prof_pool.push_back(r.start);
+        ctx->prof_pool.push_back(r.stop);
+    }
+    ctx->prof_pending.clear();
+}
+
+struct ProfScope {
+    combo_ctx* ctx;
+    int idx;
+    ProfScope(combo_ctx* c, int k) : ctx(c), idx(prof_begin(c, k)) {}
+    ~ProfScope() { prof_end(ctx, idx); }
+};
 
 // ------------------------------------------------------------------------------
 // work buffers
@@ -281,10 +341,14 @@ int material(combo_ctx* ctx, const double* F_old, const double* dF, double s, co
     m.partials = ctx->part1.as<double>();
     m.partials2 = ctx->part2.as<double>();
     const int nbp = material_blocks_pure(m.n), nbl = material_blocks_laminate(m.nc);
-    HIP_OR_FAIL(launch_material<T>(m, nbp, nbl, ctx->sums.as<double>(), ctx->stream));
+    {
+        ProfScope ps(ctx, COMBO_K_MATERIAL);
+        HIP_OR_FAIL(launch_material<T>(m, nbp, nbl, ctx->sums.as<double>(), ctx->stream));
+    }
     HIP_OR_FAIL(hipMemcpyAsync(ctx->hs->sums, ctx->sums.p, sizeof(double) * kSumsLen, hipMemcpyDeviceToHost,
                                ctx->stream));
     HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    prof_harvest(ctx);
     ctx->state_prec = sizeof(T) == 4 ? COMBO_MIXED : COMBO_FP64;
     return COMBO_OK;
 }
@@ -310,16 +374,21 @@ int forward_xy_real(combo_ctx* ctx, const double* field) {
 // residual of P (FP64): eta, and the right-hand side r = b = -K^{-1}(P_hat xi), x = 0 (precision TU)
 template <typename TU>
 int residual(combo_ctx* ctx, double mu0, double kappa0, double tol_cg, double& eta) {
-    int st = forward_xy_real<double>(ctx, ctx->P.as<double>());
-    if (st) return st;
-    ZArgs<double, TU> za = zargs<double, TU>(ctx, mu0, kappa0);
-    za.in = ctx->specB.as<double2>();
-    int nb = 0;
-    HIP_OR_FAIL(launch_z<double, TU>(Z_RHS, za, ctx->stream, &nb));
-    HIP_OR_FAIL(launch_finalize(FIN_RHS, ctx->cgst.as<CGState>(), ctx->part1.as<double>(), ctx->part2.as<double>(), nb,
-                                ctx->stream, tol_cg * tol_cg, ctx->opt.max_cg));
+    {
+        ProfScope ps(ctx, COMBO_K_RESIDUAL);
+        int st = forward_xy_real<double>(ctx, ctx->P.as<double>());
+        if (st) return st;
+        ZArgs<double, TU> za = zargs<double, TU>(ctx, mu0, kappa0);
+        za.in = ctx->specB.as<double2>();
+        int nb = 0;
+        HIP_OR_FAIL(launch_z<double, TU>(Z_RHS, za, ctx->stream, &nb));
+        HIP_OR_FAIL(launch_antiherm<TU>(ctx->ur.as<cpx<TU>>(), ctx->g, ctx->stream));
+        HIP_OR_FAIL(launch_finalize(FIN_RHS, ctx->cgst.as<CGState>(), ctx->part1.as<double>(), ctx->part2.as<double>(),
+                                    nb, ctx->stream, tol_cg * tol_cg, ctx->opt.max_cg));
+    }
     HIP_OR_FAIL(hipMemcpyAsync(&ctx->hs->cg, ctx->cgst.p, sizeof(CGState), hipMemcpyDeviceToHost, ctx->stream));
     HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    prof_harvest(ctx);
     double Pbar[9];
     material_pbar(ctx, Pbar);
     const double den = (double)ctx->g.n * std::max(frob9(Pbar), 1e-300);
@@ -333,18 +402,36 @@ int cg_iteration(combo_ctx* ctx, double mu0, double kappa0) {
     hipStream_t s = ctx->stream;
     ZArgs<T, T> za = zargs<T, T>(ctx, mu0, kappa0);
     za.out = ctx->specA.as<cpx<T>>();
-    HIP_OR_FAIL(launch_z<T, T>(Z_INV_CG, za, s));
-    HIP_OR_FAIL(launch_y<T>(+1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true), s));
+    {
+        ProfScope ps(ctx, COMBO_K_ZPASS_INV);
+        HIP_OR_FAIL(launch_z<T, T>(Z_INV_CG, za, s));
+    }
+    {
+        ProfScope ps(ctx, COMBO_K_YPASS_INV);
+        HIP_OR_FAIL(launch_y<T>(+1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true), s));
+    }
     XArgs<T> xa = xargs<T>(ctx);
     xa.in = ctx->specB.as<cpx<T>>();
     xa.out = ctx->specA.as<cpx<T>>();
-    HIP_OR_FAIL(launch_x<T>(X_CG, xa, s));
-    HIP_OR_FAIL(launch_y<T>(-1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true), s));
+    {
+        ProfScope ps(ctx, COMBO_K_XPASS_CG);
+        HIP_OR_FAIL(launch_x<T>(X_CG, xa, s));
+    }
+    {
+        ProfScope ps(ctx, COMBO_K_YPASS_FWD);
+        HIP_OR_FAIL(launch_y<T>(-1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true), s));
+    }
     za.in = ctx->specB.as<cpx<T>>();
     za.out = nullptr;
     int nbz = 0;
-    HIP_OR_FAIL(launch_z<T, T>(Z_CG, za, s, &nbz));
-    HIP_OR_FAIL(launch_finalize(FIN_ALPHA, ctx->cgst.as<CGState>(), ctx->part1.as<double>(), nullptr, nbz, s));
+    {
+        ProfScope ps(ctx, COMBO_K_ZPASS_FWD);
+        HIP_OR_FAIL(launch_z<T, T>(Z_CG, za, s, &nbz));
+    }
+    {
+        ProfScope ps(ctx, COMBO_K_CG_FINALIZE);
+        HIP_OR_FAIL(launch_finalize(FIN_ALPHA, ctx->cgst.as<CGState>(), ctx->part1.as<double>(), nullptr, nbz, s));
+    }
     UArgs<T> ua{};
     ua.g = ctx->g;
     ua.x = ctx->ux.as<cpx<T>>();
@@ -356,8 +443,14 @@ int cg_iteration(combo_ctx* ctx, double mu0, double kappa0) {
     ua.partials = ctx->part2.as<double>();
     ua.st = ctx->cgst.as<CGState>();
     int nbu = 0;
-    HIP_OR_FAIL(launch_update<T>(ua, s, &nbu));
-    HIP_OR_FAIL(launch_finalize(FIN_BETA, ctx->cgst.as<CGState>(), ctx->part2.as<double>(), nullptr, nbu, s));
+    {
+        ProfScope ps(ctx, COMBO_K_CG_UPDATE);
+        HIP_OR_FAIL(launch_update<T>(ua, s, &nbu));
+    }
+    {
+        ProfScope ps(ctx, COMBO_K_CG_FINALIZE);
+        HIP_OR_FAIL(launch_finalize(FIN_BETA, ctx->cgst.as<CGState>(), ctx->part2.as<double>(), nullptr, nbu, s));
+    }
     return COMBO_OK;
 }
 
@@ -365,7 +458,7 @@ int cg_iteration(combo_ctx* ctx, double mu0, double kappa0) {
 template <typename T>
 int cg_solve(combo_ctx* ctx, double mu0, double kappa0, int& iters) {
     const int chunk = ctx->opt.graph_chunk > 0 ? ctx->opt.graph_chunk : 8;
-    const bool use_graph = ctx->opt.graph_chunk > 0;
+    const bool use_graph = ctx->opt.graph_chunk > 0 && !ctx->profile;
     CGGraph& gr = ctx->graph[sizeof(T) == 4 ? 1 : 0];
     if (use_graph && (!gr.exec || gr.iters != chunk)) {
         gr.reset();
@@ -384,6 +477,11 @@ int cg_solve(combo_ctx* ctx, double mu0, double kappa0, int& iters) {
     for (int round = 0; round < max_rounds; ++round) {
         HIP_OR_FAIL(hipMemcpyAsync(&ctx->hs->cg, ctx->cgst.p, sizeof(CGState), hipMemcpyDeviceToHost, ctx->stream));
         HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+        prof_harvest(ctx);
+        if (verbose())
+            fprintf(stderr, "[combo] cg iter %d  |r|/|b| %.3e  alpha %.3e  beta %.3e  done %d  status %d\n",
+                    ctx->hs->cg.iter, std::sqrt(std::max(ctx->hs->cg.rho, 0.0) / std::max(ctx->hs->cg.rho0, 1e-300)),
+                    ctx->hs->cg.alpha, ctx->hs->cg.beta, ctx->hs->cg.done, ctx->hs->cg.status);
         if (ctx->hs->cg.done) break;
         if (use_graph) {
             HIP_OR_FAIL(hipGraphLaunch(gr.exec, ctx->stream));
@@ -407,6 +505,7 @@ int cg_solve(combo_ctx* ctx, double mu0, double kappa0, int& iters) {
 // dF (FP64 field) from the CG solution x (precision TU)
 template <typename TU>
 int newton_direction(combo_ctx* ctx) {
+    ProfScope ps(ctx, COMBO_K_NEWTON_DIR);
     ZArgs<double, TU> za = zargs<double, TU>(ctx, 1.0, 0.0);
     za.out = ctx->specA.as<double2>();
     HIP_OR_FAIL(launch_z<double, TU>(Z_INV_PLAIN, za, ctx->stream));
@@ -432,6 +531,7 @@ int effective_tangent(combo_ctx* ctx, double mu0, double kappa0, double tol_cg, 
         za.in = ctx->specB.as<cpx<T>>();
         int nb = 0;
         HIP_OR_FAIL(launch_z<T, T>(Z_RHS, za, ctx->stream, &nb));
+        HIP_OR_FAIL(launch_antiherm<T>(ctx->ur.as<cpx<T>>(), ctx->g, ctx->stream));
         HIP_OR_FAIL(launch_finalize(FIN_RHS, ctx->cgst.as<CGState>(), ctx->part1.as<double>(), ctx->part2.as<double>(),
                                     nb, ctx->stream, tol_cg * tol_cg, ctx->opt.max_cg));
         int it = 0;
@@ -505,6 +605,9 @@ int solve_impl(combo_ctx* ctx, const double Fbar[9], const double Fbar0[9], Solv
                     st = residual<T>(ctx, mu0, kappa0, tol_cg, eta);
                     S.time_ms_residual += ms_since(tr);
                     if (st) return st;
+                    if (verbose())
+                        fprintf(stderr, "[combo] increment %d t=%.4f newton %d eta %.3e rho0 %.3e fails %g\n", k, tn,
+                                it_n, eta, ctx->hs->cg.rho0, material_failures(ctx));
                     if (!(eta == eta)) return set_err(ctx, COMBO_E_NUMERIC, "NaN in the equilibrium residual");
                     if (eta <= ctx->opt.tol_newton) {
                         converged = true;
@@ -584,6 +687,7 @@ int solve_impl(combo_ctx* ctx, const double Fbar[9], const double Fbar0[9], Solv
         if (st) return st;
     }
     HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    prof_harvest(ctx);
     S.time_ms_total = ms_since(t_start);
     return COMBO_OK;
 }
@@ -725,6 +829,8 @@ int combo_destroy(combo_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     for (auto& g : ctx->graph) g.reset();
+    prof_harvest(ctx);
+    for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
     if (ctx->hs) (void)hipHostFree(ctx->hs);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -1098,6 +1204,27 @@ int combo_apply_operator(combo_ctx* ctx, int precision, const double* p, double*
     st = copy_out(ctx, q, ctx->dF.p, f9, mem_kind);
     if (st) return st;
     HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    return COMBO_OK;
+}
+
+int combo_profile_enable(combo_ctx* ctx, int enable) {
+    if (!ctx) return COMBO_E_INVAL;
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    prof_harvest(ctx);
+    ctx->profile = enable != 0;
+    for (int k = 0; k < COMBO_K_COUNT; ++k) {
+        ctx->prof_ms[k] = 0.0;
+        ctx->prof_n[k] = 0;
+    }
+    return COMBO_OK;
+}
+
+int combo_profile_read(combo_ctx* ctx, int kernel, double* ms_total, long long* launches) {
+    if (!ctx || kernel < 0 || kernel >= COMBO_K_COUNT) return COMBO_E_INVAL;
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    prof_harvest(ctx);
+    if (ms_total) *ms_total = ctx->prof_ms[kernel];
+    if (launches) *launches = ctx->prof_n[kernel];
     return COMBO_OK;
 }
 
