@@ -49,7 +49,22 @@ struct Grid {
     long long n;          // n1*n2*n3
     long long nspec;      // nh*n2*n3 (complex values per spectral component)
     double xs1, xs2, xs3; // 2 pi / l_d: xi_d(k) = xs_d * k
+    int xm, xwbits;       // wavefront x pass: m values per lane, log2 of lanes per row (-1: none)
 };
+
+// Position of voxel `vox` in the tangent-state arrays.  With the wavefront x
+// pass, voxel x of a row sits in lane bitrev(x / m), slot x mod m after the
+// inverse transform, so the state is stored at lane + W slot within the row and
+// the x pass reads it unit-stride; otherwise the natural order is kept.
+__host__ __device__ inline long long state_pos(long long vox, int n1, int xm, int xwbits) {
+    if (xwbits < 0) return vox;
+    const long long row = vox / n1;
+    const int x = (int)(vox - row * n1);
+    const int s = x % xm, t = x / xm;
+    int l = 0;
+    for (int b = 0; b < xwbits; ++b) l |= ((t >> b) & 1) << (xwbits - 1 - b);
+    return row * n1 + l + (1 << xwbits) * s;
+}
 
 __host__ __device__ inline int freq_of(int j, int n) { return (j < (n + 1) / 2) ? j : j - n; }
 // true if index j is the Nyquist index of an even axis of length n

@@ -86,7 +86,7 @@ struct combo_ctx {
     bool has_ms = false;
     int nc = 0;
     double n_mat = 0, n_incl = 0, sum_c = 0;
-    combo::DevBuf slot, comp_vox, comp_c, comp_N, a_prev, a_trial;
+    combo::DevBuf slot, slot_s, comp_vox, comp_c, comp_N, a_prev, a_trial;   // slot: natural order, slot_s: state_pos order
 
     // fields (FP64) and work buffers
     combo::DevBuf F_cur, F_trial, F_save, dF, P;

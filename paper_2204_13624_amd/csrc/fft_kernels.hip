@@ -25,8 +25,12 @@
 // z = a + i b, A_k = (Z_k + conj Z_{n-k})/2, B_k = (Z_k - conj Z_{n-k})/(2i).
 #include <algorithm>
 
+#include <type_traits>
+
 #include "fft_lds.h"
+#include "fft_reg.h"
 #include "kernels.h"
+#include "wave_fft.h"
 
 namespace combo {
 
@@ -51,8 +55,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // tangent action tau = A : p
 // ------------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void tangent_apply(const TangentState<T>& ts, long long vox, const T* p, T* tau) {
-    const int slot = ts.slot[vox];
+__device__ __forceinline__ void tangent_apply(const TangentState<T>& ts, long long sidx, const T* p, T* tau) {
+    const int slot = ts.slot[sidx];
     if (slot >= 0) {
         const T* A = ts.Acomp + (long long)slot * 45;
         T a[45];
@@ -74,8 +78,8 @@ __device__ __forceinline__ void tangent_apply(const TangentState<T>& ts, long lo
     const T mu = ts.mu[ph], lam = ts.lam[ph];
     T fi[9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) fi[c] = ts.Sinv[c * ts.n + vox];
-    const T m = ts.sm[vox];
+    for (int c = 0; c < 9; ++c) fi[c] = ts.Sinv[c * ts.n + sidx];
+    const T m = ts.sm[sidx];
     // B = F^{-1} p, C = B F^{-1};  tau_iJ = mu p_iJ + lam tr(B) Finv_Ji + m C_Ji
     T B[9];
 #pragma unroll
@@ -195,7 +199,7 @@ __global__ void __launch_bounds__(kBlock) k_xpass(XArgs<T> a) {
 #pragma unroll
                 for (int c = 0; c < 9; ++c) tau[c] = p[c];
             } else {
-                tangent_apply<T>(a.ts, vox, p, tau);
+                tangent_apply<T>(a.ts, state_pos(vox, a.g.n1, a.g.xm, a.g.xwbits), p, tau);
             }
             if (MODE == X_AVG) {
 #pragma unroll
@@ -239,6 +243,160 @@ __global__ void __launch_bounds__(kBlock) k_xpass(XArgs<T> a) {
         if (s < 4) a.out[cb * a.g.nspec + off] = hb;
     }
 }
+
+// ------------------------------------------------------------------------------
+// x pass, wavefront version: one grid row (y, z) per group of W lanes, m = n1/W
+// values per lane and sequence, all five packed sequences in registers, no LDS
+// and no barriers (wave_fft.h).  The inverse transform leaves voxel
+// x = s + m bitrev(l) in lane l, slot s, which is where the tangent is applied;
+// the forward transform returns to the natural layout for the store.
+// ------------------------------------------------------------------------------
+template <typename T, int MODE, int M, int W>
+__global__ void __launch_bounds__(256) k_xwave(XArgs<T> a) {
+    using C = cpx<T>;
+    constexpr int L = M * W;
+    constexpr int G = 256 / W;   // rows per workgroup
+    if (MODE == X_CG && a.st->done) return;
+    __shared__ double red[16];
+    const int lane = threadIdx.x % W;
+    const long long nrows = (long long)a.g.n2 * a.g.n3;
+    const long long row = (long long)blockIdx.x * G + threadIdx.x / W;
+    const bool live = row < nrows;
+    const int nh = a.g.nh;
+    const T xs1 = T(a.g.xs1);
+    WaveTwiddles<T, M, W> tw;
+    tw.load(a.tw, lane);
+    constexpr bool HAS_INV = (MODE == X_CG || MODE == X_AVG || MODE == X_INV_REAL);
+    constexpr bool HAS_FWD = (MODE == X_CG || MODE == X_RHS_E || MODE == X_FWD_REAL);
+    C z[5][M];
+    const int xbase = M * bitrev_lane<W>(lane);   // voxel of slot s is xbase + s
+
+    if (HAS_INV) {
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            const int ca = 2 * s, cb = 2 * s + 1;
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                const int k = lane + W * r;
+                C ha = mk<T>(0, 0), hb = mk<T>(0, 0);
+                bool conj = false;
+                int kk = k;
+                if (k >= nh) {
+                    kk = L - k;
+                    conj = true;
+                }
+                const bool valid = live && !(k >= nh && kk >= nh);   // kk = nh only at the even-n1 Nyquist bin
+                if (valid) {
+                    const long long off = row * nh + kk;
+                    ha = a.in[ca * a.g.nspec + off];
+                    if (s < 4) hb = a.in[cb * a.g.nspec + off];
+                    const T x1 = xs1 * T(kk);
+                    if (xi1_comp(ca)) ha = cscale(ha, x1);
+                    if (s < 4 && xi1_comp(cb)) hb = cscale(hb, x1);
+                }
+                if (k == 0) {
+                    z[s][r] = mk<T>(ha.x, hb.x);
+                } else if (!conj) {
+                    z[s][r] = mk<T>(ha.x - hb.y, ha.y + hb.x);
+                } else {
+                    z[s][r] = mk<T>(ha.x + hb.y, hb.x - ha.y);
+                }
+            }
+            wave_fft_nat2scr<+1, M, W, T>(z[s], lane, tw);
+        }
+    }
+
+    double acc[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < M; ++sl) {
+        const long long vox = row * L + xbase + sl;
+        T p[9];
+        if (MODE == X_RHS_E) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) p[c] = T(a.E[c]);
+        } else if (MODE == X_FWD_REAL) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) p[c] = live ? T(a.real_in[c * a.g.n + vox]) : T(0);
+        } else {
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                p[2 * s] = z[s][sl].x;
+                if (s < 4) p[2 * s + 1] = z[s][sl].y;
+            }
+        }
+        if (MODE == X_INV_REAL) {
+            if (live)
+#pragma unroll
+                for (int c = 0; c < 9; ++c) a.real_out[c * a.g.n + vox] = double(p[c]) * a.scale;
+            continue;
+        }
+        if (MODE == X_AVG) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) p[c] = T(double(p[c]) * a.scale + a.E[c]);
+        }
+        T tau[9];
+        if (MODE == X_FWD_REAL || !live) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) tau[c] = p[c];
+        } else {
+            tangent_apply<T>(a.ts, row * L + lane + W * sl, p, tau);
+        }
+        if (MODE == X_AVG) {
+            if (live)
+#pragma unroll
+                for (int c = 0; c < 9; ++c) acc[c] += double(tau[c]);
+            continue;
+        }
+#pragma unroll
+        for (int s = 0; s < 5; ++s) z[s][sl] = mk<T>(tau[2 * s], s < 4 ? tau[2 * s + 1] : T(0));
+    }
+    if (MODE == X_AVG) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const double t = block_sum(acc[c], red);
+            if (threadIdx.x == 0) a.partials[(long long)blockIdx.x * 9 + c] = t;
+        }
+        return;
+    }
+    if (!HAS_FWD) return;
+    const int src = (W - lane) & (W - 1);
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+        wave_fft_scr2nat<-1, M, W, T>(z[s], lane, tw);
+        const int ca = 2 * s, cb = 2 * s + 1;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            if (W * r >= nh) break;                       // no lane of this slot stores
+            const C zk = z[s][r];
+            C zm = shfl_c<W, T>(z[s][M - 1 - r], src);       // index L - k for lanes l >= 1
+            if (lane == 0) zm = z[s][(M - r) % M];        // index L - W r for lane 0
+            const int k = lane + W * r;
+            if (!live || k >= nh) continue;
+            C ha = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+            C hb = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
+            const T x1 = xs1 * T(k);
+            if (xi1_comp(ca)) ha = cscale(ha, x1);
+            if (xi1_comp(cb)) hb = cscale(hb, x1);
+            const long long off = row * nh + k;
+            a.out[ca * a.g.nspec + off] = ha;
+            if (s < 4) a.out[cb * a.g.nspec + off] = hb;
+        }
+    }
+}
+
+// (M, W) of the wavefront x pass for a row length n1, or M = 0 if unsupported
+#define COMBO_XWAVE_CONFIGS(X) \
+    X(256, 4, 64)              \
+    X(128, 2, 64)              \
+    X(64, 1, 64)               \
+    X(384, 6, 64)              \
+    X(192, 3, 64)              \
+    X(96, 3, 32)               \
+    X(48, 3, 16)               \
+    X(32, 1, 32)               \
+    X(16, 1, 16)
 
 // ------------------------------------------------------------------------------
 // y passes: tile = TX consecutive x frequencies of one z plane, all y
@@ -420,6 +578,69 @@ __device__ __forceinline__ void kmul(const Freq& f, double mu0, double kappa0, c
     }
 }
 
+// Per-frequency end of the forward z pass: given v = tau_hat xi at (m, z),
+//   Z_CG:   q = K^{-1} v / n, accumulate <p, q>_K = w Re(p^H v)/n
+//   Z_RHS:  r = b = -K^{-1} v, x = 0, accumulate <b, b>_K and |G P|^2 = |v|^2/|xi|^2
+//   Z_PROJ: x = K^{-1} v
+template <typename T, typename TU, int MODE>
+__device__ __forceinline__ void z_epilogue(const ZArgs<T, TU>& a, long long m, int z, const cpx<T>* vv, double& s1,
+                                           double& s2) {
+    using C = cpx<T>;
+    using CU = cpx<TU>;
+    const long long M = (long long)a.g.n2 * a.g.nh;
+    const Freq f = freq_at(a.g, m, z);
+    const long long idx = (long long)z * M + m;
+    C w[3];
+    if (f.zero) {
+        w[0] = w[1] = w[2] = mk<T>(0, 0);
+    } else {
+        kinv(f, T(a.mu0), T(a.kappa0), vv, w);
+    }
+    if (MODE == Z_CG) {
+        const T sc = T(a.inv_n);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            CU qi;
+            qi.x = TU(w[i].x * sc);
+            qi.y = TU(w[i].y * sc);
+            a.q[i * a.g.nspec + idx] = qi;
+            if (!f.zero) {
+                const CU pi = a.p[i * a.g.nspec + idx];
+                s1 += f.w * (double(pi.x) * double(vv[i].x) + double(pi.y) * double(vv[i].y)) * a.inv_n;
+            }
+        }
+    } else if (MODE == Z_RHS) {
+        CU b[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            b[i].x = TU(-w[i].x);
+            b[i].y = TU(-w[i].y);
+            a.r[i * a.g.nspec + idx] = b[i];
+            a.x[i * a.g.nspec + idx] = CU{TU(0), TU(0)};
+        }
+        if (!f.zero) {
+            double kr[3], ki[3];
+            kmul(f, a.mu0, a.kappa0, b, kr, ki);
+            double bb = 0.0, vv2 = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                bb += double(b[i].x) * kr[i] + double(b[i].y) * ki[i];
+                vv2 += double(vv[i].x) * double(vv[i].x) + double(vv[i].y) * double(vv[i].y);
+            }
+            s1 += f.w * bb;
+            s2 += f.w * vv2 / f.s;
+        }
+    } else {  // Z_PROJ
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            CU o;
+            o.x = TU(w[i].x);
+            o.y = TU(w[i].y);
+            a.x[i * a.g.nspec + idx] = o;
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void z_load(const cpx<T>* in, const Grid& g, cpx<T>* buf, int comp, long long m0, int TX) {
     const long long M = (long long)g.n2 * g.nh;
@@ -487,7 +708,6 @@ __global__ void __launch_bounds__(kBlock) k_zpass_fwd(ZArgs<T, TU> a) {
         __syncthreads();
     }
     double s1 = 0.0, s2 = 0.0;
-    const T mu0 = T(a.mu0), kappa0 = T(a.kappa0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int e = threadIdx.x + q * kBlock;
@@ -495,58 +715,8 @@ __global__ void __launch_bounds__(kBlock) k_zpass_fwd(ZArgs<T, TU> a) {
         const int z = e / TX, t = e - z * TX;
         const long long m = m0 + t;
         if (m >= M) continue;
-        const Freq f = freq_at(a.g, m, z);
-        const long long idx = (long long)z * M + m;
         C vv[3] = {v[0][q], v[1][q], v[2][q]};
-        C w[3];
-        if (f.zero) {
-            w[0] = w[1] = w[2] = mk<T>(0, 0);
-        } else {
-            kinv(f, mu0, kappa0, vv, w);
-        }
-        if (MODE == Z_CG) {
-            const T sc = T(a.inv_n);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                CU qi;
-                qi.x = TU(w[i].x * sc);
-                qi.y = TU(w[i].y * sc);
-                a.q[i * a.g.nspec + idx] = qi;
-                if (!f.zero) {
-                    const CU pi = a.p[i * a.g.nspec + idx];
-                    s1 += f.w * (double(pi.x) * double(vv[i].x) + double(pi.y) * double(vv[i].y)) * a.inv_n;
-                }
-            }
-        } else if (MODE == Z_RHS) {
-            CU b[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                b[i].x = TU(-w[i].x);
-                b[i].y = TU(-w[i].y);
-                a.r[i * a.g.nspec + idx] = b[i];
-                a.x[i * a.g.nspec + idx] = CU{TU(0), TU(0)};
-            }
-            if (!f.zero) {
-                double kr[3], ki[3];
-                kmul(f, a.mu0, a.kappa0, b, kr, ki);
-                double bb = 0.0, vv2 = 0.0;
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    bb += double(b[i].x) * kr[i] + double(b[i].y) * ki[i];
-                    vv2 += double(vv[i].x) * double(vv[i].x) + double(vv[i].y) * double(vv[i].y);
-                }
-                s1 += f.w * bb;
-                s2 += f.w * vv2 / f.s;
-            }
-        } else {  // Z_PROJ
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                CU o;
-                o.x = TU(w[i].x);
-                o.y = TU(w[i].y);
-                a.x[i * a.g.nspec + idx] = o;
-            }
-        }
+        z_epilogue<T, TU, MODE>(a, m, z, vv, s1, s2);
     }
     if (MODE == Z_CG || MODE == Z_RHS) {
         const double t1 = block_sum(s1, red);
@@ -599,8 +769,8 @@ __global__ void __launch_bounds__(kBlock) k_zpass_inv(ZArgs<T, TU> a) {
                             pn = ri;
                         } else {
                             const CU pi = a.p[idx];
-                            pn.x = TU(double(ri.x) + beta * double(pi.x));
-                            pn.y = TU(double(ri.y) + beta * double(pi.y));
+                            pn.x = ri.x + TU(beta) * pi.x;
+                            pn.y = ri.y + TU(beta) * pi.y;
                         }
                         a.p[idx] = pn;
                         u[q] = mk<T>(T(pn.x), T(pn.y));
@@ -670,10 +840,11 @@ __device__ __forceinline__ double cg_update_one(const UArgs<TU>& a, long long id
         const CU pi = a.p[o];
         CU ri = a.r[o];
         const CU qi = a.q[o];
-        xi.x = TU(double(xi.x) + alpha * double(pi.x));
-        xi.y = TU(double(xi.y) + alpha * double(pi.y));
-        ri.x = TU(double(ri.x) - alpha * double(qi.x));
-        ri.y = TU(double(ri.y) - alpha * double(qi.y));
+        const TU al = TU(alpha);   // vector arithmetic in the precision of the CG vectors
+        xi.x += al * pi.x;
+        xi.y += al * pi.y;
+        ri.x -= al * qi.x;
+        ri.y -= al * qi.y;
         a.x[o] = xi;
         rr[i] = ri;
     }
@@ -826,9 +997,320 @@ __global__ void __launch_bounds__(kBlock) k_reduce_columns(const double* partial
 }
 
 // ------------------------------------------------------------------------------
+// Two-stage register FFT versions of the y and z passes (fft_reg.h): each 1D
+// transform is one size-Q DFT per thread straight from global memory, one LDS
+// exchange and one size-P DFT per thread, so a component costs two barriers.
+// ------------------------------------------------------------------------------
+template <int P, int Q, int TX>
+constexpr int fft2_threads() { return TX * (P > Q ? P : Q); }
+
+template <int P, int Q, int TX, typename T>
+__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_fwd(YArgs<T> a) {
+    using C = cpx<T>;
+    using F = Fft2<P, Q, TX>;
+    constexpr int L = P * Q;
+    if (a.st && a.st->done) return;
+    __shared__ C ex[F::exch_elems()];
+    __shared__ C tw[L];
+    const int tid = threadIdx.x;
+    const int z = blockIdx.x / a.ntile, kx0 = (blockIdx.x % a.ntile) * TX;
+    const int nh = a.g.nh;
+    const long long zoff = (long long)z * L * nh;
+    for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
+    const bool hasA = tid < F::NA, hasB = tid < F::NB;
+    const int tA = tid % TX, j1 = tid / TX, tB = tid % TX, k1 = tid / TX;
+    const bool colA = kx0 + tA < nh, colB = kx0 + tB < nh;
+    const T xs2 = T(a.g.xs2);
+    __syncthreads();
+    C acc[P];
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll 1
+        for (int sub = 0; sub < 3; ++sub) {
+            const int c = 3 * i + sub;
+            if (hasA) {
+                C x[Q];
+                const C* src = a.in + c * a.g.nspec + zoff + kx0;   // uniform
+#pragma unroll
+                for (int j2 = 0; j2 < Q; ++j2) x[j2] = colA ? src[tA + (j1 + P * j2) * nh] : mk<T>(0, 0);
+                fft2_stageA<P, Q, TX, -1, T>(x, tA, j1, ex, tw);
+            }
+            __syncthreads();
+            if (hasB) {
+                C y[P];
+                fft2_stageB<P, Q, TX, -1, T>(y, tB, k1, ex);
+                if (sub == 0) {
+#pragma unroll
+                    for (int k2 = 0; k2 < P; ++k2) acc[k2] = y[k2];
+                } else if (colB) {
+                    const int oc = (sub == 1) ? i : 3 + i;
+                    C* dst = a.out + oc * a.g.nspec + zoff + kx0;   // uniform
+#pragma unroll
+                    for (int k2 = 0; k2 < P; ++k2) {
+                        const int ky = k1 + Q * k2;
+                        C v = y[k2];
+                        if (sub == 1) v = cadd(acc[k2], cscale(v, xs2 * T(freq_of(ky, L))));
+                        dst[tB + ky * nh] = v;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int P, int Q, int TX, typename T>
+__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_inv(YArgs<T> a) {
+    using C = cpx<T>;
+    using F = Fft2<P, Q, TX>;
+    constexpr int L = P * Q;
+    if (a.st && a.st->done) return;
+    __shared__ C ex[F::exch_elems()];
+    __shared__ C tw[L];
+    const int tid = threadIdx.x;
+    const int z = blockIdx.x / a.ntile, kx0 = (blockIdx.x % a.ntile) * TX;
+    const int nh = a.g.nh;
+    const long long zoff = (long long)z * L * nh;
+    for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
+    const bool hasA = tid < F::NA, hasB = tid < F::NB;
+    const int tA = tid % TX, j1 = tid / TX, tB = tid % TX, k1 = tid / TX;
+    const bool colA = kx0 + tA < nh, colB = kx0 + tB < nh;
+    const T xs2 = T(a.g.xs2);
+    __syncthreads();
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll 1
+        for (int sub = 0; sub < 3; ++sub) {
+            // sub 0: A_i, sub 1: xi_2 A_i (A_i re-read, normally from L2), sub 2: B_i
+            if (hasA) {
+                C x[Q];
+                const C* src = a.in + (sub == 2 ? 3 + i : i) * a.g.nspec + zoff + kx0;   // uniform
+#pragma unroll
+                for (int j2 = 0; j2 < Q; ++j2) {
+                    const int y = j1 + P * j2;
+                    C v = colA ? src[tA + y * nh] : mk<T>(0, 0);
+                    x[j2] = (sub == 1) ? cscale(v, xs2 * T(freq_of(y, L))) : v;
+                }
+                fft2_stageA<P, Q, TX, +1, T>(x, tA, j1, ex, tw);
+            }
+            __syncthreads();
+            if (hasB && colB) {
+                C y[P];
+                fft2_stageB<P, Q, TX, +1, T>(y, tB, k1, ex);
+                C* dst = a.out + (3 * i + sub) * a.g.nspec + zoff + kx0;   // uniform
+#pragma unroll
+                for (int k2 = 0; k2 < P; ++k2) dst[tB + (k1 + Q * k2) * nh] = y[k2];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int P, int Q, int TX, typename T, typename TU, int MODE>
+__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_fwd(ZArgs<T, TU> a) {
+    using C = cpx<T>;
+    using F = Fft2<P, Q, TX>;
+    constexpr int L = P * Q;
+    if (MODE == Z_CG && a.st->done) return;
+    __shared__ C ex[F::exch_elems()];
+    __shared__ C tw[L];
+    __shared__ double red[16];
+    const int tid = threadIdx.x;
+    const long long M = (long long)a.g.n2 * a.g.nh;
+    const long long m0 = (long long)blockIdx.x * TX;
+    for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
+    const bool hasA = tid < F::NA, hasB = tid < F::NB;
+    const int tA = tid % TX, j1 = tid / TX, tB = tid % TX, k1 = tid / TX;
+    const bool colA = m0 + tA < M, colB = m0 + tB < M;
+    const T xs3 = T(a.g.xs3);
+    __syncthreads();
+    C v[3][P];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll 1
+        for (int sub = 0; sub < 2; ++sub) {
+            const int c = sub ? 3 + i : i;
+            if (hasA) {
+                C x[Q];
+                const C* src = a.in + c * a.g.nspec + m0;   // uniform
+                const int Mi = (int)M;
+#pragma unroll
+                for (int j2 = 0; j2 < Q; ++j2) x[j2] = colA ? src[tA + (j1 + P * j2) * Mi] : mk<T>(0, 0);
+                fft2_stageA<P, Q, TX, -1, T>(x, tA, j1, ex, tw);
+            }
+            __syncthreads();
+            if (hasB) {
+                C y[P];
+                fft2_stageB<P, Q, TX, -1, T>(y, tB, k1, ex);
+#pragma unroll
+                for (int k2 = 0; k2 < P; ++k2) {
+                    if (sub == 0) v[i][k2] = y[k2];
+                    else v[i][k2] = cadd(v[i][k2], cscale(y[k2], xs3 * T(freq_of(k1 + Q * k2, L))));
+                }
+            }
+            __syncthreads();
+        }
+    }
+    double s1 = 0.0, s2 = 0.0;
+    if (hasB && colB) {
+#pragma unroll
+        for (int k2 = 0; k2 < P; ++k2) {
+            C vv[3] = {v[0][k2], v[1][k2], v[2][k2]};
+            z_epilogue<T, TU, MODE>(a, m0 + tB, k1 + Q * k2, vv, s1, s2);
+        }
+    }
+    if (MODE == Z_CG || MODE == Z_RHS) {
+        const double t1 = block_sum(s1, red);
+        if (tid == 0) a.partials[blockIdx.x] = t1;
+    }
+    if (MODE == Z_RHS) {
+        const double t2 = block_sum(s2, red);
+        if (tid == 0) a.partials2[blockIdx.x] = t2;
+    }
+}
+
+template <int P, int Q, int TX, typename T, typename TU, int MODE>
+__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_inv(ZArgs<T, TU> a) {
+    using C = cpx<T>;
+    using CU = cpx<TU>;
+    using F = Fft2<P, Q, TX>;
+    constexpr int L = P * Q;
+    if (MODE == Z_INV_CG && a.st->done) return;
+    __shared__ C ex[F::exch_elems()];
+    __shared__ C tw[L];
+    const int tid = threadIdx.x;
+    const long long M = (long long)a.g.n2 * a.g.nh;
+    const long long m0 = (long long)blockIdx.x * TX;
+    for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
+    const bool hasA = tid < F::NA, hasB = tid < F::NB;
+    const int tA = tid % TX, j1 = tid / TX, tB = tid % TX, k1 = tid / TX;
+    const bool colA = m0 + tA < M, colB = m0 + tB < M;
+    const T xs3 = T(a.g.xs3);
+    double beta = 0.0;
+    bool first = true;
+    if (MODE == Z_INV_CG) {
+        beta = a.st->beta;
+        first = (a.st->iter == 0);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int i = 0; i < 3; ++i) {
+        // u_i is read once (CG mode: p = r + beta p, written back) and kept for the xi_3 u_i transform
+        C u[Q];
+        if (hasA) {
+            const long long base = i * a.g.nspec + m0;   // uniform
+            CU* pb = a.p + base;
+            const CU* rb = a.r + base;
+            const CU* xb = a.x + base;
+            const int Mi = (int)M;
+#pragma unroll
+            for (int j2 = 0; j2 < Q; ++j2) {
+                u[j2] = mk<T>(0, 0);
+                if (!colA) continue;
+                const int off = tA + (j1 + P * j2) * Mi;
+                if (MODE == Z_INV_CG) {
+                    const CU ri = rb[off];
+                    CU pn;
+                    if (first) {
+                        pn = ri;
+                    } else {
+                        const CU pi = pb[off];
+                        pn.x = ri.x + TU(beta) * pi.x;
+                        pn.y = ri.y + TU(beta) * pi.y;
+                    }
+                    pb[off] = pn;
+                    u[j2] = mk<T>(T(pn.x), T(pn.y));
+                } else {
+                    const CU xi = xb[off];
+                    u[j2] = mk<T>(T(xi.x), T(xi.y));
+                }
+            }
+        }
+#pragma unroll 1
+        for (int sub = 0; sub < 2; ++sub) {
+            if (hasA) {
+                C x[Q];
+#pragma unroll
+                for (int j2 = 0; j2 < Q; ++j2) x[j2] = sub ? cscale(u[j2], xs3 * T(freq_of(j1 + P * j2, L))) : u[j2];
+                fft2_stageA<P, Q, TX, +1, T>(x, tA, j1, ex, tw);
+            }
+            __syncthreads();
+            if (hasB && colB) {
+                C y[P];
+                fft2_stageB<P, Q, TX, +1, T>(y, tB, k1, ex);
+                C* dst = a.out + (sub ? 3 + i : i) * a.g.nspec + m0;   // uniform
+                const int Mi = (int)M;
+#pragma unroll
+                for (int k2 = 0; k2 < P; ++k2) dst[tB + (k1 + Q * k2) * Mi] = y[k2];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Supported fast-path lengths: (P, Q, TX) per precision; TX keeps the exchange
+// buffer near 35 KB so four workgroups fit in the 160 KB LDS of a CU.
+#define COMBO_FFT2_CONFIGS(X)        \
+    X(float, 256, 16, 16, 16)        \
+    X(float, 128, 8, 16, 16)         \
+    X(float, 64, 8, 8, 32)           \
+    X(float, 32, 4, 8, 32)           \
+    X(double, 256, 16, 16, 8)        \
+    X(double, 128, 8, 16, 8)         \
+    X(double, 64, 8, 8, 16)          \
+    X(double, 32, 4, 8, 16)
+
+template <typename T>
+int fft2_tx(int L) {
+#define COMBO_TX_CASE(TT, LL, PP, QQ, TXX) \
+    if (std::is_same<T, TT>::value && L == LL) return TXX;
+    COMBO_FFT2_CONFIGS(COMBO_TX_CASE)
+#undef COMBO_TX_CASE
+    return 0;
+}
+
+template <typename T>
+int y_tile(const Grid& g) {
+    const int tx = fft2_tx<T>(g.n2);
+    if (tx) return tx;
+    return std::max(1, std::min(g.nh, max_elems<T>() / g.n2));
+}
+
+template <typename T>
+int z_tile(const Grid& g) {
+    const int tx = fft2_tx<T>(g.n3);
+    if (tx) return tx;
+    return (int)std::max<long long>(1, std::min<long long>((long long)g.n2 * g.nh, max_elems<T>() / g.n3));
+}
+
+template int y_tile<float>(const Grid&);
+template int y_tile<double>(const Grid&);
+template int z_tile<float>(const Grid&);
+template int z_tile<double>(const Grid&);
+
+// ------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------
-int blocks_x(const Grid& g, int R) { return (int)(((long long)g.n2 * g.n3 + R - 1) / R); }
+void xpass_wave_shape(int n1, int& m, int& w) {
+    m = w = 0;
+#define COMBO_XS_CASE(LL, MM, WW) \
+    if (n1 == LL) {                \
+        m = MM;                    \
+        w = WW;                    \
+        return;                    \
+    }
+    COMBO_XWAVE_CONFIGS(COMBO_XS_CASE)
+#undef COMBO_XS_CASE
+}
+
+int blocks_x(const Grid& g, int R) {
+    const long long nrows = (long long)g.n2 * g.n3;
+#define COMBO_XB_CASE(LL, MM, WW) \
+    if (g.n1 == LL) return (int)((nrows + (256 / WW) - 1) / (256 / WW));
+    COMBO_XWAVE_CONFIGS(COMBO_XB_CASE)
+#undef COMBO_XB_CASE
+    return (int)((nrows + R - 1) / R);
+}
 int blocks_y(const Grid& g, int TX) { return g.n3 * ((g.nh + TX - 1) / TX); }
 int blocks_z(const Grid& g, int TX) { return (int)(((long long)g.n2 * g.nh + TX - 1) / TX); }
 int blocks_u(const Grid& g) {
@@ -838,6 +1320,22 @@ int blocks_u(const Grid& g) {
 
 template <typename T>
 hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb) {
+    const long long nrows = (long long)a.g.n2 * a.g.n3;
+#define COMBO_XW_CASE(LL, MM, WW)                                                                             \
+    if (a.g.n1 == LL) {                                                                                     \
+        const int nblk = (int)((nrows + (256 / WW) - 1) / (256 / WW));                                       \
+        if (nb) *nb = nblk;                                                                                  \
+        switch (mode) {                                                                                      \
+            case X_CG: hipLaunchKernelGGL((k_xwave<T, X_CG, MM, WW>), dim3(nblk), dim3(256), 0, s, a); break;   \
+            case X_RHS_E: hipLaunchKernelGGL((k_xwave<T, X_RHS_E, MM, WW>), dim3(nblk), dim3(256), 0, s, a); break; \
+            case X_AVG: hipLaunchKernelGGL((k_xwave<T, X_AVG, MM, WW>), dim3(nblk), dim3(256), 0, s, a); break; \
+            case X_FWD_REAL: hipLaunchKernelGGL((k_xwave<T, X_FWD_REAL, MM, WW>), dim3(nblk), dim3(256), 0, s, a); break; \
+            default: hipLaunchKernelGGL((k_xwave<T, X_INV_REAL, MM, WW>), dim3(nblk), dim3(256), 0, s, a); break; \
+        }                                                                                                    \
+        return hipGetLastError();                                                                            \
+    }
+    COMBO_XWAVE_CONFIGS(COMBO_XW_CASE)
+#undef COMBO_XW_CASE
     const int nblk = blocks_x(a.g, a.R);
     if (nb) *nb = nblk;
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n1 + (size_t)5 * a.R * a.g.n1);
@@ -852,8 +1350,22 @@ hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb) {
 }
 
 template <typename T>
-hipError_t launch_y(int dir, const YArgs<T>& a, hipStream_t s) {
+hipError_t launch_y(int dir, const YArgs<T>& a0, hipStream_t s) {
+    YArgs<T> a = a0;
+    a.TX = y_tile<T>(a.g);
+    a.ntile = (a.g.nh + a.TX - 1) / a.TX;
     const int nblk = a.g.n3 * a.ntile;
+#define COMBO_Y_CASE(TT, LL, PP, QQ, TXX)                                                                       \
+    if constexpr (std::is_same<T, TT>::value) {                                                               \
+        if (a.g.n2 == LL) {                                                                                    \
+            constexpr int nt = fft2_threads<PP, QQ, TXX>();                                                    \
+            if (dir < 0) hipLaunchKernelGGL((k_y2_fwd<PP, QQ, TXX, T>), dim3(nblk), dim3(nt), 0, s, a);        \
+            else hipLaunchKernelGGL((k_y2_inv<PP, QQ, TXX, T>), dim3(nblk), dim3(nt), 0, s, a);                \
+            return hipGetLastError();                                                                          \
+        }                                                                                                      \
+    }
+    COMBO_FFT2_CONFIGS(COMBO_Y_CASE)
+#undef COMBO_Y_CASE
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n2 + (size_t)a.g.n2 * a.TX);
     if (dir < 0) hipLaunchKernelGGL(k_ypass_fwd<T>, dim3(nblk), dim3(kBlock), lds, s, a);
     else hipLaunchKernelGGL(k_ypass_inv<T>, dim3(nblk), dim3(kBlock), lds, s, a);
@@ -861,9 +1373,27 @@ hipError_t launch_y(int dir, const YArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T, typename TU>
-hipError_t launch_z(int mode, const ZArgs<T, TU>& a, hipStream_t s, int* nb) {
+hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb) {
+    ZArgs<T, TU> a = a0;
+    a.TX = z_tile<T>(a.g);
     const int nblk = blocks_z(a.g, a.TX);
     if (nb) *nb = nblk;
+#define COMBO_Z_CASE(TT, LL, PP, QQ, TXX)                                                                      \
+    if constexpr (std::is_same<T, TT>::value) {                                                              \
+        if (a.g.n3 == LL) {                                                                                   \
+            constexpr int nt = fft2_threads<PP, QQ, TXX>();                                                   \
+            switch (mode) {                                                                                   \
+                case Z_CG: hipLaunchKernelGGL((k_z2_fwd<PP, QQ, TXX, T, TU, Z_CG>), dim3(nblk), dim3(nt), 0, s, a); break; \
+                case Z_RHS: hipLaunchKernelGGL((k_z2_fwd<PP, QQ, TXX, T, TU, Z_RHS>), dim3(nblk), dim3(nt), 0, s, a); break; \
+                case Z_PROJ: hipLaunchKernelGGL((k_z2_fwd<PP, QQ, TXX, T, TU, Z_PROJ>), dim3(nblk), dim3(nt), 0, s, a); break; \
+                case Z_INV_CG: hipLaunchKernelGGL((k_z2_inv<PP, QQ, TXX, T, TU, Z_INV_CG>), dim3(nblk), dim3(nt), 0, s, a); break; \
+                default: hipLaunchKernelGGL((k_z2_inv<PP, QQ, TXX, T, TU, Z_INV_PLAIN>), dim3(nblk), dim3(nt), 0, s, a); break; \
+            }                                                                                                 \
+            return hipGetLastError();                                                                         \
+        }                                                                                                     \
+    }
+    COMBO_FFT2_CONFIGS(COMBO_Z_CASE)
+#undef COMBO_Z_CASE
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n3 + (size_t)a.g.n3 * a.TX);
     switch (mode) {
         case Z_CG: hipLaunchKernelGGL((k_zpass_fwd<T, TU, Z_CG>), dim3(nblk), dim3(kBlock), lds, s, a); break;

@@ -23,6 +23,7 @@ struct CGState {
 // Tangent state of the pointwise law in the precision T of the linear solves.
 template <typename T>
 struct TangentState {
+    // all three arrays are indexed by state_pos(voxel)
     const int* slot;    // [n]: -1 matrix, -2 inclusion, >= 0 index of a composite voxel
     const T* Sinv;      // [9][n] F^{-1} of pure voxels (row-major)
     const T* sm;        // [n] mu - lambda ln J of pure voxels
@@ -121,6 +122,13 @@ enum FinMode { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RHS = 2 };
 hipError_t launch_finalize(int mode, CGState* st, const double* partials, const double* partials2, int count,
                            hipStream_t s, double tol2 = 0.0, int maxit = 0);
 hipError_t launch_reduce_columns(const double* partials, int rows, int cols, double* out, hipStream_t s);
+
+// tile widths the y and z launchers use (two-stage fast path or LDS Stockham)
+template <typename T> int y_tile(const Grid& g);
+template <typename T> int z_tile(const Grid& g);
+
+// (m, W) of the wavefront x pass for a row length n1; m = W = 0 if it has none
+void xpass_wave_shape(int n1, int& m, int& w);
 
 int blocks_x(const Grid& g, int R);
 int blocks_y(const Grid& g, int TX);

@@ -24,8 +24,9 @@ struct MatArgs {
     double* a_out;          // [3][nc]
     int warm;
     int maxit;
-    T* Sinv;                // [9][n] tangent state (null: not wanted)
+    T* Sinv;                // [9][n] tangent state at state_pos(voxel) (null: not wanted)
     T* sm;                  // [n]
+    int n1, xm, xwbits;     // state layout (see state_pos)
     T* Acomp;               // [nc][45]
     double* A_full;         // [81][n] full FP64 tangent (diagnostics) or null
     double* a_full;         // [3][n] jump vector per voxel (diagnostics) or null

@@ -123,9 +123,10 @@ __global__ void __launch_bounds__(256) k_material_pure(MatArgs<T> a) {
             sums[9 * ph + c] += P[c];
         }
         if (a.Sinv) {
+            const long long sp = state_pos(vox, a.n1, a.xm, a.xwbits);
 #pragma unroll
-            for (int c = 0; c < 9; ++c) a.Sinv[c * a.n + vox] = T(Finv[c]);
-            a.sm[vox] = T(m);
+            for (int c = 0; c < 9; ++c) a.Sinv[c * a.n + sp] = T(Finv[c]);
+            a.sm[sp] = T(m);
         }
         if (a.A_full) {
             for (int r = 0; r < 81; ++r)

@@ -94,8 +94,8 @@ template <typename T> PassShape shape_for(const combo_ctx* c) {
     PassShape s;
     s.xR = std::max(1, maxE / (5 * c->g.n1));
     s.xR = (int)std::min<long long>(s.xR, (long long)c->g.n2 * c->g.n3);
-    s.yTX = std::max(1, std::min(c->g.nh, maxE / c->g.n2));
-    s.zTX = (int)std::max<long long>(1, std::min<long long>((long long)c->g.n2 * c->g.nh, maxE / c->g.n3));
+    s.yTX = y_tile<T>(c->g);
+    s.zTX = z_tile<T>(c->g);
     return s;
 }
 
@@ -247,7 +247,7 @@ void reference_medium(const combo_ctx* ctx, double& mu0, double& kappa0) {
 template <typename T>
 TangentState<T> tangent_state(const combo_ctx* ctx) {
     TangentState<T> ts{};
-    ts.slot = ctx->slot.as<int>();
+    ts.slot = ctx->slot_s.as<int>();
     ts.Sinv = ctx->Sinv.as<T>();
     ts.sm = ctx->sm.as<T>();
     ts.Acomp = ctx->Acomp.as<T>();
@@ -334,6 +334,9 @@ int material(combo_ctx* ctx, const double* F_old, const double* dF, double s, co
     m.maxit = ctx->opt.max_laminate;
     m.Sinv = ctx->Sinv.as<T>();
     m.sm = ctx->sm.as<T>();
+    m.n1 = ctx->g.n1;
+    m.xm = ctx->g.xm;
+    m.xwbits = ctx->g.xwbits;
     m.Acomp = ctx->Acomp.as<T>();
     m.A_full = A_full;
     m.a_full = a_full;
@@ -856,6 +859,15 @@ int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2,
     ctx->g.xs1 = twopi / l1;
     ctx->g.xs2 = twopi / l2;
     ctx->g.xs3 = twopi / l3;
+    int xm = 0, xw = 0;
+    xpass_wave_shape(n1, xm, xw);
+    ctx->g.xm = xm;
+    ctx->g.xwbits = -1;
+    if (xw > 0) {
+        int b = 0;
+        while ((1 << b) < xw) ++b;
+        ctx->g.xwbits = b;
+    }
     ctx->l[0] = l1;
     ctx->l[1] = l2;
     ctx->l[2] = l3;
@@ -967,6 +979,10 @@ int combo_set_microstructure(combo_ctx* ctx, const uint8_t* phase, const double*
     ctx->n_mat = nm;
     ctx->n_incl = ni;
     ctx->sum_c = sc;
+    std::vector<int> slot_s(n);
+    for (long long v = 0; v < n; ++v) slot_s[state_pos(v, ctx->g.n1, ctx->g.xm, ctx->g.xwbits)] = slot[v];
+    HIP_OR_FAIL(ctx->slot_s.ensure(sizeof(int) * n));
+    HIP_OR_FAIL(hipMemcpy(ctx->slot_s.p, slot_s.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     HIP_OR_FAIL(ctx->slot.ensure(sizeof(int) * n));
     HIP_OR_FAIL(ctx->comp_vox.ensure(sizeof(int) * std::max(nc, 1)));
     HIP_OR_FAIL(ctx->comp_c.ensure(sizeof(double) * std::max(nc, 1)));

@@ -114,7 +114,11 @@ def test_law_backprojection_cases_match_oracle(ctx):
 # ---------------------------------------------------------------------------------
 @pytest.mark.parametrize("n,l", [((16, 16, 16), (1.0, 1.0, 1.0)), ((9, 6, 12), (2.0, 0.5, 1.3)),
                                  ((48, 18, 27), (1.0, 1.0, 2.0)), ((2, 1, 3), (1.0, 1.0, 1.0)),
-                                 ((96, 8, 4), (1.0, 0.3, 0.3))])
+                                 ((96, 8, 4), (1.0, 0.3, 0.3)), ((256, 6, 3), (2.0, 0.5, 0.25)),
+                                 ((128, 32, 4), (1.0, 1.0, 1.0)), ((64, 64, 32), (1.0, 0.7, 1.0)),
+                                 ((9, 256, 2), (1.0, 1.0, 1.0)), ((6, 4, 256), (0.5, 1.0, 3.0)),
+                                 ((12, 128, 64), (1.0, 1.0, 1.0)), ((384, 2, 2), (1.0, 1.0, 1.0)),
+                                 ((192, 3, 2), (1.0, 1.0, 1.0))])
 @pytest.mark.parametrize("which", [combo.COMBO_GREEN_GAMMA0, combo.COMBO_GREEN_G])
 def test_green_operators_match_oracle(ctx, n, l, which):
     rng = np.random.default_rng(11)
@@ -133,9 +137,9 @@ def test_green_operators_match_oracle(ctx, n, l, which):
     assert rel(out32, ref) <= 2e-6
 
 
+@pytest.mark.parametrize("n", [(12, 9, 8), (64, 32, 16), (256, 4, 8), (48, 64, 32)])
 @pytest.mark.parametrize("precision,tol", [(combo.COMBO_FP64, 1e-11), (combo.COMBO_MIXED, 3e-6)])
-def test_cg_operator_matches_oracle(ctx, precision, tol):
-    n = (12, 9, 8)
+def test_cg_operator_matches_oracle(ctx, precision, tol, n):
     ms = synth.random_composite_field(n, 5, frac_composite=0.3)
     setup(ctx, ms, precision=precision)
     F = synth.random_F_field(n, 6, amplitude=0.15)
