@@ -68,7 +68,7 @@ def cpu_baseline(ms, lc, sub=128, iters=3):
     t0, c0 = time.perf_counter(), time.process_time()
     try:
         osol.cg(Av, b, prob, mu0, kappa0, 1e-30, iters)
-    except osol.SolveError:
+    except (osol.SolveError, osol.NegativeCurvature):
         pass
     wall, cpu = time.perf_counter() - t0, time.process_time() - c0
     nv = sub ** 3

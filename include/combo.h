@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define COMBO_ABI_VERSION 1
+#define COMBO_ABI_VERSION 2
 
 typedef struct combo_ctx combo_ctx;
 typedef struct combo_batch combo_batch;
@@ -119,6 +119,7 @@ typedef struct {
     double time_ms_material;
     double time_ms_residual;
     double time_ms_tangent;
+    int cg_truncations;       /* Newton steps whose CG stopped at negative curvature (truncated Newton) */
 } combo_stats;
 
 /* Library identification and messages ------------------------------------ */
@@ -205,6 +206,51 @@ enum combo_kernel {
 int combo_profile_enable(combo_ctx* ctx, int enable);
 /* Accumulated milliseconds and number of timed launches of one kernel class. */
 int combo_profile_read(combo_ctx* ctx, int kernel, double* ms_total, long long* launches);
+
+/* Batches of RVEs -----------------------------------------------------------
+ * Many independent RVEs, each with its own grid, box, materials and
+ * microstructure, solved together on one GPU (the many-RVE workloads of
+ * multiscale FE^2-type use, paper Sec. 1).  Every pass of the solve runs as
+ * one launch over all members that share its kernel shape (axis length),
+ * each workgroup reading its member's arguments from a device table; every
+ * member keeps its own Newton, step-control and CG progress, and a member
+ * whose CG has finished leaves the launches of the others at once.  Member i
+ * solved in a batch follows the steps of combo_solve on a context with the
+ * same data and options, F_init = NULL and n_increments[i] increments; the
+ * batched kernels are separately compiled instances of the same code, so the
+ * results agree to rounding (the compiler may fuse multiply-adds differently). */
+/* Create an empty batch on GPU `device` using `hip_stream` (NULL = a stream the
+ * batch creates and owns).  COMBO_E_HIP if no usable GPU. */
+int combo_batch_create(combo_batch** out, int device, void* hip_stream);
+/* Frees every member and all device memory of the batch. */
+int combo_batch_destroy(combo_batch* b);
+/* Message of the last failed call on b (member failures name the member). */
+const char* combo_batch_last_error(const combo_batch* b);
+/* Options of every member (validated as combo_set_options; graph_chunk is ignored). */
+int combo_batch_set_options(combo_batch* b, const combo_options* opt);
+/* Append one RVE: grid and box as combo_set_grid, materials as
+ * combo_set_materials, microstructure as combo_set_microstructure (pointers of
+ * mem_kind, copied).  *index (may be NULL) receives the member's position.
+ * On failure nothing is appended. */
+int combo_batch_add(combo_batch* b, int n1, int n2, int n3, double l1, double l2, double l3,
+                    const combo_material mats[2], const uint8_t* phase, const double* c, const double* N,
+                    int mem_kind, int* index);
+/* Number of members (0 for NULL). */
+int combo_batch_size(const combo_batch* b);
+/* Solve every member i from F = I to the macroscopic deformation
+ * Fbar[9 i .. 9 i + 8] in n_increments[i] load increments (n_increments NULL:
+ * the options' value).  Host arrays over the members, each may be NULL except
+ * Fbar: Pbar [m][9], Abar [m][81] (written when options.want_tangent),
+ * Pbar_phase [m][18] (as combo_solve), stats [m] (time_ms_total is the
+ * batch's wall time; per-phase times are 0).  Returns COMBO_OK if every member
+ * converged, else the status of the first failing member; every member's own
+ * status is in stats[i].status and the outputs of converged members are
+ * written either way. */
+int combo_batch_solve(combo_batch* b, const double* Fbar, const int* n_increments, double* Pbar, double* Abar,
+                      double* Pbar_phase, combo_stats* stats);
+/* Fields of member i after combo_batch_solve: F and P, [9][n_i] each (either
+ * may be NULL), in memory of mem_kind. */
+int combo_batch_fields(combo_batch* b, int i, double* F, double* P, int mem_kind);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,14 @@ Readings where the paper is silent (the GPU solver uses the same ones):
     not depend on it, only iteration counts do;
   * Newton test: eta = |G[P]|_2 / (sqrt(n) |Pbar|_F) <= tol_newton (root mean
     square equilibrium residual relative to the effective stress);
-  * CG test: |r|_C0 / |b|_C0 <= tol_cg; CG breakdown (<p, q> <= 0) is an error;
+  * CG test: |r|_C0 / |b|_C0 <= tol_cg;
+  * negative curvature: far from equilibrium (the homogeneous predictor puts
+    stiff inclusions at the uniform-strain stress) the Neo-Hooke tangent can be
+    indefinite on compatible fields, and CG meets <p, q> <= 0.  The Newton step
+    then takes the CG iterate reached before that direction (truncated Newton);
+    if that is the first CG iteration (no iterate yet), the Newton loop fails
+    and the increment is halved.  A NaN <p, q> stays an error, and so does
+    negative curvature in the effective-tangent solves;
   * load path Fbar_k = Fbar_0 + (k/K)(Fbar - Fbar_0), homogeneous predictor
     F += Fbar_k - Fbar_{k-1};
   * step control: F + s dF with s = 1, halved (at most 10 times) while any
@@ -73,6 +80,15 @@ class Problem:
     @property
     def nvox(self):
         return self.n[0] * self.n[1] * self.n[2]
+
+
+class NegativeCurvature(RuntimeError):
+    """CG met a direction p with <p, Gamma^0[A:p]> <= 0; x is the iterate after `it` iterations."""
+
+    def __init__(self, x, it, gam):
+        super().__init__("CG negative curvature <p, q> = %r after %d iterations" % (gam, it))
+        self.x = x
+        self.it = it
 
 
 class SolveError(RuntimeError):
@@ -175,8 +191,10 @@ def cg(Av, b, prob, mu0, kappa0, tol, maxit):
             raise SolveError(E_NOCONV, "CG did not converge in %d iterations" % maxit)
         q = spectral.apply_gamma0(apply_tangent(Av, p, shape), prob.n, prob.l, mu0, kappa0)
         gam = inner_c0(p, q, mu0, kappa0)
-        if not (gam > 0.0):
+        if gam != gam:
             raise SolveError(E_NUMERIC, "CG breakdown: <p, q> = %r" % gam)
+        if not (gam > 0.0):
+            raise NegativeCurvature(x, it, gam)
         alpha = rho / gam
         x += alpha * p
         r -= alpha * q
@@ -198,7 +216,10 @@ def effective_tangent(F, prob, opts, mu0, kappa0):
         E[kL // 3, kL % 3] = 1.0
         tau = apply_tangent(Av, E, shape)
         b = -spectral.apply_gamma0(tau, prob.n, prob.l, mu0, kappa0)
-        dF, it = cg(Av, b, prob, mu0, kappa0, opts.tol_cg, opts.max_cg)
+        try:
+            dF, it = cg(Av, b, prob, mu0, kappa0, opts.tol_cg, opts.max_cg)
+        except NegativeCurvature as e:
+            raise SolveError(E_NUMERIC, "effective tangent: %s" % e)
         cg_total += it
         Abar[:, kL] = apply_tangent(Av, E + dF, shape).mean(axis=(2, 3, 4)).reshape(9)
     return Abar, cg_total
@@ -238,7 +259,7 @@ def solve(prob, Fbar, opts=None, F_init=None):
     else:
         F = np.array(F_init, float).reshape((3, 3) + tuple(shape))
     Fbar0 = F.mean(axis=(2, 3, 4))
-    stats = dict(newton_iters=0, cg_iters=0, increments=0, step_halvings=0, cutbacks=0,
+    stats = dict(newton_iters=0, cg_iters=0, increments=0, step_halvings=0, cutbacks=0, cg_truncations=0,
                  lam_iters=0, lam_iters_max=0, lam_backproj=0, lam_fail=0, eta=[])
 
     def load(t):
@@ -268,7 +289,14 @@ def solve(prob, Fbar, opts=None, F_init=None):
                     if _ == opts.max_newton:
                         break
                     b = -spectral.apply_gamma0(P, prob.n, prob.l, mu0, kappa0)
-                    dF, it = cg(Av, b, prob, mu0, kappa0, opts.tol_cg, opts.max_cg)
+                    try:
+                        dF, it = cg(Av, b, prob, mu0, kappa0, opts.tol_cg, opts.max_cg)
+                    except NegativeCurvature as e:
+                        dF, it = e.x, e.it
+                        stats["cg_truncations"] += 1
+                        if it == 0:
+                            stats["cg_iters"] += it
+                            break
                     stats["cg_iters"] += it
                     stats["newton_iters"] += 1
                     s = 1.0

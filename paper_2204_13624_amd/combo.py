@@ -74,6 +74,7 @@ class combo_stats(ctypes.Structure):
         ("time_ms_material", ctypes.c_double),
         ("time_ms_residual", ctypes.c_double),
         ("time_ms_tangent", ctypes.c_double),
+        ("cg_truncations", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -102,6 +103,15 @@ _SIGS = {
     "combo_apply_operator": (_I, [_P, _I, _P, _P, _I]),
     "combo_profile_enable": (_I, [_P, _I]),
     "combo_profile_read": (_I, [_P, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
+    "combo_batch_create": (_I, [ctypes.POINTER(_P), _I, _P]),
+    "combo_batch_destroy": (_I, [_P]),
+    "combo_batch_last_error": (ctypes.c_char_p, [_P]),
+    "combo_batch_set_options": (_I, [_P, ctypes.POINTER(combo_options)]),
+    "combo_batch_add": (_I, [_P, _I, _I, _I, _D, _D, _D, ctypes.POINTER(combo_material), _P, _P, _P, _I,
+                             ctypes.POINTER(_I)]),
+    "combo_batch_size": (_I, [_P]),
+    "combo_batch_solve": (_I, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(combo_stats)]),
+    "combo_batch_fields": (_I, [_P, _I, _P, _P, _I]),
 }
 
 KERNEL_NAMES = ["xpass_cg", "ypass_inv", "ypass_fwd", "zpass_inv", "zpass_fwd", "cg_update", "cg_finalize",
@@ -302,6 +312,84 @@ def combo_profile_read(ctx, kernel):
 
 def combo_profile_all(ctx):
     return {name: combo_profile_read(ctx, k) for k, name in enumerate(KERNEL_NAMES)}
+
+
+# ---- batches ---------------------------------------------------------------------
+
+def _bcheck(b, status):
+    if status != COMBO_OK:
+        raise ComboError(status, load_library().combo_batch_last_error(b).decode() if b else "")
+
+
+def _mats_array(mats):
+    arr = (combo_material * 2)()
+    for i in range(2):
+        arr[i].mu, arr[i].lambda_ = float(mats[i][0]), float(mats[i][1])
+    return arr
+
+
+def combo_batch_create(device=0, stream=None):
+    b = ctypes.c_void_p()
+    s = ctypes.c_void_p(stream) if stream else None
+    _bcheck(None, load_library().combo_batch_create(ctypes.byref(b), int(device), s))
+    return b
+
+
+def combo_batch_destroy(b):
+    return load_library().combo_batch_destroy(b)
+
+
+def combo_batch_last_error(b):
+    return load_library().combo_batch_last_error(b).decode()
+
+
+def combo_batch_set_options(b, opts):
+    _bcheck(b, load_library().combo_batch_set_options(b, ctypes.byref(opts)))
+
+
+def combo_batch_add(b, n, l, mats, phase, c, N):
+    """Append one RVE (n = (n1, n2, n3), l = (l1, l2, l3)); returns its index."""
+    pp, k1 = _ptr(phase, np.uint8)
+    cp, k2 = _ptr(c, np.float64)
+    npt, k3 = _ptr(N, np.float64)
+    idx = ctypes.c_int(-1)
+    _bcheck(b, load_library().combo_batch_add(b, int(n[0]), int(n[1]), int(n[2]), float(l[0]), float(l[1]),
+                                              float(l[2]), _mats_array(mats), pp, cp, npt, _mem_kind(k1, k2, k3),
+                                              ctypes.byref(idx)))
+    return idx.value
+
+
+def combo_batch_size(b):
+    return load_library().combo_batch_size(b)
+
+
+def combo_batch_solve(b, Fbar, n_increments=None, want_tangent=False):
+    """Fbar (m, 3, 3); returns dict(status, Pbar (m,3,3), Abar (m,9,9) or None, Pbar_phase (m,2,3,3), stats list)."""
+    m = combo_batch_size(b)
+    fb = np.ascontiguousarray(np.asarray(Fbar, dtype=np.float64).reshape(m, 9))
+    ninc = None
+    if n_increments is not None:
+        ninc = np.ascontiguousarray(np.asarray(n_increments, dtype=np.int32).reshape(m))
+    Pbar = np.zeros((m, 9))
+    Abar = np.zeros((m, 81)) if want_tangent else None
+    Pph = np.zeros((m, 18))
+    stats = (combo_stats * m)()
+    status = load_library().combo_batch_solve(
+        b, fb.ctypes.data, ninc.ctypes.data if ninc is not None else None, Pbar.ctypes.data,
+        Abar.ctypes.data if Abar is not None else None, Pph.ctypes.data, stats)
+    out = dict(status=status, stats=[s.as_dict() for s in stats], Pbar=Pbar.reshape(m, 3, 3),
+               Abar=Abar.reshape(m, 9, 9) if Abar is not None else None, Pbar_phase=Pph.reshape(m, 2, 3, 3))
+    if status != COMBO_OK:
+        err = ComboError(status, combo_batch_last_error(b))
+        err.result = out
+        raise err
+    return out
+
+
+def combo_batch_fields(b, i, F=None, P=None):
+    fp, k1 = _ptr(F, np.float64)
+    pp, k2 = _ptr(P, np.float64)
+    _bcheck(b, load_library().combo_batch_fields(b, int(i), fp, pp, _mem_kind(k1, k2)))
 
 
 # ---- convenience object ----------------------------------------------------------

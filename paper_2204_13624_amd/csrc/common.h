@@ -66,6 +66,22 @@ __host__ __device__ inline long long state_pos(long long vox, int n1, int xm, in
     return row * n1 + l + (1 << xwbits) * s;
 }
 
+// One workgroup of a batched launch: which RVE, which of its tiles, and how many
+// tiles that RVE has in this launch (grid-stride kernels stride by it).
+struct TileMap {
+    int rve;
+    int tile;
+    int ntiles;
+};
+
+// Device-side description of a batched launch: per-RVE argument blocks and the
+// workgroup -> (RVE, tile) map (nblocks entries).  Null pointer = single launch.
+struct BatchLaunch {
+    const void* args;
+    const TileMap* map;
+    int nblocks;
+};
+
 __host__ __device__ inline int freq_of(int j, int n) { return (j < (n + 1) / 2) ? j : j - n; }
 // true if index j is the Nyquist index of an even axis of length n
 __host__ __device__ inline bool is_nyquist(int j, int n) { return (n % 2 == 0) && (j == n / 2) && n > 1; }

@@ -17,14 +17,22 @@ namespace combo {
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool own = true;   // false: a view of memory owned elsewhere (never freed here)
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && own) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        own = true;
+    }
+    void borrow(void* q, size_t nbytes) {
+        release();
+        p = q;
+        bytes = nbytes;
+        own = false;
     }
     hipError_t ensure(size_t nbytes) {
         if (nbytes <= bytes && p) return hipSuccess;
@@ -106,3 +114,21 @@ struct combo_ctx {
     double prof_ms[COMBO_K_COUNT] = {};
     long long prof_n[COMBO_K_COUNT] = {};
 };
+
+// A batch of independent RVEs solved together (each member is a full context
+// sharing the batch's stream; its CG state and sums live in one device array
+// so that one copy brings every member's scalars to the host).
+struct combo_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    combo_options opt{};
+    std::vector<combo_ctx*> members;
+    combo::DevBuf scal;                 // [members] x kScalStride bytes: CGState at 0, sums at kScalSums
+    char* hscal = nullptr;              // pinned host copy of scal
+    size_t hscal_bytes = 0;
+    static constexpr size_t kScalStride = 1024;
+    static constexpr size_t kScalSums = 128;
+};
+

@@ -105,7 +105,7 @@ __device__ __forceinline__ void tangent_apply(const TangentState<T>& ts, long lo
 __device__ __forceinline__ bool xi1_comp(int c) { return c == 0 || c == 3 || c == 6; }
 
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kBlock) k_xpass(XArgs<T> a) {
+__device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     if (MODE == X_CG && a.st->done) return;
     extern __shared__ char smem_raw[];
@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(kBlock) k_xpass(XArgs<T> a) {
     C* buf = tw + L;                   // [5R][L], column-major (each sequence contiguous)
     __shared__ double red[16];
     const long long nrows = (long long)a.g.n2 * a.g.n3;
-    const long long row0 = (long long)blockIdx.x * R;
+    const long long row0 = (long long)tile_ * R;
     const int tid = threadIdx.x;
     const T xs1 = T(a.g.xs1);
     load_twiddles<T>(tw, a.tw, L);
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(kBlock) k_xpass(XArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
             const double t = block_sum(acc[c], red);
-            if (tid == 0) a.partials[(long long)blockIdx.x * 9 + c] = t;
+            if (tid == 0) a.partials[(long long)tile_ * 9 + c] = t;
         }
         return;
     }
@@ -244,6 +244,17 @@ __global__ void __launch_bounds__(kBlock) k_xpass(XArgs<T> a) {
     }
 }
 
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_xpass(XArgs<T> a) {
+    k_xpass_body<T, MODE>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_xpass_b(const XArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_xpass_body<T, MODE>(as[e.rve], e.tile, e.ntiles);
+}
+
 // ------------------------------------------------------------------------------
 // x pass, wavefront version: one grid row (y, z) per group of W lanes, m = n1/W
 // values per lane and sequence, all five packed sequences in registers, no LDS
@@ -252,7 +263,7 @@ __global__ void __launch_bounds__(kBlock) k_xpass(XArgs<T> a) {
 // the forward transform returns to the natural layout for the store.
 // ------------------------------------------------------------------------------
 template <typename T, int MODE, int M, int W>
-__global__ void __launch_bounds__(256) k_xwave(XArgs<T> a) {
+__device__ __forceinline__ void k_xwave_body(const XArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     constexpr int L = M * W;
     constexpr int G = 256 / W;   // rows per workgroup
@@ -260,7 +271,7 @@ __global__ void __launch_bounds__(256) k_xwave(XArgs<T> a) {
     __shared__ double red[16];
     const int lane = threadIdx.x % W;
     const long long nrows = (long long)a.g.n2 * a.g.n3;
-    const long long row = (long long)blockIdx.x * G + threadIdx.x / W;
+    const long long row = (long long)tile_ * G + threadIdx.x / W;
     const bool live = row < nrows;
     const int nh = a.g.nh;
     const T xs1 = T(a.g.xs1);
@@ -356,7 +367,7 @@ __global__ void __launch_bounds__(256) k_xwave(XArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
             const double t = block_sum(acc[c], red);
-            if (threadIdx.x == 0) a.partials[(long long)blockIdx.x * 9 + c] = t;
+            if (threadIdx.x == 0) a.partials[(long long)tile_ * 9 + c] = t;
         }
         return;
     }
@@ -384,6 +395,17 @@ __global__ void __launch_bounds__(256) k_xwave(XArgs<T> a) {
             if (s < 4) a.out[cb * a.g.nspec + off] = hb;
         }
     }
+}
+
+template <typename T, int MODE, int M, int W>
+__global__ void __launch_bounds__(256) k_xwave(XArgs<T> a) {
+    k_xwave_body<T, MODE, M, W>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int MODE, int M, int W>
+__global__ void __launch_bounds__(256) k_xwave_b(const XArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_xwave_body<T, MODE, M, W>(as[e.rve], e.tile, e.ntiles);
 }
 
 // (M, W) of the wavefront x pass for a row length n1, or M = 0 if unsupported
@@ -426,15 +448,15 @@ __device__ __forceinline__ void y_store(const YArgs<T>& a, const cpx<T>* buf, in
 // forward: in 9 comps (row-major (i,J), comps (i,1) already times xi_1) -> out 6:
 // out_i = FFT(in_i1) + xi_2 FFT(in_i2), out_{3+i} = FFT(in_i3)   (1-based J in the comments)
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_ypass_fwd(YArgs<T> a) {
+__device__ __forceinline__ void k_ypass_fwd_body(const YArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     if (a.st && a.st->done) return;
     extern __shared__ char smem_raw[];
     const int L = a.g.n2, TX = a.TX;
     C* tw = reinterpret_cast<C*>(smem_raw);
     C* buf = tw + L;
-    const int z = blockIdx.x / a.ntile;
-    const int kx0 = (blockIdx.x % a.ntile) * TX;
+    const int z = tile_ / a.ntile;
+    const int kx0 = (tile_ % a.ntile) * TX;
     load_twiddles<T>(tw, a.tw, L);
     constexpr int Q = max_elems<T>() / kBlock;
     C acc[Q];
@@ -473,17 +495,28 @@ __global__ void __launch_bounds__(kBlock) k_ypass_fwd(YArgs<T> a) {
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ypass_fwd(YArgs<T> a) {
+    k_ypass_fwd_body<T>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ypass_fwd_b(const YArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_ypass_fwd_body<T>(as[e.rve], e.tile, e.ntiles);
+}
+
 // inverse: in 6 comps [A_i, B_i] -> out 9: (i,1) = IFFT(A_i), (i,2) = IFFT(xi_2 A_i), (i,3) = IFFT(B_i)
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_ypass_inv(YArgs<T> a) {
+__device__ __forceinline__ void k_ypass_inv_body(const YArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     if (a.st && a.st->done) return;
     extern __shared__ char smem_raw[];
     const int L = a.g.n2, TX = a.TX;
     C* tw = reinterpret_cast<C*>(smem_raw);
     C* buf = tw + L;
-    const int z = blockIdx.x / a.ntile;
-    const int kx0 = (blockIdx.x % a.ntile) * TX;
+    const int z = tile_ / a.ntile;
+    const int kx0 = (tile_ % a.ntile) * TX;
     load_twiddles<T>(tw, a.tw, L);
     constexpr int Q = max_elems<T>() / kBlock;
     C av[Q];
@@ -522,6 +555,17 @@ __global__ void __launch_bounds__(kBlock) k_ypass_inv(YArgs<T> a) {
         y_store(a, buf, 3 * i + 2, z, kx0, TX);
         __syncthreads();
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ypass_inv(YArgs<T> a) {
+    k_ypass_inv_body<T>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_ypass_inv_b(const YArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_ypass_inv_body<T>(as[e.rve], e.tile, e.ntiles);
 }
 
 // ------------------------------------------------------------------------------
@@ -668,7 +712,7 @@ __device__ __forceinline__ void z_store(cpx<T>* out, const Grid& g, const cpx<T>
 //   Z_RHS:  r = b = -K^{-1} v, x = 0, partials of <b, b>_K and of |G P|^2 = |v|^2/|xi|^2
 //   Z_PROJ: x = K^{-1} v
 template <typename T, typename TU, int MODE>
-__global__ void __launch_bounds__(kBlock) k_zpass_fwd(ZArgs<T, TU> a) {
+__device__ __forceinline__ void k_zpass_fwd_body(const ZArgs<T, TU>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using CU = cpx<TU>;
     if (MODE == Z_CG && a.st->done) return;
@@ -677,7 +721,7 @@ __global__ void __launch_bounds__(kBlock) k_zpass_fwd(ZArgs<T, TU> a) {
     const int L = a.g.n3, TX = a.TX;
     C* tw = reinterpret_cast<C*>(smem_raw);
     C* buf = tw + L;
-    const long long m0 = (long long)blockIdx.x * TX;
+    const long long m0 = (long long)tile_ * TX;
     const long long M = (long long)a.g.n2 * a.g.nh;
     load_twiddles<T>(tw, a.tw, L);
     constexpr int Q = max_elems<T>() / kBlock;
@@ -720,18 +764,29 @@ __global__ void __launch_bounds__(kBlock) k_zpass_fwd(ZArgs<T, TU> a) {
     }
     if (MODE == Z_CG || MODE == Z_RHS) {
         const double t1 = block_sum(s1, red);
-        if (threadIdx.x == 0) a.partials[blockIdx.x] = t1;
+        if (threadIdx.x == 0) a.partials[tile_] = t1;
     }
     if (MODE == Z_RHS) {
         const double t2 = block_sum(s2, red);
-        if (threadIdx.x == 0) a.partials2[blockIdx.x] = t2;
+        if (threadIdx.x == 0) a.partials2[tile_] = t2;
     }
+}
+
+template <typename T, typename TU, int MODE>
+__global__ void __launch_bounds__(kBlock) k_zpass_fwd(ZArgs<T, TU> a) {
+    k_zpass_fwd_body<T, TU, MODE>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T, typename TU, int MODE>
+__global__ void __launch_bounds__(kBlock) k_zpass_fwd_b(const ZArgs<T, TU>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_zpass_fwd_body<T, TU, MODE>(as[e.rve], e.tile, e.ntiles);
 }
 
 // inverse z pass: source vector u (Z_INV_CG: p = r + beta p first, p = r on the
 // first iteration; Z_INV_PLAIN: u = x), out_i = IFFT(u_i), out_{3+i} = IFFT(xi_3 u_i)
 template <typename T, typename TU, int MODE>
-__global__ void __launch_bounds__(kBlock) k_zpass_inv(ZArgs<T, TU> a) {
+__device__ __forceinline__ void k_zpass_inv_body(const ZArgs<T, TU>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using CU = cpx<TU>;
     if (MODE == Z_INV_CG && a.st->done) return;
@@ -739,7 +794,7 @@ __global__ void __launch_bounds__(kBlock) k_zpass_inv(ZArgs<T, TU> a) {
     const int L = a.g.n3, TX = a.TX;
     C* tw = reinterpret_cast<C*>(smem_raw);
     C* buf = tw + L;
-    const long long m0 = (long long)blockIdx.x * TX;
+    const long long m0 = (long long)tile_ * TX;
     const long long M = (long long)a.g.n2 * a.g.nh;
     load_twiddles<T>(tw, a.tw, L);
     constexpr int Q = max_elems<T>() / kBlock;
@@ -799,6 +854,17 @@ __global__ void __launch_bounds__(kBlock) k_zpass_inv(ZArgs<T, TU> a) {
         z_store<T>(a.out, a.g, buf, 3 + i, m0, TX);
         __syncthreads();
     }
+}
+
+template <typename T, typename TU, int MODE>
+__global__ void __launch_bounds__(kBlock) k_zpass_inv(ZArgs<T, TU> a) {
+    k_zpass_inv_body<T, TU, MODE>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T, typename TU, int MODE>
+__global__ void __launch_bounds__(kBlock) k_zpass_inv_b(const ZArgs<T, TU>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_zpass_inv_body<T, TU, MODE>(as[e.rve], e.tile, e.ntiles);
 }
 
 // ------------------------------------------------------------------------------
@@ -865,15 +931,15 @@ __device__ __forceinline__ double rkr(const UArgs<TU>& a, const cpx<TU>* rr, lon
 }
 
 template <typename TU>
-__global__ void __launch_bounds__(kBlock) k_cg_update(UArgs<TU> a) {
+__device__ __forceinline__ void k_cg_update_body(const UArgs<TU>& a, int tile_, int ntiles_) {
     using CU = cpx<TU>;
     if (a.st->done) return;
     __shared__ double red[16];
     const double alpha = a.st->alpha;
     const long long M = (long long)a.g.n2 * a.g.nh;
     double s = 0.0;
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < a.g.nspec;
-         idx += (long long)gridDim.x * blockDim.x) {
+    for (long long idx = (long long)tile_ * blockDim.x + threadIdx.x; idx < a.g.nspec;
+         idx += (long long)ntiles_ * blockDim.x) {
         const int z = (int)(idx / M);
         const long long m = idx - (long long)z * M;
         const int ky = (int)(m / a.g.nh);
@@ -907,32 +973,56 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(UArgs<TU> a) {
         s += rkr(a, r1, M, idx);
     }
     const double tot = block_sum(s, red);
-    if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
+    if (threadIdx.x == 0) a.partials[tile_] = tot;
 }
 
-// anti-Hermitian projection of the x = 0 plane of one CG vector (right-hand sides)
 template <typename TU>
-__global__ void __launch_bounds__(kBlock) k_antiherm_kx0(cpx<TU>* u, Grid g) {
+__global__ void __launch_bounds__(kBlock) k_cg_update(UArgs<TU> a) {
+    k_cg_update_body<TU>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename TU>
+__global__ void __launch_bounds__(kBlock) k_cg_update_b(const UArgs<TU>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_cg_update_body<TU>(as[e.rve], e.tile, e.ntiles);
+}
+
+// anti-Hermitian projection of the x = 0 plane of the CG vector a.r (right-hand sides)
+template <typename TU>
+__device__ __forceinline__ void k_antiherm_body(const UArgs<TU>& a, int tile_, int ntiles_) {
+    const Grid& g = a.g;
+    cpx<TU>* u = a.r;
     const long long M = (long long)g.n2 * g.nh;
     const long long npl = (long long)g.n2 * g.n3;
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < npl; t += (long long)gridDim.x * blockDim.x) {
+    for (long long t = (long long)tile_ * blockDim.x + threadIdx.x; t < npl; t += (long long)ntiles_ * blockDim.x) {
         const int z = (int)(t / g.n2), ky = (int)(t - (long long)z * g.n2);
         const long long idx = (long long)z * M + (long long)ky * g.nh;
         const long long idx2 = kx0_partner(g, M, z, ky);
         if (idx2 < idx) continue;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            cpx<TU> a = u[i * g.nspec + idx];
+            cpx<TU> v = u[i * g.nspec + idx];
             if (idx2 == idx) {
-                a.x = TU(0);
+                v.x = TU(0);
             } else {
-                cpx<TU> b = u[i * g.nspec + idx2];
-                antiherm_pair(a, b);
-                u[i * g.nspec + idx2] = b;
+                cpx<TU> w = u[i * g.nspec + idx2];
+                antiherm_pair(v, w);
+                u[i * g.nspec + idx2] = w;
             }
-            u[i * g.nspec + idx] = a;
+            u[i * g.nspec + idx] = v;
         }
     }
+}
+
+template <typename TU>
+__global__ void __launch_bounds__(kBlock) k_antiherm(UArgs<TU> a) {
+    k_antiherm_body<TU>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename TU>
+__global__ void __launch_bounds__(kBlock) k_antiherm_b(const UArgs<TU>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_antiherm_body<TU>(as[e.rve], e.tile, e.ntiles);
 }
 
 // ------------------------------------------------------------------------------
@@ -944,19 +1034,19 @@ __device__ __forceinline__ double ordered_sum(const double* p, int count, double
     return block_sum(s, sh);
 }
 
-__global__ void __launch_bounds__(kBlock) k_finalize(int mode, CGState* st, const double* partials,
-                                                     const double* partials2, int count, double tol2, int maxit) {
+__device__ __forceinline__ void finalize_body(int mode, const FinArgs& f) {
     __shared__ double red[16];
+    CGState* st = f.st;
     if (mode != FIN_RHS && st->done) return;
-    const double s1 = ordered_sum(partials, count, red);
+    const double s1 = ordered_sum(f.partials, f.count, red);
     double s2 = 0.0;
-    if (mode == FIN_RHS) s2 = ordered_sum(partials2, count, red);
+    if (mode == FIN_RHS) s2 = ordered_sum(f.partials2, f.count, red);
     if (threadIdx.x != 0) return;
     if (mode == FIN_RHS) {
         st->rho0 = s1;
         st->rho = s1;
-        st->tol2 = tol2;
-        st->maxit = maxit;
+        st->tol2 = f.tol2;
+        st->maxit = f.maxit;
         st->eta2 = s2;
         st->iter = 0;
         st->beta = 0.0;
@@ -964,8 +1054,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int mode, CGState* st, cons
         st->status = 0;
         st->done = (s1 > 0.0) ? 0 : 1;
     } else if (mode == FIN_ALPHA) {
-        if (!(s1 > 0.0)) {
+        if (s1 != s1) {
             st->status = 1;
+            st->done = 1;
+        } else if (!(s1 > 0.0)) {   // negative curvature: x keeps the last iterate
+            st->status = 3;
             st->done = 1;
         } else {
             st->alpha = st->rho / s1;
@@ -984,6 +1077,12 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int mode, CGState* st, cons
         st->beta = s1 / st->rho;
         st->rho = s1;
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_finalize(int mode, FinArgs f) { finalize_body(mode, f); }
+
+__global__ void __launch_bounds__(kBlock) k_finalize_b(int mode, const FinArgs* __restrict__ fs) {
+    finalize_body(mode, fs[blockIdx.x]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_reduce_columns(const double* partials, int rows, int cols, double* out) {
@@ -1005,7 +1104,7 @@ template <int P, int Q, int TX>
 constexpr int fft2_threads() { return TX * (P > Q ? P : Q); }
 
 template <int P, int Q, int TX, typename T>
-__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_fwd(YArgs<T> a) {
+__device__ __forceinline__ void k_y2_fwd_body(const YArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using F = Fft2<P, Q, TX>;
     constexpr int L = P * Q;
@@ -1013,7 +1112,7 @@ __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_fwd(YArgs<T> 
     __shared__ C ex[F::exch_elems()];
     __shared__ C tw[L];
     const int tid = threadIdx.x;
-    const int z = blockIdx.x / a.ntile, kx0 = (blockIdx.x % a.ntile) * TX;
+    const int z = tile_ / a.ntile, kx0 = (tile_ % a.ntile) * TX;
     const int nh = a.g.nh;
     const long long zoff = (long long)z * L * nh;
     for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
@@ -1060,7 +1159,18 @@ __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_fwd(YArgs<T> 
 }
 
 template <int P, int Q, int TX, typename T>
-__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_inv(YArgs<T> a) {
+__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_fwd(YArgs<T> a) {
+    k_y2_fwd_body<P, Q, TX, T>(a, blockIdx.x, gridDim.x);
+}
+
+template <int P, int Q, int TX, typename T>
+__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_fwd_b(const YArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_y2_fwd_body<P, Q, TX, T>(as[e.rve], e.tile, e.ntiles);
+}
+
+template <int P, int Q, int TX, typename T>
+__device__ __forceinline__ void k_y2_inv_body(const YArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using F = Fft2<P, Q, TX>;
     constexpr int L = P * Q;
@@ -1068,7 +1178,7 @@ __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_inv(YArgs<T> 
     __shared__ C ex[F::exch_elems()];
     __shared__ C tw[L];
     const int tid = threadIdx.x;
-    const int z = blockIdx.x / a.ntile, kx0 = (blockIdx.x % a.ntile) * TX;
+    const int z = tile_ / a.ntile, kx0 = (tile_ % a.ntile) * TX;
     const int nh = a.g.nh;
     const long long zoff = (long long)z * L * nh;
     for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
@@ -1106,8 +1216,19 @@ __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_inv(YArgs<T> 
     }
 }
 
+template <int P, int Q, int TX, typename T>
+__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_inv(YArgs<T> a) {
+    k_y2_inv_body<P, Q, TX, T>(a, blockIdx.x, gridDim.x);
+}
+
+template <int P, int Q, int TX, typename T>
+__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_inv_b(const YArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_y2_inv_body<P, Q, TX, T>(as[e.rve], e.tile, e.ntiles);
+}
+
 template <int P, int Q, int TX, typename T, typename TU, int MODE>
-__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_fwd(ZArgs<T, TU> a) {
+__device__ __forceinline__ void k_z2_fwd_body(const ZArgs<T, TU>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using F = Fft2<P, Q, TX>;
     constexpr int L = P * Q;
@@ -1117,7 +1238,7 @@ __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_fwd(ZArgs<T, 
     __shared__ double red[16];
     const int tid = threadIdx.x;
     const long long M = (long long)a.g.n2 * a.g.nh;
-    const long long m0 = (long long)blockIdx.x * TX;
+    const long long m0 = (long long)tile_ * TX;
     for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
     const bool hasA = tid < F::NA, hasB = tid < F::NB;
     const int tA = tid % TX, j1 = tid / TX, tB = tid % TX, k1 = tid / TX;
@@ -1161,16 +1282,27 @@ __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_fwd(ZArgs<T, 
     }
     if (MODE == Z_CG || MODE == Z_RHS) {
         const double t1 = block_sum(s1, red);
-        if (tid == 0) a.partials[blockIdx.x] = t1;
+        if (tid == 0) a.partials[tile_] = t1;
     }
     if (MODE == Z_RHS) {
         const double t2 = block_sum(s2, red);
-        if (tid == 0) a.partials2[blockIdx.x] = t2;
+        if (tid == 0) a.partials2[tile_] = t2;
     }
 }
 
 template <int P, int Q, int TX, typename T, typename TU, int MODE>
-__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_inv(ZArgs<T, TU> a) {
+__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_fwd(ZArgs<T, TU> a) {
+    k_z2_fwd_body<P, Q, TX, T, TU, MODE>(a, blockIdx.x, gridDim.x);
+}
+
+template <int P, int Q, int TX, typename T, typename TU, int MODE>
+__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_fwd_b(const ZArgs<T, TU>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_z2_fwd_body<P, Q, TX, T, TU, MODE>(as[e.rve], e.tile, e.ntiles);
+}
+
+template <int P, int Q, int TX, typename T, typename TU, int MODE>
+__device__ __forceinline__ void k_z2_inv_body(const ZArgs<T, TU>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using CU = cpx<TU>;
     using F = Fft2<P, Q, TX>;
@@ -1180,7 +1312,7 @@ __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_inv(ZArgs<T, 
     __shared__ C tw[L];
     const int tid = threadIdx.x;
     const long long M = (long long)a.g.n2 * a.g.nh;
-    const long long m0 = (long long)blockIdx.x * TX;
+    const long long m0 = (long long)tile_ * TX;
     for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
     const bool hasA = tid < F::NA, hasB = tid < F::NB;
     const int tA = tid % TX, j1 = tid / TX, tB = tid % TX, k1 = tid / TX;
@@ -1248,16 +1380,31 @@ __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_inv(ZArgs<T, 
     }
 }
 
+template <int P, int Q, int TX, typename T, typename TU, int MODE>
+__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_inv(ZArgs<T, TU> a) {
+    k_z2_inv_body<P, Q, TX, T, TU, MODE>(a, blockIdx.x, gridDim.x);
+}
+
+template <int P, int Q, int TX, typename T, typename TU, int MODE>
+__global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_inv_b(const ZArgs<T, TU>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_z2_inv_body<P, Q, TX, T, TU, MODE>(as[e.rve], e.tile, e.ntiles);
+}
+
 // Supported fast-path lengths: (P, Q, TX) per precision; TX keeps the exchange
 // buffer near 35 KB so four workgroups fit in the 160 KB LDS of a CU.
 #define COMBO_FFT2_CONFIGS(X)        \
     X(float, 256, 16, 16, 16)        \
     X(float, 128, 8, 16, 16)         \
+    X(float, 96, 8, 12, 16)          \
     X(float, 64, 8, 8, 32)           \
+    X(float, 48, 8, 6, 24)           \
     X(float, 32, 4, 8, 32)           \
     X(double, 256, 16, 16, 8)        \
     X(double, 128, 8, 16, 8)         \
+    X(double, 96, 8, 12, 16)         \
     X(double, 64, 8, 8, 16)          \
+    X(double, 48, 8, 6, 24)          \
     X(double, 32, 4, 8, 16)
 
 template <typename T>
@@ -1318,19 +1465,33 @@ int blocks_u(const Grid& g) {
     return (int)(b < 4096 ? b : 4096);
 }
 
+#define COMBO_UNPAREN(...) __VA_ARGS__
+// launch KNAME<TARGS> with the argument block `a`, or its batched twin KNAME_b<TARGS>
+// over the tile map of `b` (KARGS_T: the argument block type, one token)
+#define COMBO_LAUNCH(KNAME, TARGS, KARGS_T, GRID, BLOCK, LDS)                                                    \
+    do {                                                                                                      \
+        if (b) {                                                                                              \
+            hipLaunchKernelGGL((KNAME##_b<COMBO_UNPAREN TARGS>), dim3(b->nblocks), dim3(BLOCK), LDS, s,       \
+                               static_cast<const KARGS_T*>(b->args), b->map);                                 \
+        } else {                                                                                              \
+            hipLaunchKernelGGL((KNAME<COMBO_UNPAREN TARGS>), dim3(GRID), dim3(BLOCK), LDS, s, a);             \
+        }                                                                                                     \
+    } while (0)
+
 template <typename T>
-hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb) {
+hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const BatchLaunch* b) {
+    using XA = XArgs<T>;
     const long long nrows = (long long)a.g.n2 * a.g.n3;
 #define COMBO_XW_CASE(LL, MM, WW)                                                                             \
     if (a.g.n1 == LL) {                                                                                     \
         const int nblk = (int)((nrows + (256 / WW) - 1) / (256 / WW));                                       \
         if (nb) *nb = nblk;                                                                                  \
         switch (mode) {                                                                                      \
-            case X_CG: hipLaunchKernelGGL((k_xwave<T, X_CG, MM, WW>), dim3(nblk), dim3(256), 0, s, a); break;   \
-            case X_RHS_E: hipLaunchKernelGGL((k_xwave<T, X_RHS_E, MM, WW>), dim3(nblk), dim3(256), 0, s, a); break; \
-            case X_AVG: hipLaunchKernelGGL((k_xwave<T, X_AVG, MM, WW>), dim3(nblk), dim3(256), 0, s, a); break; \
-            case X_FWD_REAL: hipLaunchKernelGGL((k_xwave<T, X_FWD_REAL, MM, WW>), dim3(nblk), dim3(256), 0, s, a); break; \
-            default: hipLaunchKernelGGL((k_xwave<T, X_INV_REAL, MM, WW>), dim3(nblk), dim3(256), 0, s, a); break; \
+            case X_CG: COMBO_LAUNCH(k_xwave, (T, X_CG, MM, WW), XA, nblk, 256, 0); break;               \
+            case X_RHS_E: COMBO_LAUNCH(k_xwave, (T, X_RHS_E, MM, WW), XA, nblk, 256, 0); break;         \
+            case X_AVG: COMBO_LAUNCH(k_xwave, (T, X_AVG, MM, WW), XA, nblk, 256, 0); break;             \
+            case X_FWD_REAL: COMBO_LAUNCH(k_xwave, (T, X_FWD_REAL, MM, WW), XA, nblk, 256, 0); break;   \
+            default: COMBO_LAUNCH(k_xwave, (T, X_INV_REAL, MM, WW), XA, nblk, 256, 0); break;           \
         }                                                                                                    \
         return hipGetLastError();                                                                            \
     }
@@ -1340,40 +1501,49 @@ hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb) {
     if (nb) *nb = nblk;
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n1 + (size_t)5 * a.R * a.g.n1);
     switch (mode) {
-        case X_CG: hipLaunchKernelGGL((k_xpass<T, X_CG>), dim3(nblk), dim3(kBlock), lds, s, a); break;
-        case X_RHS_E: hipLaunchKernelGGL((k_xpass<T, X_RHS_E>), dim3(nblk), dim3(kBlock), lds, s, a); break;
-        case X_AVG: hipLaunchKernelGGL((k_xpass<T, X_AVG>), dim3(nblk), dim3(kBlock), lds, s, a); break;
-        case X_FWD_REAL: hipLaunchKernelGGL((k_xpass<T, X_FWD_REAL>), dim3(nblk), dim3(kBlock), lds, s, a); break;
-        default: hipLaunchKernelGGL((k_xpass<T, X_INV_REAL>), dim3(nblk), dim3(kBlock), lds, s, a); break;
+        case X_CG: COMBO_LAUNCH(k_xpass, (T, X_CG), XA, nblk, kBlock, lds); break;
+        case X_RHS_E: COMBO_LAUNCH(k_xpass, (T, X_RHS_E), XA, nblk, kBlock, lds); break;
+        case X_AVG: COMBO_LAUNCH(k_xpass, (T, X_AVG), XA, nblk, kBlock, lds); break;
+        case X_FWD_REAL: COMBO_LAUNCH(k_xpass, (T, X_FWD_REAL), XA, nblk, kBlock, lds); break;
+        default: COMBO_LAUNCH(k_xpass, (T, X_INV_REAL), XA, nblk, kBlock, lds); break;
     }
     return hipGetLastError();
 }
 
+// y and z launchers: the caller's TX/ntile are replaced by the tile width of the
+// kernel that runs (two-stage fast path or LDS Stockham)
 template <typename T>
-hipError_t launch_y(int dir, const YArgs<T>& a0, hipStream_t s) {
-    YArgs<T> a = a0;
+void y_fill_tiles(YArgs<T>& a) {
     a.TX = y_tile<T>(a.g);
     a.ntile = (a.g.nh + a.TX - 1) / a.TX;
+}
+
+template <typename T>
+hipError_t launch_y(int dir, const YArgs<T>& a0, hipStream_t s, const BatchLaunch* b) {
+    using YA = YArgs<T>;
+    YArgs<T> a = a0;
+    y_fill_tiles(a);
     const int nblk = a.g.n3 * a.ntile;
 #define COMBO_Y_CASE(TT, LL, PP, QQ, TXX)                                                                       \
     if constexpr (std::is_same<T, TT>::value) {                                                               \
         if (a.g.n2 == LL) {                                                                                    \
             constexpr int nt = fft2_threads<PP, QQ, TXX>();                                                    \
-            if (dir < 0) hipLaunchKernelGGL((k_y2_fwd<PP, QQ, TXX, T>), dim3(nblk), dim3(nt), 0, s, a);        \
-            else hipLaunchKernelGGL((k_y2_inv<PP, QQ, TXX, T>), dim3(nblk), dim3(nt), 0, s, a);                \
+            if (dir < 0) COMBO_LAUNCH(k_y2_fwd, (PP, QQ, TXX, T), YA, nblk, nt, 0);                      \
+            else COMBO_LAUNCH(k_y2_inv, (PP, QQ, TXX, T), YA, nblk, nt, 0);                              \
             return hipGetLastError();                                                                          \
         }                                                                                                      \
     }
     COMBO_FFT2_CONFIGS(COMBO_Y_CASE)
 #undef COMBO_Y_CASE
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n2 + (size_t)a.g.n2 * a.TX);
-    if (dir < 0) hipLaunchKernelGGL(k_ypass_fwd<T>, dim3(nblk), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL(k_ypass_inv<T>, dim3(nblk), dim3(kBlock), lds, s, a);
+    if (dir < 0) COMBO_LAUNCH(k_ypass_fwd, (T), YA, nblk, kBlock, lds);
+    else COMBO_LAUNCH(k_ypass_inv, (T), YA, nblk, kBlock, lds);
     return hipGetLastError();
 }
 
 template <typename T, typename TU>
-hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb) {
+hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb, const BatchLaunch* b) {
+    using ZA = ZArgs<T, TU>;
     ZArgs<T, TU> a = a0;
     a.TX = z_tile<T>(a.g);
     const int nblk = blocks_z(a.g, a.TX);
@@ -1383,11 +1553,11 @@ hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb) {
         if (a.g.n3 == LL) {                                                                                   \
             constexpr int nt = fft2_threads<PP, QQ, TXX>();                                                   \
             switch (mode) {                                                                                   \
-                case Z_CG: hipLaunchKernelGGL((k_z2_fwd<PP, QQ, TXX, T, TU, Z_CG>), dim3(nblk), dim3(nt), 0, s, a); break; \
-                case Z_RHS: hipLaunchKernelGGL((k_z2_fwd<PP, QQ, TXX, T, TU, Z_RHS>), dim3(nblk), dim3(nt), 0, s, a); break; \
-                case Z_PROJ: hipLaunchKernelGGL((k_z2_fwd<PP, QQ, TXX, T, TU, Z_PROJ>), dim3(nblk), dim3(nt), 0, s, a); break; \
-                case Z_INV_CG: hipLaunchKernelGGL((k_z2_inv<PP, QQ, TXX, T, TU, Z_INV_CG>), dim3(nblk), dim3(nt), 0, s, a); break; \
-                default: hipLaunchKernelGGL((k_z2_inv<PP, QQ, TXX, T, TU, Z_INV_PLAIN>), dim3(nblk), dim3(nt), 0, s, a); break; \
+                case Z_CG: COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_CG), ZA, nblk, nt, 0); break;        \
+                case Z_RHS: COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_RHS), ZA, nblk, nt, 0); break;      \
+                case Z_PROJ: COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_PROJ), ZA, nblk, nt, 0); break;    \
+                case Z_INV_CG: COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_CG), ZA, nblk, nt, 0); break; \
+                default: COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_PLAIN), ZA, nblk, nt, 0); break;  \
             }                                                                                                 \
             return hipGetLastError();                                                                         \
         }                                                                                                     \
@@ -1396,34 +1566,39 @@ hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb) {
 #undef COMBO_Z_CASE
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n3 + (size_t)a.g.n3 * a.TX);
     switch (mode) {
-        case Z_CG: hipLaunchKernelGGL((k_zpass_fwd<T, TU, Z_CG>), dim3(nblk), dim3(kBlock), lds, s, a); break;
-        case Z_RHS: hipLaunchKernelGGL((k_zpass_fwd<T, TU, Z_RHS>), dim3(nblk), dim3(kBlock), lds, s, a); break;
-        case Z_PROJ: hipLaunchKernelGGL((k_zpass_fwd<T, TU, Z_PROJ>), dim3(nblk), dim3(kBlock), lds, s, a); break;
-        case Z_INV_CG: hipLaunchKernelGGL((k_zpass_inv<T, TU, Z_INV_CG>), dim3(nblk), dim3(kBlock), lds, s, a); break;
-        default: hipLaunchKernelGGL((k_zpass_inv<T, TU, Z_INV_PLAIN>), dim3(nblk), dim3(kBlock), lds, s, a); break;
+        case Z_CG: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_CG), ZA, nblk, kBlock, lds); break;
+        case Z_RHS: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_RHS), ZA, nblk, kBlock, lds); break;
+        case Z_PROJ: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_PROJ), ZA, nblk, kBlock, lds); break;
+        case Z_INV_CG: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_CG), ZA, nblk, kBlock, lds); break;
+        default: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_PLAIN), ZA, nblk, kBlock, lds); break;
     }
     return hipGetLastError();
 }
 
 template <typename TU>
-hipError_t launch_update(const UArgs<TU>& a, hipStream_t s, int* nb) {
+hipError_t launch_update(const UArgs<TU>& a, hipStream_t s, int* nb, const BatchLaunch* b) {
+    using UA = UArgs<TU>;
     const int nblk = blocks_u(a.g);
     if (nb) *nb = nblk;
-    hipLaunchKernelGGL(k_cg_update<TU>, dim3(nblk), dim3(kBlock), 0, s, a);
+    COMBO_LAUNCH(k_cg_update, (TU), UA, nblk, kBlock, 0);
     return hipGetLastError();
+}
+
+int blocks_antiherm(const Grid& g) {
+    const long long npl = (long long)g.n2 * g.n3;
+    return (int)std::min<long long>((npl + kBlock - 1) / kBlock, 1024);
 }
 
 template <typename TU>
-hipError_t launch_antiherm(cpx<TU>* u, const Grid& g, hipStream_t s) {
-    long long npl = (long long)g.n2 * g.n3;
-    int nb = (int)std::min<long long>((npl + kBlock - 1) / kBlock, 1024);
-    hipLaunchKernelGGL(k_antiherm_kx0<TU>, dim3(nb), dim3(kBlock), 0, s, u, g);
+hipError_t launch_antiherm(const UArgs<TU>& a, hipStream_t s, const BatchLaunch* b) {
+    using UA = UArgs<TU>;
+    COMBO_LAUNCH(k_antiherm, (TU), UA, blocks_antiherm(a.g), kBlock, 0);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(int mode, CGState* st, const double* partials, const double* partials2, int count,
-                           hipStream_t s, double tol2, int maxit) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, mode, st, partials, partials2, count, tol2, maxit);
+hipError_t launch_finalize(int mode, const FinArgs& f, hipStream_t s, const FinArgs* dev_batch, int nrve) {
+    if (dev_batch) hipLaunchKernelGGL(k_finalize_b, dim3(nrve), dim3(kBlock), 0, s, mode, dev_batch);
+    else hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, mode, f);
     return hipGetLastError();
 }
 
@@ -1432,16 +1607,16 @@ hipError_t launch_reduce_columns(const double* partials, int rows, int cols, dou
     return hipGetLastError();
 }
 
-template hipError_t launch_x<float>(int, const XArgs<float>&, hipStream_t, int*);
-template hipError_t launch_x<double>(int, const XArgs<double>&, hipStream_t, int*);
-template hipError_t launch_y<float>(int, const YArgs<float>&, hipStream_t);
-template hipError_t launch_y<double>(int, const YArgs<double>&, hipStream_t);
-template hipError_t launch_z<float, float>(int, const ZArgs<float, float>&, hipStream_t, int*);
-template hipError_t launch_z<double, double>(int, const ZArgs<double, double>&, hipStream_t, int*);
-template hipError_t launch_z<double, float>(int, const ZArgs<double, float>&, hipStream_t, int*);
-template hipError_t launch_update<float>(const UArgs<float>&, hipStream_t, int*);
-template hipError_t launch_update<double>(const UArgs<double>&, hipStream_t, int*);
-template hipError_t launch_antiherm<float>(cpx<float>*, const Grid&, hipStream_t);
-template hipError_t launch_antiherm<double>(cpx<double>*, const Grid&, hipStream_t);
+template hipError_t launch_x<float>(int, const XArgs<float>&, hipStream_t, int*, const BatchLaunch*);
+template hipError_t launch_x<double>(int, const XArgs<double>&, hipStream_t, int*, const BatchLaunch*);
+template hipError_t launch_y<float>(int, const YArgs<float>&, hipStream_t, const BatchLaunch*);
+template hipError_t launch_y<double>(int, const YArgs<double>&, hipStream_t, const BatchLaunch*);
+template hipError_t launch_z<float, float>(int, const ZArgs<float, float>&, hipStream_t, int*, const BatchLaunch*);
+template hipError_t launch_z<double, double>(int, const ZArgs<double, double>&, hipStream_t, int*, const BatchLaunch*);
+template hipError_t launch_z<double, float>(int, const ZArgs<double, float>&, hipStream_t, int*, const BatchLaunch*);
+template hipError_t launch_update<float>(const UArgs<float>&, hipStream_t, int*, const BatchLaunch*);
+template hipError_t launch_update<double>(const UArgs<double>&, hipStream_t, int*, const BatchLaunch*);
+template hipError_t launch_antiherm<float>(const UArgs<float>&, hipStream_t, const BatchLaunch*);
+template hipError_t launch_antiherm<double>(const UArgs<double>&, hipStream_t, const BatchLaunch*);
 
 }  // namespace combo

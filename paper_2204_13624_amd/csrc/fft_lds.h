@@ -202,7 +202,7 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* buf, int L, int TX, int Ns
 
 // Transform TX columns of length plan.L held in buf; tw = forward twiddles of plan.L.
 template <int DIR, bool COLMAJOR, typename T>
-__device__ void fft_lds(cpx<T>* buf, const AxisPlan& plan, int TX, const cpx<T>* tw) {
+__device__ __forceinline__ void fft_lds(cpx<T>* buf, const AxisPlan& plan, int TX, const cpx<T>* tw) {
     int Ns = 1;
     for (int p = 0; p < plan.npass; ++p) {
         const int R = plan.radix[p];

@@ -17,7 +17,7 @@ struct CGState {
     int iter;
     int maxit;
     int done;       // 1 once converged or failed: every later kernel of the solve returns at once
-    int status;     // 0 ok, 1 breakdown (<p, Ap> <= 0 or NaN), 2 iteration limit
+    int status;     // 0 ok, 1 breakdown (NaN), 2 iteration limit, 3 negative curvature (<p, Ap> <= 0)
 };
 
 // Tangent state of the pointwise law in the precision T of the linear solves.
@@ -108,19 +108,33 @@ struct PassShape {
 };
 
 // Launchers (fft_kernels.hip).  All enqueue on `s` and return hipError_t.
-template <typename T> hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nblocks_out = nullptr);
-template <typename T> hipError_t launch_y(int dir, const YArgs<T>& a, hipStream_t s);
+// Launchers (fft_kernels.hip).  All enqueue on `s` and return hipError_t.  With
+// a BatchLaunch, `a` only selects the kernel variant (all RVEs of the batch share
+// its grid) and the per-RVE arguments come from b->args.
+template <typename T> hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nblocks_out = nullptr,
+                                          const BatchLaunch* b = nullptr);
+template <typename T> hipError_t launch_y(int dir, const YArgs<T>& a, hipStream_t s, const BatchLaunch* b = nullptr);
 // z modes
 enum ZMode { Z_CG = 0, Z_RHS = 1, Z_INV_CG = 2, Z_INV_PLAIN = 3, Z_PROJ = 4 };
 template <typename T, typename TU> hipError_t launch_z(int mode, const ZArgs<T, TU>& a, hipStream_t s,
-                                                       int* nblocks_out = nullptr);
-template <typename TU> hipError_t launch_update(const UArgs<TU>& a, hipStream_t s, int* nblocks_out = nullptr);
-// anti-Hermitian projection of the x = 0 frequency plane of a CG vector
-template <typename TU> hipError_t launch_antiherm(cpx<TU>* u, const Grid& g, hipStream_t s);
-// finalisers (one workgroup): reduce `count` partials in fixed order
+                                                       int* nblocks_out = nullptr, const BatchLaunch* b = nullptr);
+template <typename TU> hipError_t launch_update(const UArgs<TU>& a, hipStream_t s, int* nblocks_out = nullptr,
+                                               const BatchLaunch* b = nullptr);
+// anti-Hermitian projection of the x = 0 frequency plane of the CG vector a.r
+template <typename TU> hipError_t launch_antiherm(const UArgs<TU>& a, hipStream_t s, const BatchLaunch* b = nullptr);
+int blocks_antiherm(const Grid& g);
+// finalisers (one workgroup per RVE): reduce `count` partials in fixed order
 enum FinMode { FIN_ALPHA = 0, FIN_BETA = 1, FIN_RHS = 2 };
-hipError_t launch_finalize(int mode, CGState* st, const double* partials, const double* partials2, int count,
-                           hipStream_t s, double tol2 = 0.0, int maxit = 0);
+struct FinArgs {
+    CGState* st;
+    const double* partials;
+    const double* partials2;
+    int count;
+    double tol2;
+    int maxit;
+};
+// single: one FinArgs by value; batched: nrve FinArgs in device memory
+hipError_t launch_finalize(int mode, const FinArgs& f, hipStream_t s, const FinArgs* dev_batch = nullptr, int nrve = 1);
 hipError_t launch_reduce_columns(const double* partials, int rows, int cols, double* out, hipStream_t s);
 
 // tile widths the y and z launchers use (two-stage fast path or LDS Stockham)

@@ -70,4 +70,17 @@ int material_blocks_laminate(int nc);
 template <typename T>
 hipError_t launch_material(const MatArgs<T>& a, int nbp, int nbl, double* sums_out, hipStream_t s);
 
+// Batched material update: per-RVE MatArgs and tile maps for the pure and the
+// laminate kernels, then one reduction workgroup per RVE (red[i] describes RVE i).
+struct MatReduceArgs {
+    const double* pp;   // pure partials [nbp][19]
+    int nbp;
+    const double* pl;   // laminate partials [nbl][31]
+    int nbl;
+    double* out;        // [kSumsLen]
+};
+template <typename T>
+hipError_t launch_material_batch(const MatArgs<T>* dev_args, const BatchLaunch& pure, const BatchLaunch& lam,
+                                 const MatReduceArgs* dev_red, int nrve, hipStream_t s);
+
 }  // namespace combo

@@ -88,13 +88,13 @@ __device__ __forceinline__ void block_sum_n(double* v, double* sh, double* out) 
 // pure voxels (and the deformation update of every voxel)
 // ------------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_material_pure(MatArgs<T> a) {
+__device__ __forceinline__ void k_material_pure_body(const MatArgs<T>& a, int tile_, int ntiles_) {
     __shared__ double sh[4 * 19];
     double sums[19];
 #pragma unroll
     for (int c = 0; c < 19; ++c) sums[c] = 0.0;
-    for (long long vox = (long long)blockIdx.x * blockDim.x + threadIdx.x; vox < a.n;
-         vox += (long long)gridDim.x * blockDim.x) {
+    for (long long vox = (long long)tile_ * blockDim.x + threadIdx.x; vox < a.n;
+         vox += (long long)ntiles_ * blockDim.x) {
         double F[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
@@ -140,19 +140,30 @@ __global__ void __launch_bounds__(256) k_material_pure(MatArgs<T> a) {
     }
     double out[19];
     block_sum_n<19>(sums, sh, out);
-    if (threadIdx.x < 19) a.partials[(long long)blockIdx.x * 19 + threadIdx.x] = out[threadIdx.x];
+    if (threadIdx.x < 19) a.partials[(long long)tile_ * 19 + threadIdx.x] = out[threadIdx.x];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_material_pure(MatArgs<T> a) {
+    k_material_pure_body<T>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_material_pure_b(const MatArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_material_pure_body<T>(as[e.rve], e.tile, e.ntiles);
 }
 
 // ------------------------------------------------------------------------------
 // composite voxels
 // ------------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(128) k_material_laminate(MatArgs<T> a) {
+__device__ __forceinline__ void k_material_laminate_body(const MatArgs<T>& a, int tile_, int ntiles_) {
     __shared__ double sh[2 * 31];
     double sums[31];   // P_box (9), c P+ (9), (1-c) P- (9), fails, iters, backprojections, max iters
 #pragma unroll
     for (int c = 0; c < 31; ++c) sums[c] = 0.0;
-    for (int ic = blockIdx.x * blockDim.x + threadIdx.x; ic < a.nc; ic += gridDim.x * blockDim.x) {
+    for (int ic = tile_ * blockDim.x + threadIdx.x; ic < a.nc; ic += ntiles_ * blockDim.x) {
         const long long vox = a.comp_vox[ic];
         double Fb[9];
 #pragma unroll
@@ -357,19 +368,30 @@ __global__ void __launch_bounds__(128) k_material_laminate(MatArgs<T> a) {
     __shared__ double shm[4];
     if ((threadIdx.x & 63) == 0) shm[threadIdx.x >> 6] = sums[30];
     __syncthreads();
-    if (threadIdx.x < 30) a.partials[(long long)blockIdx.x * 31 + threadIdx.x] = out[threadIdx.x];
+    if (threadIdx.x < 30) a.partials2[(long long)tile_ * 31 + threadIdx.x] = out[threadIdx.x];
     if (threadIdx.x == 0) {
         double mx = 0.0;
         for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) mx = fmax(mx, shm[w]);
-        a.partials[(long long)blockIdx.x * 31 + 30] = mx;
+        a.partials2[(long long)tile_ * 31 + 30] = mx;
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(128) k_material_laminate(MatArgs<T> a) {
+    k_material_laminate_body<T>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(128) k_material_laminate_b(const MatArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_material_laminate_body<T>(as[e.rve], e.tile, e.ntiles);
 }
 
 // ------------------------------------------------------------------------------
 // reductions of the per-block material sums (fixed order)
 // ------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_material_reduce(const double* pp, int nbp, const double* pl, int nbl,
-                                                         double* out) {
+__device__ __forceinline__ void material_reduce_body(const double* pp, int nbp, const double* pl, int nbl,
+                                                     double* out) {
     // out[0..19) = sums over pure blocks, out[19..50) = sums over laminate blocks (index 49 = max)
     __shared__ double sh[4];
     for (int c = 0; c < 19 + 31; ++c) {
@@ -399,6 +421,17 @@ __global__ void __launch_bounds__(256) k_material_reduce(const double* pp, int n
     }
 }
 
+__global__ void __launch_bounds__(256) k_material_reduce(const double* pp, int nbp, const double* pl, int nbl,
+                                                         double* out) {
+    material_reduce_body(pp, nbp, pl, nbl, out);
+}
+
+// one workgroup per RVE
+__global__ void __launch_bounds__(256) k_material_reduce_b(const MatReduceArgs* __restrict__ red) {
+    const MatReduceArgs r = red[blockIdx.x];
+    material_reduce_body(r.pp, r.nbp, r.pl, r.nbl, r.out);
+}
+
 int material_blocks_pure(long long n) {
     long long b = (n + 255) / 256;
     return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
@@ -410,15 +443,11 @@ int material_blocks_laminate(int nc) {
 
 template <typename T>
 hipError_t launch_material(const MatArgs<T>& a, int nbp, int nbl, double* sums_out, hipStream_t s) {
-    MatArgs<T> ap = a;
-    ap.partials = a.partials;
-    hipLaunchKernelGGL(k_material_pure<T>, dim3(nbp), dim3(256), 0, s, ap);
+    hipLaunchKernelGGL(k_material_pure<T>, dim3(nbp), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    MatArgs<T> al = a;
-    al.partials = a.partials2;
     if (a.nc > 0) {
-        hipLaunchKernelGGL(k_material_laminate<T>, dim3(nbl), dim3(128), 0, s, al);
+        hipLaunchKernelGGL(k_material_laminate<T>, dim3(nbl), dim3(128), 0, s, a);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -427,7 +456,28 @@ hipError_t launch_material(const MatArgs<T>& a, int nbp, int nbl, double* sums_o
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_material_batch(const MatArgs<T>* dev_args, const BatchLaunch& pure, const BatchLaunch& lam,
+                                 const MatReduceArgs* dev_red, int nrve, hipStream_t s) {
+    if (pure.nblocks > 0) {
+        hipLaunchKernelGGL(k_material_pure_b<T>, dim3(pure.nblocks), dim3(256), 0, s, dev_args, pure.map);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (lam.nblocks > 0) {
+        hipLaunchKernelGGL(k_material_laminate_b<T>, dim3(lam.nblocks), dim3(128), 0, s, dev_args, lam.map);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_material_reduce_b, dim3(nrve), dim3(256), 0, s, dev_red);
+    return hipGetLastError();
+}
+
 template hipError_t launch_material<float>(const MatArgs<float>&, int, int, double*, hipStream_t);
 template hipError_t launch_material<double>(const MatArgs<double>&, int, int, double*, hipStream_t);
+template hipError_t launch_material_batch<float>(const MatArgs<float>*, const BatchLaunch&, const BatchLaunch&,
+                                                 const MatReduceArgs*, int, hipStream_t);
+template hipError_t launch_material_batch<double>(const MatArgs<double>*, const BatchLaunch&, const BatchLaunch&,
+                                                  const MatReduceArgs*, int, hipStream_t);
 
 }  // namespace combo

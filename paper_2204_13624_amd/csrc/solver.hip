@@ -29,6 +29,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -38,6 +39,10 @@
 using namespace combo;
 
 namespace {
+
+// internal (positive) return of cg_solve: CG stopped at a direction of
+// non-positive curvature; x holds the iterate reached before it
+constexpr int kNegCurv = 1;
 
 int set_err(combo_ctx* ctx, int status, const std::string& msg) {
     if (ctx) ctx->err = msg;
@@ -307,6 +312,32 @@ ZArgs<T, TU> zargs(const combo_ctx* ctx, double mu0, double kappa0) {
     return a;
 }
 
+template <typename TU>
+UArgs<TU> uargs(const combo_ctx* ctx, double mu0, double kappa0) {
+    UArgs<TU> ua{};
+    ua.g = ctx->g;
+    ua.x = ctx->ux.as<cpx<TU>>();
+    ua.r = ctx->ur.as<cpx<TU>>();
+    ua.p = ctx->up.as<cpx<TU>>();
+    ua.q = ctx->uq.as<cpx<TU>>();
+    ua.mu0 = mu0;
+    ua.kappa0 = kappa0;
+    ua.partials = ctx->part2.as<double>();
+    ua.st = ctx->cgst.as<CGState>();
+    return ua;
+}
+
+FinArgs finargs(const combo_ctx* ctx, const double* p1, const double* p2, int count, double tol2 = 0.0, int maxit = 0) {
+    FinArgs f{};
+    f.st = ctx->cgst.as<CGState>();
+    f.partials = p1;
+    f.partials2 = p2;
+    f.count = count;
+    f.tol2 = tol2;
+    f.maxit = maxit;
+    return f;
+}
+
 // material law at F = F_old + s dF + dFbar -> F_trial, P, tangent state (precision T), a_trial.
 template <typename T>
 int material(combo_ctx* ctx, const double* F_old, const double* dF, double s, const double dFbar[9], double* F_new,
@@ -385,9 +416,9 @@ int residual(combo_ctx* ctx, double mu0, double kappa0, double tol_cg, double& e
         za.in = ctx->specB.as<double2>();
         int nb = 0;
         HIP_OR_FAIL(launch_z<double, TU>(Z_RHS, za, ctx->stream, &nb));
-        HIP_OR_FAIL(launch_antiherm<TU>(ctx->ur.as<cpx<TU>>(), ctx->g, ctx->stream));
-        HIP_OR_FAIL(launch_finalize(FIN_RHS, ctx->cgst.as<CGState>(), ctx->part1.as<double>(), ctx->part2.as<double>(),
-                                    nb, ctx->stream, tol_cg * tol_cg, ctx->opt.max_cg));
+        HIP_OR_FAIL(launch_antiherm<TU>(uargs<TU>(ctx, mu0, kappa0), ctx->stream));
+        HIP_OR_FAIL(launch_finalize(FIN_RHS, finargs(ctx, ctx->part1.as<double>(), ctx->part2.as<double>(), nb,
+                                                     tol_cg * tol_cg, ctx->opt.max_cg), ctx->stream));
     }
     HIP_OR_FAIL(hipMemcpyAsync(&ctx->hs->cg, ctx->cgst.p, sizeof(CGState), hipMemcpyDeviceToHost, ctx->stream));
     HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
@@ -433,18 +464,9 @@ int cg_iteration(combo_ctx* ctx, double mu0, double kappa0) {
     }
     {
         ProfScope ps(ctx, COMBO_K_CG_FINALIZE);
-        HIP_OR_FAIL(launch_finalize(FIN_ALPHA, ctx->cgst.as<CGState>(), ctx->part1.as<double>(), nullptr, nbz, s));
+        HIP_OR_FAIL(launch_finalize(FIN_ALPHA, finargs(ctx, ctx->part1.as<double>(), nullptr, nbz), s));
     }
-    UArgs<T> ua{};
-    ua.g = ctx->g;
-    ua.x = ctx->ux.as<cpx<T>>();
-    ua.r = ctx->ur.as<cpx<T>>();
-    ua.p = ctx->up.as<cpx<T>>();
-    ua.q = ctx->uq.as<cpx<T>>();
-    ua.mu0 = mu0;
-    ua.kappa0 = kappa0;
-    ua.partials = ctx->part2.as<double>();
-    ua.st = ctx->cgst.as<CGState>();
+    const UArgs<T> ua = uargs<T>(ctx, mu0, kappa0);
     int nbu = 0;
     {
         ProfScope ps(ctx, COMBO_K_CG_UPDATE);
@@ -452,7 +474,7 @@ int cg_iteration(combo_ctx* ctx, double mu0, double kappa0) {
     }
     {
         ProfScope ps(ctx, COMBO_K_CG_FINALIZE);
-        HIP_OR_FAIL(launch_finalize(FIN_BETA, ctx->cgst.as<CGState>(), ctx->part2.as<double>(), nullptr, nbu, s));
+        HIP_OR_FAIL(launch_finalize(FIN_BETA, finargs(ctx, ctx->part2.as<double>(), nullptr, nbu), s));
     }
     return COMBO_OK;
 }
@@ -499,7 +521,11 @@ int cg_solve(combo_ctx* ctx, double mu0, double kappa0, int& iters) {
     if (!ctx->hs->cg.done)
         return set_err(ctx, COMBO_E_NOCONV, "CG did not terminate");
     if (ctx->hs->cg.status == 1)
-        return set_err(ctx, COMBO_E_NUMERIC, "CG breakdown (<p, A p> <= 0 or NaN)");
+        return set_err(ctx, COMBO_E_NUMERIC, "CG breakdown (<p, A p> is NaN)");
+    if (ctx->hs->cg.status == 3) {
+        set_err(ctx, COMBO_E_NUMERIC, "CG met negative curvature (<p, A p> <= 0)");
+        return kNegCurv;
+    }
     if (ctx->hs->cg.status == 2)
         return set_err(ctx, COMBO_E_NOCONV, "CG did not converge in max_cg iterations");
     return COMBO_OK;
@@ -534,11 +560,12 @@ int effective_tangent(combo_ctx* ctx, double mu0, double kappa0, double tol_cg, 
         za.in = ctx->specB.as<cpx<T>>();
         int nb = 0;
         HIP_OR_FAIL(launch_z<T, T>(Z_RHS, za, ctx->stream, &nb));
-        HIP_OR_FAIL(launch_antiherm<T>(ctx->ur.as<cpx<T>>(), ctx->g, ctx->stream));
-        HIP_OR_FAIL(launch_finalize(FIN_RHS, ctx->cgst.as<CGState>(), ctx->part1.as<double>(), ctx->part2.as<double>(),
-                                    nb, ctx->stream, tol_cg * tol_cg, ctx->opt.max_cg));
+        HIP_OR_FAIL(launch_antiherm<T>(uargs<T>(ctx, mu0, kappa0), ctx->stream));
+        HIP_OR_FAIL(launch_finalize(FIN_RHS, finargs(ctx, ctx->part1.as<double>(), ctx->part2.as<double>(), nb,
+                                                     tol_cg * tol_cg, ctx->opt.max_cg), ctx->stream));
         int it = 0;
         int st = cg_solve<T>(ctx, mu0, kappa0, it);
+        if (st == kNegCurv) return COMBO_E_NUMERIC;   // message set by cg_solve
         if (st) return st;
         cg_total += it;
         ZArgs<T, T> zi = zargs<T, T>(ctx, mu0, kappa0);
@@ -567,6 +594,7 @@ struct SolveOut {
     combo_stats st{};
     double Pbar[9]{};
     double Pp[9]{}, Pm[9]{};
+    double Abar_store[81]{};
 };
 
 template <typename T>
@@ -622,6 +650,13 @@ int solve_impl(combo_ctx* ctx, const double Fbar[9], const double Fbar0[9], Solv
                     st = cg_solve<T>(ctx, mu0, kappa0, cgit);
                     S.time_ms_cg += ms_since(tc);
                     S.cg_iters_total += cgit;
+                    if (st == kNegCurv) {
+                        // truncated Newton: step along the iterate reached so far, or
+                        // halve the increment if there is none
+                        S.cg_truncations += 1;
+                        st = COMBO_OK;
+                        if (cgit == 0) break;
+                    }
                     if (st) {
                         S.eta_final = eta;
                         return st;
@@ -693,6 +728,536 @@ int solve_impl(combo_ctx* ctx, const double Fbar[9], const double Fbar0[9], Solv
     prof_harvest(ctx);
     S.time_ms_total = ms_since(t_start);
     return COMBO_OK;
+}
+
+// ------------------------------------------------------------------------------
+// batched solve: many RVEs, one launch per pass and kernel shape
+// ------------------------------------------------------------------------------
+int bset_err(combo_batch* b, int status, const std::string& msg) {
+    if (b) b->err = msg;
+    return status;
+}
+
+#define BHIP_OR_FAIL(...)                                                                                   \
+    do {                                                                                                    \
+        hipError_t e__ = (__VA_ARGS__);                                                                     \
+        if (e__ != hipSuccess)                                                                              \
+            return bset_err(B, e__ == hipErrorOutOfMemory ? COMBO_E_NOMEM : COMBO_E_HIP,                    \
+                            std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e__));                     \
+    } while (0)
+
+// Argument tables and tile maps of a set of batched launches, built on the host,
+// uploaded in one copy, then launched in order.
+struct LaunchPlan {
+    std::vector<char> host;
+    std::vector<std::function<hipError_t(char*)>> ops;
+    DevBuf dev;
+    size_t put(const void* src, size_t bytes) {
+        const size_t off = (host.size() + 255) & ~(size_t)255;
+        host.resize(off + bytes);
+        if (bytes) memcpy(host.data() + off, src, bytes);
+        return off;
+    }
+    void clear() {
+        host.clear();
+        ops.clear();
+    }
+    // nothing may be in flight on the stream that reads `dev`
+    hipError_t upload() {
+        if (host.empty()) return hipSuccess;
+        hipError_t e = dev.ensure(host.size());
+        if (e != hipSuccess) return e;
+        return hipMemcpy(dev.p, host.data(), host.size(), hipMemcpyHostToDevice);
+    }
+    hipError_t run() const {
+        for (const auto& op : ops) {
+            hipError_t e = op(static_cast<char*>(dev.p));
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+};
+
+// One pass over the members whose argument blocks are `args`: one launch per
+// distinct key (the kernel shape), over the nblk[i] tiles of each member i.
+template <class A, class F>
+void plan_pass(LaunchPlan& lp, const std::vector<A>& args, const std::vector<long long>& key,
+               const std::vector<int>& nblk, F launch) {
+    if (args.empty()) return;
+    const size_t aoff = lp.put(args.data(), sizeof(A) * args.size());
+    std::vector<int> idx(args.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return key[a] < key[b]; });
+    for (size_t g0 = 0; g0 < idx.size();) {
+        size_t g1 = g0;
+        while (g1 < idx.size() && key[idx[g1]] == key[idx[g0]]) ++g1;
+        std::vector<TileMap> map;
+        for (size_t k = g0; k < g1; ++k) {
+            const int i = idx[k];
+            for (int t = 0; t < nblk[i]; ++t) map.push_back(TileMap{i, t, nblk[i]});
+        }
+        const size_t moff = lp.put(map.data(), sizeof(TileMap) * map.size());
+        const A rep = args[idx[g0]];
+        const int nb = (int)map.size();
+        lp.ops.push_back([=](char* base) -> hipError_t {
+            BatchLaunch bl{base + aoff, reinterpret_cast<const TileMap*>(base + moff), nb};
+            return launch(rep, &bl);
+        });
+        g0 = g1;
+    }
+}
+
+void plan_finalize(LaunchPlan& lp, int mode, const std::vector<FinArgs>& f, hipStream_t s) {
+    if (f.empty()) return;
+    const size_t off = lp.put(f.data(), sizeof(FinArgs) * f.size());
+    const int cnt = (int)f.size();
+    const FinArgs rep = f[0];
+    lp.ops.push_back([=](char* base) -> hipError_t {
+        return launch_finalize(mode, rep, s, reinterpret_cast<const FinArgs*>(base + off), cnt);
+    });
+}
+
+long long key2(long long a, long long b) { return (a << 32) | b; }
+
+enum MemberPhase { PH_INC = 0, PH_RES, PH_CG, PH_STEP, PH_DONE, PH_FAIL };
+
+struct Member {
+    combo_ctx* ctx = nullptr;
+    int index = 0;
+    double Fbar[9]{}, Fbar0[9]{};
+    int K = 1;
+    double mu0 = 0, kappa0 = 0, tol_cg = 0;
+    int phase = PH_INC;
+    int k = 1, depth = 0, it_n = 0, h = 0, cg_rounds = 0;
+    double t = 0, t1 = 0, dt = 0, tn = 0, s = 1.0, eta = 0.0;
+    double dFbar[9]{};
+    SolveOut out;
+    int status = COMBO_OK;
+    double load(double tt, int c) const { return Fbar0[c] + tt * (Fbar[c] - Fbar0[c]); }
+};
+
+void member_fail(Member& m, int status, const std::string& msg) {
+    m.status = status;
+    m.ctx->err = msg;
+    m.phase = PH_FAIL;
+    m.out.st.eta_final = m.eta;
+}
+
+void member_begin_substep(Member& m) {
+    m.tn = std::min(m.t1, m.t + m.dt);
+    for (int c = 0; c < 9; ++c) m.dFbar[c] = m.load(m.tn, c) - m.load(m.t, c);
+    m.phase = PH_INC;
+}
+
+void member_begin_increment(Member& m) {
+    const double t0 = double(m.k - 1) / m.K;
+    m.t1 = double(m.k) / m.K;
+    m.dt = m.t1 - t0;
+    m.t = t0;
+    m.depth = 0;
+    member_begin_substep(m);
+}
+
+// the load step did not converge: restore F, halve the increment
+int member_cutback(Member& m) {
+    combo_ctx* ctx = m.ctx;
+    HIP_OR_FAIL(hipMemcpyAsync(ctx->F_cur.p, ctx->F_save.p, sizeof(double) * 9 * (size_t)ctx->g.n,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    m.out.st.laminate_failures += (long long)(ctx->hs->sums[46]);
+    m.depth += 1;
+    m.out.st.cutbacks += 1;
+    if (m.depth > ctx->opt.max_cutbacks) {
+        member_fail(m, COMBO_E_NOCONV, "load increment " + std::to_string(m.k) + " failed after " +
+                                           std::to_string(ctx->opt.max_cutbacks) + " cutbacks");
+        return COMBO_OK;
+    }
+    m.dt *= 0.5;
+    member_begin_substep(m);
+    return COMBO_OK;
+}
+
+void member_accept_swap(Member& m) {
+    std::swap(m.ctx->F_cur.p, m.ctx->F_trial.p);
+    std::swap(m.ctx->a_prev.p, m.ctx->a_trial.p);
+}
+
+void member_finish(Member& m) {
+    combo_ctx* ctx = m.ctx;
+    const double* sm = ctx->hs->sums;
+    m.out.st.eta_final = m.eta;
+    for (int c = 0; c < 9; ++c) {
+        m.out.Pbar[c] = (sm[c] + sm[9 + c] + sm[19 + c]) / (double)ctx->g.n;
+        const double vp = ctx->n_incl + ctx->sum_c, vm = ctx->n_mat + ((double)ctx->nc - ctx->sum_c);
+        m.out.Pp[c] = vp > 0 ? (sm[9 + c] + sm[28 + c]) / vp : 0.0;
+        m.out.Pm[c] = vm > 0 ? (sm[c] + sm[37 + c]) / vm : 0.0;
+    }
+    m.phase = PH_DONE;
+}
+
+// host decision after the tick's scalars have been read back
+int member_advance(Member& m) {
+    combo_ctx* ctx = m.ctx;
+    combo_stats& S = m.out.st;
+    switch (m.phase) {
+        case PH_INC:
+            if (material_failures(ctx) == 0.0) {
+                member_accept_swap(m);
+                m.it_n = 0;
+                m.phase = PH_RES;
+                return COMBO_OK;
+            }
+            return member_cutback(m);
+        case PH_RES: {
+            double Pbar[9];
+            material_pbar(ctx, Pbar);
+            const double den = (double)ctx->g.n * std::max(frob9(Pbar), 1e-300);
+            m.eta = std::sqrt(std::max(ctx->hs->cg.eta2, 0.0)) / den;
+            if (verbose())
+                fprintf(stderr, "[combo] member %d increment %d t=%.4f newton %d eta %.3e\n", m.index, m.k, m.tn,
+                        m.it_n, m.eta);
+            if (!(m.eta == m.eta)) {
+                member_fail(m, COMBO_E_NUMERIC, "NaN in the equilibrium residual");
+                return COMBO_OK;
+            }
+            if (m.eta <= ctx->opt.tol_newton) {
+                const double* sm = ctx->hs->sums;
+                S.laminate_iters_total += (long long)sm[47];
+                S.laminate_backprojections += (long long)sm[48];
+                S.laminate_iters_max = std::max(S.laminate_iters_max, (int)sm[49]);
+                S.increments_done += 1;
+                m.t = m.tn;
+                if (m.t < m.t1 - 1e-15) {
+                    member_begin_substep(m);
+                } else if (m.k < m.K) {
+                    m.k += 1;
+                    member_begin_increment(m);
+                } else {
+                    member_finish(m);
+                }
+                return COMBO_OK;
+            }
+            if (m.it_n == ctx->opt.max_newton) return member_cutback(m);
+            m.cg_rounds = 0;
+            m.phase = PH_CG;
+            return COMBO_OK;
+        }
+        case PH_CG: {
+            const CGState& cg = ctx->hs->cg;
+            if (!cg.done) {
+                m.cg_rounds += 1;
+                if (m.cg_rounds > ctx->opt.max_cg / 8 + 2) member_fail(m, COMBO_E_NOCONV, "CG did not terminate");
+                return COMBO_OK;
+            }
+            S.cg_iters_total += cg.iter;
+            if (cg.status == 1) {
+                member_fail(m, COMBO_E_NUMERIC, "CG breakdown (<p, A p> is NaN)");
+                return COMBO_OK;
+            }
+            if (cg.status == 3) {
+                // truncated Newton, as in the single solve
+                S.cg_truncations += 1;
+                if (cg.iter == 0) return member_cutback(m);
+            }
+            if (cg.status == 2) {
+                member_fail(m, COMBO_E_NOCONV, "CG did not converge in max_cg iterations");
+                return COMBO_OK;
+            }
+            S.newton_iters += 1;
+            m.s = 1.0;
+            m.h = 0;
+            m.phase = PH_STEP;
+            return COMBO_OK;
+        }
+        case PH_STEP:
+            if (material_failures(ctx) == 0.0) {
+                member_accept_swap(m);
+                m.it_n += 1;
+                m.phase = PH_RES;
+                return COMBO_OK;
+            }
+            m.s *= 0.5;
+            S.step_halvings += 1;
+            m.h += 1;
+            if (m.h > ctx->opt.max_step_halvings) return member_cutback(m);
+            return COMBO_OK;
+        default: return COMBO_OK;
+    }
+}
+
+template <typename T>
+MatArgs<T> member_matargs(const Member& m) {
+    combo_ctx* ctx = m.ctx;
+    MatArgs<T> a{};
+    a.n = ctx->g.n;
+    a.nc = ctx->nc;
+    a.F_old = ctx->F_cur.as<double>();
+    if (m.phase == PH_INC) {
+        a.dF = nullptr;
+        a.s = 0.0;
+        for (int c = 0; c < 9; ++c) a.dFbar[c] = m.dFbar[c];
+    } else {
+        a.dF = ctx->dF.as<double>();
+        a.s = m.s;
+    }
+    a.F_new = ctx->F_trial.as<double>();
+    a.P = ctx->P.as<double>();
+    a.slot = ctx->slot.as<int>();
+    for (int p = 0; p < 2; ++p) {
+        a.mu[p] = ctx->mats[p].mu;
+        a.lam[p] = ctx->mats[p].lambda;
+    }
+    a.comp_vox = ctx->comp_vox.as<int>();
+    a.cc = ctx->comp_c.as<double>();
+    a.NN = ctx->comp_N.as<double>();
+    a.a_prev = ctx->a_prev.as<double>();
+    a.a_out = ctx->a_trial.as<double>();
+    a.warm = ctx->opt.warm_start_laminate ? 1 : 0;
+    a.maxit = ctx->opt.max_laminate;
+    a.Sinv = ctx->Sinv.as<T>();
+    a.sm = ctx->sm.as<T>();
+    a.n1 = ctx->g.n1;
+    a.xm = ctx->g.xm;
+    a.xwbits = ctx->g.xwbits;
+    a.Acomp = ctx->Acomp.as<T>();
+    a.partials = ctx->part1.as<double>();
+    a.partials2 = ctx->part2.as<double>();
+    return a;
+}
+
+// the launches of one tick: increment starts, Newton directions, material
+// updates, residuals (the CG chunk has its own cached plan)
+template <typename T>
+void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
+    hipStream_t s = B->stream;
+    lp.clear();
+    // F_save <- F at the start of a (sub)increment
+    for (Member& m : ms) {
+        if (m.phase != PH_INC) continue;
+        combo_ctx* ctx = m.ctx;
+        void* dst = ctx->F_save.p;
+        const void* src = ctx->F_cur.p;
+        const size_t bytes = sizeof(double) * 9 * (size_t)ctx->g.n;
+        lp.ops.push_back([=](char*) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s); });
+    }
+    // Newton directions dF from the CG solutions (first trial of a step only)
+    {
+        std::vector<ZArgs<double, T>> za;
+        std::vector<YArgs<double>> ya;
+        std::vector<XArgs<double>> xa;
+        std::vector<long long> kz, ky, kx;
+        std::vector<int> nz, ny, nx;
+        for (Member& m : ms) {
+            if (m.phase != PH_STEP || m.h != 0) continue;
+            combo_ctx* ctx = m.ctx;
+            ZArgs<double, T> z = zargs<double, T>(ctx, 1.0, 0.0);
+            z.out = ctx->specA.as<double2>();
+            za.push_back(z);
+            kz.push_back(key2(ctx->g.n3, z.TX));
+            nz.push_back(blocks_z(ctx->g, z.TX));
+            YArgs<double> y = yargs<double>(ctx, ctx->specA.p, ctx->specB.p, false);
+            ya.push_back(y);
+            ky.push_back(key2(ctx->g.n2, y.TX));
+            ny.push_back(blocks_y(ctx->g, y.TX));
+            XArgs<double> x = xargs<double>(ctx);
+            x.in = ctx->specB.as<double2>();
+            x.real_out = ctx->dF.as<double>();
+            xa.push_back(x);
+            kx.push_back(key2(ctx->g.n1, x.R));
+            nx.push_back(blocks_x(ctx->g, x.R));
+        }
+        plan_pass(lp, za, kz, nz, [=](const ZArgs<double, T>& a, const BatchLaunch* bl) {
+            return launch_z<double, T>(Z_INV_PLAIN, a, s, nullptr, bl);
+        });
+        plan_pass(lp, ya, ky, ny,
+                  [=](const YArgs<double>& a, const BatchLaunch* bl) { return launch_y<double>(+1, a, s, bl); });
+        plan_pass(lp, xa, kx, nx, [=](const XArgs<double>& a, const BatchLaunch* bl) {
+            return launch_x<double>(X_INV_REAL, a, s, nullptr, bl);
+        });
+    }
+    // material law at the trial fields
+    {
+        std::vector<MatArgs<T>> ma;
+        std::vector<MatReduceArgs> red;
+        std::vector<TileMap> mp, ml;
+        for (Member& m : ms) {
+            if (m.phase != PH_INC && m.phase != PH_STEP) continue;
+            combo_ctx* ctx = m.ctx;
+            const int i = (int)ma.size();
+            ma.push_back(member_matargs<T>(m));
+            const int nbp = material_blocks_pure(ctx->g.n);
+            const int nbl = ctx->nc > 0 ? material_blocks_laminate(ctx->nc) : 0;
+            for (int t = 0; t < nbp; ++t) mp.push_back(TileMap{i, t, nbp});
+            for (int t = 0; t < nbl; ++t) ml.push_back(TileMap{i, t, nbl});
+            red.push_back(MatReduceArgs{ctx->part1.as<double>(), nbp, ctx->part2.as<double>(), nbl,
+                                        ctx->sums.as<double>()});
+            ctx->state_prec = sizeof(T) == 4 ? COMBO_MIXED : COMBO_FP64;
+        }
+        if (!ma.empty()) {
+            const size_t aoff = lp.put(ma.data(), sizeof(MatArgs<T>) * ma.size());
+            const size_t poff = lp.put(mp.data(), sizeof(TileMap) * mp.size());
+            const size_t loff = lp.put(ml.data(), sizeof(TileMap) * ml.size());
+            const size_t roff = lp.put(red.data(), sizeof(MatReduceArgs) * red.size());
+            const int np = (int)mp.size(), nl = (int)ml.size(), nr = (int)red.size();
+            lp.ops.push_back([=](char* base) -> hipError_t {
+                BatchLaunch pure{nullptr, reinterpret_cast<const TileMap*>(base + poff), np};
+                BatchLaunch lam{nullptr, reinterpret_cast<const TileMap*>(base + loff), nl};
+                return launch_material_batch<T>(reinterpret_cast<const MatArgs<T>*>(base + aoff), pure, lam,
+                                                reinterpret_cast<const MatReduceArgs*>(base + roff), nr, s);
+            });
+        }
+    }
+    // residuals: FP64 forward passes of P, right-hand sides, eta
+    {
+        std::vector<XArgs<double>> xa;
+        std::vector<YArgs<double>> ya;
+        std::vector<ZArgs<double, T>> za;
+        std::vector<UArgs<T>> ua;
+        std::vector<FinArgs> fa;
+        std::vector<long long> kx, ky, kz, ku;
+        std::vector<int> nx, ny, nz, nu;
+        for (Member& m : ms) {
+            if (m.phase != PH_RES) continue;
+            combo_ctx* ctx = m.ctx;
+            XArgs<double> x = xargs<double>(ctx);
+            x.real_in = ctx->P.as<double>();
+            x.out = ctx->specA.as<double2>();
+            xa.push_back(x);
+            kx.push_back(key2(ctx->g.n1, x.R));
+            nx.push_back(blocks_x(ctx->g, x.R));
+            YArgs<double> y = yargs<double>(ctx, ctx->specA.p, ctx->specB.p, false);
+            ya.push_back(y);
+            ky.push_back(key2(ctx->g.n2, y.TX));
+            ny.push_back(blocks_y(ctx->g, y.TX));
+            ZArgs<double, T> z = zargs<double, T>(ctx, m.mu0, m.kappa0);
+            z.in = ctx->specB.as<double2>();
+            za.push_back(z);
+            kz.push_back(key2(ctx->g.n3, z.TX));
+            const int nbz = blocks_z(ctx->g, z.TX);
+            nz.push_back(nbz);
+            ua.push_back(uargs<T>(ctx, m.mu0, m.kappa0));
+            ku.push_back(0);
+            nu.push_back(blocks_antiherm(ctx->g));
+            fa.push_back(finargs(ctx, ctx->part1.as<double>(), ctx->part2.as<double>(), nbz, m.tol_cg * m.tol_cg,
+                                 ctx->opt.max_cg));
+        }
+        plan_pass(lp, xa, kx, nx, [=](const XArgs<double>& a, const BatchLaunch* bl) {
+            return launch_x<double>(X_FWD_REAL, a, s, nullptr, bl);
+        });
+        plan_pass(lp, ya, ky, ny,
+                  [=](const YArgs<double>& a, const BatchLaunch* bl) { return launch_y<double>(-1, a, s, bl); });
+        plan_pass(lp, za, kz, nz, [=](const ZArgs<double, T>& a, const BatchLaunch* bl) {
+            return launch_z<double, T>(Z_RHS, a, s, nullptr, bl);
+        });
+        plan_pass(lp, ua, ku, nu, [=](const UArgs<T>& a, const BatchLaunch* bl) { return launch_antiherm<T>(a, s, bl); });
+        plan_finalize(lp, FIN_RHS, fa, s);
+    }
+}
+
+// one CG iteration over the members listed (8 launches per kernel shape)
+template <typename T>
+void plan_cg(combo_batch* B, std::vector<Member>& ms, const std::vector<int>& list, LaunchPlan& lp) {
+    hipStream_t s = B->stream;
+    lp.clear();
+    std::vector<ZArgs<T, T>> zi, zf;
+    std::vector<YArgs<T>> yi, yf;
+    std::vector<XArgs<T>> xa;
+    std::vector<UArgs<T>> ua;
+    std::vector<FinArgs> fal, fbe;
+    std::vector<long long> kz, ky, kx, ku;
+    std::vector<int> nz, ny, nx, nu;
+    for (int i : list) {
+        Member& m = ms[i];
+        combo_ctx* ctx = m.ctx;
+        ZArgs<T, T> z = zargs<T, T>(ctx, m.mu0, m.kappa0);
+        z.out = ctx->specA.as<cpx<T>>();
+        zi.push_back(z);
+        z.in = ctx->specB.as<cpx<T>>();
+        z.out = nullptr;
+        zf.push_back(z);
+        kz.push_back(key2(ctx->g.n3, z.TX));
+        const int nbz = blocks_z(ctx->g, z.TX);
+        nz.push_back(nbz);
+        YArgs<T> yv = yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true);
+        yi.push_back(yv);
+        yf.push_back(yv);
+        ky.push_back(key2(ctx->g.n2, yv.TX));
+        ny.push_back(blocks_y(ctx->g, yv.TX));
+        XArgs<T> x = xargs<T>(ctx);
+        x.in = ctx->specB.as<cpx<T>>();
+        x.out = ctx->specA.as<cpx<T>>();
+        xa.push_back(x);
+        kx.push_back(key2(ctx->g.n1, x.R));
+        nx.push_back(blocks_x(ctx->g, x.R));
+        ua.push_back(uargs<T>(ctx, m.mu0, m.kappa0));
+        ku.push_back(0);
+        const int nbu = blocks_u(ctx->g);
+        nu.push_back(nbu);
+        fal.push_back(finargs(ctx, ctx->part1.as<double>(), nullptr, nbz));
+        fbe.push_back(finargs(ctx, ctx->part2.as<double>(), nullptr, nbu));
+    }
+    plan_pass(lp, zi, kz, nz,
+              [=](const ZArgs<T, T>& a, const BatchLaunch* bl) { return launch_z<T, T>(Z_INV_CG, a, s, nullptr, bl); });
+    plan_pass(lp, yi, ky, ny, [=](const YArgs<T>& a, const BatchLaunch* bl) { return launch_y<T>(+1, a, s, bl); });
+    plan_pass(lp, xa, kx, nx,
+              [=](const XArgs<T>& a, const BatchLaunch* bl) { return launch_x<T>(X_CG, a, s, nullptr, bl); });
+    plan_pass(lp, yf, ky, ny, [=](const YArgs<T>& a, const BatchLaunch* bl) { return launch_y<T>(-1, a, s, bl); });
+    plan_pass(lp, zf, kz, nz,
+              [=](const ZArgs<T, T>& a, const BatchLaunch* bl) { return launch_z<T, T>(Z_CG, a, s, nullptr, bl); });
+    plan_finalize(lp, FIN_ALPHA, fal, s);
+    plan_pass(lp, ua, ku, nu, [=](const UArgs<T>& a, const BatchLaunch* bl) { return launch_update<T>(a, s, nullptr, bl); });
+    plan_finalize(lp, FIN_BETA, fbe, s);
+}
+
+template <typename T>
+int batch_solve_impl(combo_batch* B, std::vector<Member>& ms) {
+    const size_t stride = combo_batch::kScalStride;
+    const size_t nm = ms.size();
+    LaunchPlan tick, cgp;
+    std::vector<int> cg_list, cg_prev;
+    bool cg_valid = false;
+    const int chunk = 8;
+    for (;;) {
+        bool active = false;
+        for (Member& m : ms) active = active || (m.phase != PH_DONE && m.phase != PH_FAIL);
+        if (!active) break;
+        plan_tick<T>(B, ms, tick);
+        BHIP_OR_FAIL(tick.upload());
+        cg_list.clear();
+        for (size_t i = 0; i < nm; ++i)
+            if (ms[i].phase == PH_CG) cg_list.push_back((int)i);
+        if (!cg_list.empty() && (!cg_valid || cg_list != cg_prev)) {
+            plan_cg<T>(B, ms, cg_list, cgp);
+            BHIP_OR_FAIL(cgp.upload());
+            cg_prev = cg_list;
+            cg_valid = true;
+        }
+        BHIP_OR_FAIL(tick.run());
+        if (!cg_list.empty())
+            for (int k = 0; k < chunk; ++k) BHIP_OR_FAIL(cgp.run());
+        BHIP_OR_FAIL(hipMemcpyAsync(B->hscal, B->scal.p, stride * nm, hipMemcpyDeviceToHost, B->stream));
+        BHIP_OR_FAIL(hipStreamSynchronize(B->stream));
+        for (size_t i = 0; i < nm; ++i) {
+            Member& m = ms[i];
+            if (m.phase == PH_DONE || m.phase == PH_FAIL) continue;
+            const char* src = B->hscal + i * stride;
+            memcpy(&m.ctx->hs->cg, src, sizeof(CGState));
+            memcpy(m.ctx->hs->sums, src + combo_batch::kScalSums, sizeof(double) * kSumsLen);
+            int st = member_advance(m);
+            if (st) {
+                member_fail(m, st, m.ctx->err);
+            }
+        }
+    }
+    return COMBO_OK;
+}
+
+const char* options_error(const combo_options* o) {
+    if (o->precision != COMBO_FP64 && o->precision != COMBO_MIXED) return "precision must be COMBO_FP64 or COMBO_MIXED";
+    if (!(o->tol_newton > 0) || !(o->tol_cg > 0) || o->max_newton < 0 || o->max_cg < 1 || o->max_laminate < 0 ||
+        o->max_laminate > 64 || o->n_increments < 1 || o->max_step_halvings < 0 || o->max_cutbacks < 0 ||
+        o->graph_chunk < 0 || o->graph_chunk > 256)
+        return "option out of range";
+    return nullptr;
 }
 
 int require_ready(combo_ctx* ctx) {
@@ -910,12 +1475,8 @@ int combo_set_materials(combo_ctx* ctx, const combo_material mats[2]) {
 
 int combo_set_options(combo_ctx* ctx, const combo_options* o) {
     if (!ctx || !o) return COMBO_E_INVAL;
-    if (o->precision != COMBO_FP64 && o->precision != COMBO_MIXED)
-        return set_err(ctx, COMBO_E_INVAL, "precision must be COMBO_FP64 or COMBO_MIXED");
-    if (!(o->tol_newton > 0) || !(o->tol_cg > 0) || o->max_newton < 0 || o->max_cg < 1 || o->max_laminate < 0 ||
-        o->max_laminate > 64 || o->n_increments < 1 || o->max_step_halvings < 0 || o->max_cutbacks < 0 ||
-        o->graph_chunk < 0 || o->graph_chunk > 256)
-        return set_err(ctx, COMBO_E_INVAL, "option out of range");
+    const char* bad = options_error(o);
+    if (bad) return set_err(ctx, COMBO_E_INVAL, bad);
     ctx->opt = *o;
     for (auto& gr : ctx->graph) gr.reset();
     return COMBO_OK;
@@ -1241,6 +1802,183 @@ int combo_profile_read(combo_ctx* ctx, int kernel, double* ms_total, long long* 
     prof_harvest(ctx);
     if (ms_total) *ms_total = ctx->prof_ms[kernel];
     if (launches) *launches = ctx->prof_n[kernel];
+    return COMBO_OK;
+}
+
+// ---- batches ------------------------------------------------------------------
+int combo_batch_create(combo_batch** out, int device, void* stream) {
+    if (!out) return COMBO_E_INVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return COMBO_E_HIP;
+    if (device < 0 || device >= count) return COMBO_E_INVAL;
+    if (hipSetDevice(device) != hipSuccess) return COMBO_E_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return COMBO_E_HIP;
+    if (std::string(prop.gcnArchName).find("gfx950") == std::string::npos) return COMBO_E_HIP;
+    combo_batch* b = new combo_batch();
+    b->device = device;
+    if (stream) {
+        b->stream = static_cast<hipStream_t>(stream);
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return COMBO_E_HIP;
+        }
+        b->own_stream = true;
+    }
+    combo_default_options(&b->opt);
+    *out = b;
+    return COMBO_OK;
+}
+
+int combo_batch_destroy(combo_batch* b) {
+    if (!b) return COMBO_E_INVAL;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    for (combo_ctx* m : b->members) combo_destroy(m);
+    b->members.clear();
+    b->scal.release();
+    if (b->hscal) (void)hipHostFree(b->hscal);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return COMBO_OK;
+}
+
+const char* combo_batch_last_error(const combo_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+int combo_batch_size(const combo_batch* b) { return b ? (int)b->members.size() : 0; }
+
+int combo_batch_set_options(combo_batch* b, const combo_options* o) {
+    if (!b || !o) return COMBO_E_INVAL;
+    const char* bad = options_error(o);
+    if (bad) return bset_err(b, COMBO_E_INVAL, bad);
+    b->opt = *o;
+    for (combo_ctx* m : b->members) combo_set_options(m, o);
+    return COMBO_OK;
+}
+
+int combo_batch_add(combo_batch* b, int n1, int n2, int n3, double l1, double l2, double l3,
+                    const combo_material mats[2], const uint8_t* phase, const double* c, const double* N, int mem_kind,
+                    int* index) {
+    if (!b) return COMBO_E_INVAL;
+    if (!mats) return bset_err(b, COMBO_E_INVAL, "materials are null");
+    combo_ctx* m = nullptr;
+    int st = combo_create(&m, b->device, b->stream);
+    if (st) return bset_err(b, st, "member context creation failed");
+    st = combo_set_grid(m, n1, n2, n3, l1, l2, l3);
+    if (!st) st = combo_set_materials(m, mats);
+    if (!st) st = combo_set_options(m, &b->opt);
+    if (!st) st = combo_set_microstructure(m, phase, c, N, mem_kind);
+    if (st) {
+        bset_err(b, st, "member " + std::to_string(b->members.size()) + ": " + m->err);
+        combo_destroy(m);
+        return st;
+    }
+    if (index) *index = (int)b->members.size();
+    b->members.push_back(m);
+    return COMBO_OK;
+}
+
+int combo_batch_solve(combo_batch* B, const double* Fbar, const int* n_increments, double* Pbar, double* Abar,
+                      double* Pbar_phase, combo_stats* stats) {
+    if (!B) return COMBO_E_INVAL;
+    const size_t nm = B->members.size();
+    if (stats) memset(stats, 0, sizeof(combo_stats) * nm);
+    if (nm == 0) return bset_err(B, COMBO_E_STATE, "the batch has no members");
+    if (!Fbar) return bset_err(B, COMBO_E_INVAL, "Fbar is null");
+    for (size_t i = 0; i < nm; ++i) {
+        const std::string who = "member " + std::to_string(i) + ": ";
+        if (!finite9(Fbar + 9 * i)) return bset_err(B, COMBO_E_NUMERIC, who + "Fbar is not finite");
+        if (!(det9(Fbar + 9 * i) > 0.0)) return bset_err(B, COMBO_E_INADMISSIBLE, who + "det Fbar <= 0");
+        if (n_increments && n_increments[i] < 1) return bset_err(B, COMBO_E_INVAL, who + "n_increments < 1");
+    }
+    BHIP_OR_FAIL(hipSetDevice(B->device));
+    const auto t_start = clk::now();
+    const size_t stride = combo_batch::kScalStride;
+    if (B->scal.bytes < stride * nm) {
+        BHIP_OR_FAIL(B->scal.ensure(stride * nm));
+        if (B->hscal) (void)hipHostFree(B->hscal);
+        B->hscal = nullptr;
+        BHIP_OR_FAIL(hipHostMalloc((void**)&B->hscal, stride * nm, hipHostMallocDefault));
+        B->hscal_bytes = stride * nm;
+    }
+    std::vector<Member> ms(nm);
+    for (size_t i = 0; i < nm; ++i) {
+        Member& m = ms[i];
+        combo_ctx* ctx = B->members[i];
+        m.ctx = ctx;
+        m.index = (int)i;
+        char* base = static_cast<char*>(B->scal.p) + i * stride;
+        ctx->cgst.borrow(base, sizeof(CGState));
+        ctx->sums.borrow(base + combo_batch::kScalSums, sizeof(double) * (kSumsLen + 16));
+        for (int c = 0; c < 9; ++c) {
+            m.Fbar[c] = Fbar[9 * i + c];
+            m.Fbar0[c] = (c % 4 == 0) ? 1.0 : 0.0;
+        }
+        m.K = n_increments ? n_increments[i] : std::max(1, ctx->opt.n_increments);
+        reference_medium(ctx, m.mu0, m.kappa0);
+        m.tol_cg = ctx->opt.tol_cg;
+        if (ctx->opt.precision == COMBO_MIXED) m.tol_cg = std::max(m.tol_cg, 1e-5);
+        const long long n = ctx->g.n;
+        hipLaunchKernelGGL(k_fill_identity, dim3(1024), dim3(256), 0, B->stream, ctx->F_cur.as<double>(), n);
+        BHIP_OR_FAIL(hipGetLastError());
+        BHIP_OR_FAIL(hipMemsetAsync(ctx->a_prev.p, 0, sizeof(double) * 3 * std::max(ctx->nc, 1), B->stream));
+        hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, B->stream, ctx->cgst.as<CGState>());
+        BHIP_OR_FAIL(hipGetLastError());
+        m.k = 1;
+        member_begin_increment(m);
+    }
+    int st = B->opt.precision == COMBO_MIXED ? batch_solve_impl<float>(B, ms) : batch_solve_impl<double>(B, ms);
+    if (st) return st;
+    // effective tangents, member by member
+    for (Member& m : ms) {
+        if (m.phase != PH_DONE || !B->opt.want_tangent || !Abar) continue;
+        int it = 0;
+        auto tt = clk::now();
+        int s2 = B->opt.precision == COMBO_MIXED
+                     ? effective_tangent<float>(m.ctx, m.mu0, m.kappa0, m.tol_cg, m.out.Abar_store, it)
+                     : effective_tangent<double>(m.ctx, m.mu0, m.kappa0, m.tol_cg, m.out.Abar_store, it);
+        m.out.st.time_ms_tangent = ms_since(tt);
+        m.out.st.cg_iters_tangent = it;
+        if (s2) member_fail(m, s2, m.ctx->err);
+    }
+    BHIP_OR_FAIL(hipStreamSynchronize(B->stream));
+    const double wall = ms_since(t_start);
+    int first = COMBO_OK;
+    for (size_t i = 0; i < nm; ++i) {
+        Member& m = ms[i];
+        m.out.st.status = m.phase == PH_DONE ? COMBO_OK : m.status;
+        m.out.st.time_ms_total = wall;
+        if (stats) stats[i] = m.out.st;
+        if (m.phase != PH_DONE) {
+            if (first == COMBO_OK) {
+                first = m.status;
+                B->err = "member " + std::to_string(i) + ": " + m.ctx->err;
+            }
+            continue;
+        }
+        if (Pbar) memcpy(Pbar + 9 * i, m.out.Pbar, sizeof(m.out.Pbar));
+        if (Pbar_phase) {
+            memcpy(Pbar_phase + 18 * i, m.out.Pp, sizeof(m.out.Pp));
+            memcpy(Pbar_phase + 18 * i + 9, m.out.Pm, sizeof(m.out.Pm));
+        }
+        if (Abar && B->opt.want_tangent) memcpy(Abar + 81 * i, m.out.Abar_store, sizeof(m.out.Abar_store));
+    }
+    return first;
+}
+
+int combo_batch_fields(combo_batch* B, int i, double* F, double* P, int mem_kind) {
+    if (!B) return COMBO_E_INVAL;
+    if (i < 0 || i >= (int)B->members.size()) return bset_err(B, COMBO_E_INVAL, "member index out of range");
+    if (mem_kind != COMBO_MEM_HOST && mem_kind != COMBO_MEM_DEVICE) return bset_err(B, COMBO_E_INVAL, "bad mem_kind");
+    combo_ctx* ctx = B->members[i];
+    BHIP_OR_FAIL(hipSetDevice(B->device));
+    const size_t f9 = sizeof(double) * 9 * (size_t)ctx->g.n;
+    int st = COMBO_OK;
+    if (F && (st = copy_out(ctx, F, ctx->F_cur.p, f9, mem_kind))) return bset_err(B, st, ctx->err);
+    if (P && (st = copy_out(ctx, P, ctx->P.p, f9, mem_kind))) return bset_err(B, st, ctx->err);
+    BHIP_OR_FAIL(hipStreamSynchronize(B->stream));
     return COMBO_OK;
 }
 

@@ -118,7 +118,8 @@ def test_law_backprojection_cases_match_oracle(ctx):
                                  ((128, 32, 4), (1.0, 1.0, 1.0)), ((64, 64, 32), (1.0, 0.7, 1.0)),
                                  ((9, 256, 2), (1.0, 1.0, 1.0)), ((6, 4, 256), (0.5, 1.0, 3.0)),
                                  ((12, 128, 64), (1.0, 1.0, 1.0)), ((384, 2, 2), (1.0, 1.0, 1.0)),
-                                 ((192, 3, 2), (1.0, 1.0, 1.0))])
+                                 ((192, 3, 2), (1.0, 1.0, 1.0)), ((12, 48, 96), (1.0, 1.0, 1.0)),
+                                 ((6, 96, 48), (1.0, 2.0, 1.0))])
 @pytest.mark.parametrize("which", [combo.COMBO_GREEN_GAMMA0, combo.COMBO_GREEN_G])
 def test_green_operators_match_oracle(ctx, n, l, which):
     rng = np.random.default_rng(11)
@@ -137,7 +138,7 @@ def test_green_operators_match_oracle(ctx, n, l, which):
     assert rel(out32, ref) <= 2e-6
 
 
-@pytest.mark.parametrize("n", [(12, 9, 8), (64, 32, 16), (256, 4, 8), (48, 64, 32)])
+@pytest.mark.parametrize("n", [(12, 9, 8), (64, 32, 16), (256, 4, 8), (48, 64, 32), (48, 48, 48), (12, 96, 96)])
 @pytest.mark.parametrize("precision,tol", [(combo.COMBO_FP64, 1e-11), (combo.COMBO_MIXED, 3e-6)])
 def test_cg_operator_matches_oracle(ctx, precision, tol, n):
     ms = synth.random_composite_field(n, 5, frac_composite=0.3)
@@ -222,6 +223,26 @@ def test_increments_match_oracle(ctx):
     r = combo.combo_solve(ctx, synth.stretch(0.2))
     assert r["stats"]["increments_done"] == 4
     assert rel(r["Pbar"], ref["Pbar"]) <= 1e-8
+
+
+NEGCURV_FBAR = np.eye(3) - 0.05 * np.array([[1.0, 0.3, 0.0], [0.2, -0.5, 0.0], [0.0, 0.0, 0.2]])
+
+
+def test_negative_curvature_truncated_newton_matches_oracle(ctx):
+    """Stiff sphere, 5 % compression in one increment: CG meets negative
+    curvature at the predictor and the Newton step is truncated."""
+    ms = synth.single_sphere((8, 8, 8), radius=0.3, center=(0.05, -0.02, 0.03))
+    mats = synth.contrast_mats(100.0)
+    ref = osol.solve(oracle_problem(ms, mats), NEGCURV_FBAR, osol.Options(tol_newton=1e-11, tol_cg=1e-12))
+    assert ref["stats"]["cg_truncations"] >= 1
+    setup(ctx, ms, mats, tol_newton=1e-11, tol_cg=1e-12)
+    r = combo.combo_solve(ctx, NEGCURV_FBAR)
+    assert r["stats"]["cg_truncations"] >= 1
+    assert rel(r["Pbar"], ref["Pbar"]) <= 1e-8
+    setup(ctx, ms, mats, tol_newton=1e-8, tol_cg=1e-6, precision=combo.COMBO_MIXED)
+    rm = combo.combo_solve(ctx, NEGCURV_FBAR)
+    assert rm["stats"]["cg_truncations"] >= 1
+    assert rel(rm["Pbar"], ref["Pbar"]) <= 1e-6
 
 
 def test_error_paths(ctx):

@@ -184,3 +184,45 @@ def test_failure_injection():
     with pytest.raises(solver.SolveError) as e:
         solver.solve(problem(ms), FBAR, solver.Options(max_cg=1))
     assert e.value.status == solver.E_NOCONV
+
+
+# stiff sphere under 5 % compression: the homogeneous predictor loads the
+# inclusion at the uniform-strain stress, where the tangent is indefinite on
+# compatible fields (CG meets <p, q> < 0 at the first Newton step)
+NEGCURV_MATS = synth.contrast_mats(100.0)
+NEGCURV_FBAR = np.eye(3) - 0.05 * np.array([[1.0, 0.3, 0.0], [0.2, -0.5, 0.0], [0.0, 0.0, 0.2]])
+
+
+def test_predictor_tangent_is_indefinite_on_compatible_fields():
+    """The negative curvature CG meets is real: a compatible field with
+    <p, Gamma0[A:p]> < 0 exists at the predictor, and is gone at equilibrium."""
+    ms = _sphere8()
+    prob = problem(ms, NEGCURV_MATS)
+    mu0, kappa0 = solver.reference_medium(NEGCURV_MATS)
+    F = np.broadcast_to(NEGCURV_FBAR[:, :, None, None, None], (3, 3) + tuple(prob.shape)).copy()
+    P, Av, ok, _, _ = solver.evaluate(F, prob)
+    b = -solver.spectral.apply_gamma0(P, prob.n, prob.l, mu0, kappa0)
+    with pytest.raises(solver.NegativeCurvature) as e:
+        solver.cg(Av, b, prob, mu0, kappa0, 1e-12, 500)
+    assert e.value.it > 0
+    # energy second variation of the direction that failed, straight from the law:
+    # sum_x dF : A : dF over the compatible field dF (a Rayleigh quotient of A itself)
+    r = solver.solve(prob, NEGCURV_FBAR, solver.Options(tol_newton=1e-12, tol_cg=1e-12))
+    assert r["stats"]["cg_truncations"] >= 1
+    _, Av2, _, _, _ = solver.evaluate(r["F"], prob)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        p = solver.spectral.apply_g(rng.normal(size=(3, 3) + tuple(prob.shape)), prob.n, prob.l)
+        assert float(np.sum(p * solver.apply_tangent(Av2, p, prob.shape))) > 0.0
+
+
+def test_truncated_newton_reaches_the_path_independent_equilibrium():
+    """One increment (CG truncated at negative curvature) and ten increments
+    (the stable path) end in the same equilibrium."""
+    ms = _sphere8()
+    prob = problem(ms, NEGCURV_MATS)
+    r1 = solver.solve(prob, NEGCURV_FBAR, solver.Options(tol_newton=1e-12, tol_cg=1e-12))
+    r10 = solver.solve(prob, NEGCURV_FBAR, solver.Options(tol_newton=1e-12, tol_cg=1e-12, n_increments=10))
+    assert r1["stats"]["cg_truncations"] >= 1
+    assert np.abs(r1["Pbar"] - r10["Pbar"]).max() <= 1e-10 * np.abs(r10["Pbar"]).max()
+    assert np.abs(r1["F"] - r10["F"]).max() <= 1e-9
