@@ -46,6 +46,26 @@ def kernel_bytes(name, n, nspec, nc, s):
     return table.get(name)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of a CG kernel class from the committed PMC record
+    (FETCH_SIZE / WRITE_SIZE scaled by a plain-copy calibration), or None if the
+    record is missing or the kernel sources changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_spheres_256_mixed.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
+        return rec["kernels"][kernel]["traffic_bytes"]
+    except (OSError, ValueError, KeyError, AttributeError):
+        return None
+
+
 def cpu_cores_used(cpu_s, wall_s):
     return max(1, int(round(cpu_s / max(wall_s, 1e-9))))
 
@@ -79,6 +99,68 @@ def cpu_baseline(ms, lc, sub=128, iters=3):
                                                                              or platform.machine())}
 
 
+def batch_bench(combo, synth, steps):
+    """The many-RVE workload: 64 RVEs of 32^3..96^3 in one batch, against the same
+    RVEs solved one after another on one context each (setup excluded)."""
+    import torch
+    t = time.time()
+    items = synth.workload_batch()
+    log("batch workload generated in %.1f s: %d RVEs, %d voxels" % (time.time() - t, len(items),
+                                                                    sum(ms.nvox for ms, _ in items)))
+    o = combo.combo_default_options()
+    o.precision = combo.COMBO_MIXED
+    o.tol_newton = 1e-6
+    o.tol_cg = 1e-4
+    o.max_cg = 20000
+    b = combo.combo_batch_create(0)
+    combo.combo_batch_set_options(b, o)
+    for ms, lc in items:
+        combo.combo_batch_add(b, ms.n, ms.l, lc.mats, ms.phase, ms.c, ms.N)
+    Fb = np.stack([lc.Fbar for _, lc in items])
+    K = [lc.n_increments for _, lc in items]
+    nv = [ms.nvox for ms, _ in items]
+    combo.combo_batch_solve(b, Fb, n_increments=K)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = combo.combo_batch_solve(b, Fb, n_increments=K)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    cg = [s["cg_iters_total"] for s in r["stats"]]
+    vox_it = sum(n * c for n, c in zip(nv, cg))
+    combo.combo_batch_destroy(b)
+    # the same members one at a time
+    ctxs = []
+    for ms, lc in items:
+        c = combo.combo_create(0)
+        combo.combo_set_grid(c, *ms.n, *ms.l)
+        combo.combo_set_materials(c, lc.mats)
+        combo.combo_set_microstructure(c, ms.phase, ms.c, ms.N)
+        oo = combo.combo_default_options()
+        for k, _ in o._fields_:
+            setattr(oo, k, getattr(o, k))
+        oo.n_increments = lc.n_increments
+        combo.combo_set_options(c, oo)
+        ctxs.append(c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_it = 0
+    for c, (ms, lc) in zip(ctxs, items):
+        rr = combo.combo_solve(c, lc.Fbar)
+        seq_it += ms.nvox * rr["stats"]["cg_iters_total"]
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    for c in ctxs:
+        combo.combo_destroy(c)
+    log("batch: %.3f s (%.3e voxel-CG-iters/s), one by one: %.3f s" % (wall, vox_it / wall, seq))
+    return {"workload": "64 RVEs, grids from {32,48,64,96}^3, 5-30 spheres or aligned cylinders each, contrast "
+                        "10^U[1,3], |Fbar-I|<=0.1, 1-5 increments, mixed precision, eta<=1e-6, tol_cg 1e-4",
+            "n_rve": len(items), "voxels": int(sum(nv)), "value": vox_it / wall, "unit": "voxel-CG-iters/s",
+            "time_s": wall, "cg_iters": int(sum(cg)), "newton_iters": int(sum(s["newton_iters"] for s in r["stats"])),
+            "cg_truncations": int(sum(s["cg_truncations"] for s in r["stats"])),
+            "one_by_one_time_s": seq, "one_by_one_value": seq_it / seq, "speedup_vs_one_by_one": seq / wall}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +172,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--increments", type=int, default=0,
+                    help="override the workload's load increments (shorter runs for counter collection)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -99,8 +186,18 @@ def main():
     import torch
     from paper_2204_13624_amd import combo, synth
 
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     t = time.time()
     ms, lc = synth.workload_spheres_256(args.n)
+    if args.increments > 0:
+        lc.n_increments = args.increments
     log("workload generated in %.1f s: n=%d, composites=%d, c=%.4f" % (time.time() - t, ms.nvox, ms.n_composite,
                                                                        ms.info["c_total"]))
     assert torch.cuda.is_available()
@@ -166,8 +263,9 @@ def main():
     if cg_kernels:
         dom = max(cg_kernels, key=lambda k: cg_kernels[k]["ms_total"])
         ach = cg_kernels[dom]["GBps"]
+        traffic = measured_traffic(dom) if args.n == 256 else None
         roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": cg_kernels[dom]["bytes_per_launch"], "avg_us": cg_kernels[dom]["avg_us"]}
     b_cg = sum(kernel_bytes(k, n, nspec, nc, 4) for k in
                ("xpass_cg", "ypass_inv", "ypass_fwd", "zpass_inv", "zpass_fwd", "cg_update")) / n
@@ -207,6 +305,7 @@ def main():
                                                    np.abs(r64["Pbar"]).max())
         log("fp64: %.2f s, cg %d" % (out["time_to_solution_s"]["fp64"], r64["stats"]["cg_iters_total"]))
     combo.combo_destroy(ctx)
+    out["batch"] = None if args.no_batch else batch_bench(combo, synth, args.steps)
     if not args.no_cpu:
         t = time.time()
         out["cpu_baseline"] = cpu_baseline(ms, lc)
