@@ -352,7 +352,7 @@ __device__ __forceinline__ void k_xwave_body(const XArgs<T>& a, int tile_, int n
 #pragma unroll
             for (int c = 0; c < 9; ++c) tau[c] = p[c];
         } else {
-            tangent_apply<T>(a.ts, row * L + lane + W * sl, p, tau);
+            tangent_apply<T>(a.ts, a.g.xwbits >= 0 ? row * L + lane + W * sl : vox, p, tau);
         }
         if (MODE == X_AVG) {
             if (live)
@@ -409,6 +409,229 @@ __global__ void __launch_bounds__(256) k_xwave_b(const XArgs<T>* __restrict__ as
 }
 
 // (M, W) of the wavefront x pass for a row length n1, or M = 0 if unsupported
+// ------------------------------------------------------------------------------
+// x pass, two-stage version (CG operator and averaged tangent): a workgroup takes
+// R rows; the five packed sequences of its rows are 5R "columns" of an
+// L = P * Q two-stage transform (size-Q DFT in registers, twiddles, one LDS
+// exchange, size-P DFT in registers; fft_reg.h).  Between the inverse and the
+// forward transform the real rows sit in LDS, where the tangent acts voxel by
+// voxel with the state read in natural order.  Column t = s R + r (sequence s,
+// row r); a stage-A item (t, j1) holds x[j1 + P j2], a stage-B item (t, k1)
+// holds X[k1 + Q k2], and the forward stage A starts from the LDS rows.
+// ------------------------------------------------------------------------------
+template <int P, int Q>
+struct XLdsShape {
+    static constexpr int L = P * Q;
+    static constexpr int NT = P > Q ? P : Q;    // threads per column
+    static constexpr int R = 256 / (5 * NT);    // rows per workgroup
+    static constexpr int TX = 5 * R;            // columns
+    static constexpr int QP = Q + 1;            // padded stage-A row (LDS banks)
+    static constexpr int LP = L + 1;            // padded natural row
+    static constexpr int EXA = TX * P * QP;     // complex elements of the exchange
+    static constexpr int EXN = TX * LP;         // complex elements of the natural rows
+};
+
+constexpr int cmax3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
+
+template <typename T, int MODE, int P, int Q>
+__device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int ntiles_) {
+    using C = cpx<T>;
+    using S = XLdsShape<P, Q>;
+    constexpr int L = S::L, R = S::R, TX = S::TX, QP = S::QP, LP = S::LP;
+    constexpr int FLD = (10 * R * L * (int)sizeof(T) + (int)sizeof(C) - 1) / (int)sizeof(C);
+    constexpr int BUFC = cmax3(S::EXA, S::EXN, FLD);
+    if (MODE == X_CG && a.st->done) return;
+    __shared__ C buf[BUFC];   // exchange, natural rows and real rows in turn
+    __shared__ C tw[L];
+    __shared__ double red[16];
+    T* fld = reinterpret_cast<T*>(buf);   // real rows [9][R][L] and a sink row block
+    const int tid = threadIdx.x;
+    const int nh = a.g.nh;
+    const long long nspec = a.g.nspec;
+    const long long nrows = (long long)a.g.n2 * a.g.n3;
+    const long long row0 = (long long)tile_ * R;
+    const T xs1 = T(a.g.xs1);
+    for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
+    const int t = tid / S::NT, j = tid % S::NT;   // column and item index of this thread
+    const bool col_ok = t < TX;
+    const int s = col_ok ? t / R : 0, r = col_ok ? t % R : 0;
+    const long long row = row0 + r;
+    const bool live = col_ok && row < nrows;
+    const int ca = 2 * s, cb = 2 * s + 1;
+    __syncthreads();
+
+    // ---- inverse: half spectra -> packed complex rows z = a + i b -> real rows.
+    // Branch-free so that all loads of an item are in flight together: the fifth
+    // sequence (one component) reads its component twice and scales the copy by
+    // 0, and invalid bins read bin 0 of the row and scale it by 0.
+    T* fa = fld + (ca * R + r) * L;
+    T* fb = fld + ((s < 4 ? cb : 9) * R + r) * L;   // row 9 of fld is a write-only sink
+    if (col_ok && j < P) {
+        const long long rowc = live ? row : 0;
+        const C* pa = a.in + ca * nspec + rowc * nh;
+        const C* pb = a.in + (s < 4 ? cb : ca) * nspec + rowc * nh;
+        const bool sa = xi1_comp(ca), sb = xi1_comp(cb);
+        const T mb0 = s < 4 ? T(1) : T(0);
+        C ha[Q], hb[Q];
+#pragma unroll
+        for (int j2 = 0; j2 < Q; ++j2) {
+            const int k = j + P * j2;
+            const int kk = k >= nh ? L - k : k;
+            const int kc = kk < nh ? kk : 0;
+            ha[j2] = pa[kc];
+            hb[j2] = pb[kc];
+        }
+        C x[Q];
+#pragma unroll
+        for (int j2 = 0; j2 < Q; ++j2) {
+            const int k = j + P * j2;
+            const bool conj = k >= nh;
+            const int kk = conj ? L - k : k;
+            const T m = (live && kk < nh) ? T(1) : T(0);
+            const T x1 = xs1 * T(kk);
+            const T ma = sa ? m * x1 : m;
+            const T mb = sb ? mb0 * m * x1 : mb0 * m;
+            const C A = cscale(ha[j2], ma), B = cscale(hb[j2], mb);
+            const C zc = conj ? mk<T>(A.x + B.y, B.x - A.y) : mk<T>(A.x - B.y, A.y + B.x);
+            x[j2] = k == 0 ? mk<T>(A.x, B.x) : zc;
+        }
+        RegDFT<Q, +1, C>::run(x);
+#pragma unroll
+        for (int k1 = 0; k1 < Q; ++k1) {
+            C v = x[k1];
+            if (k1 > 0) {
+                C w = tw[j * k1];
+                w.y = -w.y;
+                v = cmul(v, w);
+            }
+            buf[(t * P + j) * QP + k1] = v;
+        }
+    }
+    __syncthreads();
+    C y[P];
+    if (col_ok && j < Q) {
+#pragma unroll
+        for (int j1 = 0; j1 < P; ++j1) y[j1] = buf[(t * P + j1) * QP + j];
+        RegDFT<P, +1, C>::run(y);   // y[k2] = z at voxel j + Q k2
+    }
+    __syncthreads();
+    if (col_ok && j < Q) {
+#pragma unroll
+        for (int k2 = 0; k2 < P; ++k2) {
+            fa[j + Q * k2] = y[k2].x;
+            fb[j + Q * k2] = y[k2].y;
+        }
+    }
+    __syncthreads();
+
+    // ---- tangent action per voxel (X_AVG: averaged instead of stored)
+    double acc[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+    for (int v = tid; v < R * L; v += blockDim.x) {
+        const int rr = v / L, xx = v - rr * L;
+        const long long rw = row0 + rr;
+        if (rw >= nrows) continue;
+        T p[9], tau[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) p[c] = fld[(c * R + rr) * L + xx];
+        if (MODE == X_AVG) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) p[c] = T(double(p[c]) * a.scale + a.E[c]);
+        }
+        tangent_apply<T>(a.ts, rw * L + xx, p, tau);
+        if (MODE == X_AVG) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) acc[c] += double(tau[c]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) fld[(c * R + rr) * L + xx] = tau[c];
+        }
+    }
+    if (MODE == X_AVG) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const double tt = block_sum(acc[c], red);
+            if (tid == 0) a.partials[(long long)tile_ * 9 + c] = tt;
+        }
+        return;
+    }
+    __syncthreads();
+
+    // ---- forward: real rows -> packed complex rows -> half spectra
+    C x2[Q];
+    if (col_ok && j < P) {
+        const T* gb = fld + ((s < 4 ? cb : ca) * R + r) * L;
+        const T mb0 = s < 4 ? T(1) : T(0);
+#pragma unroll
+        for (int j2 = 0; j2 < Q; ++j2) {
+            const int xx = j + P * j2;
+            x2[j2] = mk<T>(fa[xx], mb0 * gb[xx]);
+        }
+    }
+    __syncthreads();
+    if (col_ok && j < P) {
+        RegDFT<Q, -1, C>::run(x2);
+#pragma unroll
+        for (int k1 = 0; k1 < Q; ++k1) {
+            C v = x2[k1];
+            if (k1 > 0) v = cmul(v, tw[j * k1]);
+            buf[(t * P + j) * QP + k1] = v;
+        }
+    }
+    __syncthreads();
+    if (col_ok && j < Q) {
+#pragma unroll
+        for (int j1 = 0; j1 < P; ++j1) y[j1] = buf[(t * P + j1) * QP + j];
+        RegDFT<P, -1, C>::run(y);   // y[k2] = Z[j + Q k2]
+    }
+    __syncthreads();
+    if (col_ok && j < Q) {
+#pragma unroll
+        for (int k2 = 0; k2 < P; ++k2) buf[t * LP + j + Q * k2] = y[k2];
+    }
+    __syncthreads();
+    for (int i = tid; i < TX * nh; i += blockDim.x) {
+        const int tt = i / nh, k = i - tt * nh;
+        const int ss = tt / R, rr = tt - ss * R;
+        const long long rw = row0 + rr;
+        if (rw >= nrows) continue;
+        const C zk = buf[tt * LP + k];
+        const C zm = buf[tt * LP + (k == 0 ? 0 : L - k)];
+        C ha = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+        C hb = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
+        const int c1 = 2 * ss, c2 = 2 * ss + 1;
+        const T x1 = xs1 * T(k);
+        if (xi1_comp(c1)) ha = cscale(ha, x1);
+        if (xi1_comp(c2)) hb = cscale(hb, x1);
+        const long long off = rw * nh + k;
+        a.out[c1 * nspec + off] = ha;
+        if (ss < 4) a.out[c2 * nspec + off] = hb;
+    }
+}
+
+template <typename T, int MODE, int P, int Q>
+__global__ void __launch_bounds__(256) k_xlds(XArgs<T> a) {
+    k_xlds_body<T, MODE, P, Q>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int MODE, int P, int Q>
+__global__ void __launch_bounds__(256) k_xlds_b(const XArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
+    const TileMap e = map[blockIdx.x];
+    k_xlds_body<T, MODE, P, Q>(as[e.rve], e.tile, e.ntiles);
+}
+
+// row lengths with a two-stage x pass (CG operator, averaged tangent): L, P, Q
+#define COMBO_XLDS_CONFIGS(X) \
+    X(256, 16, 16)            \
+    X(128, 8, 16)             \
+    X(384, 16, 24)            \
+    X(192, 16, 12)            \
+    X(96, 8, 12)              \
+    X(64, 8, 8)               \
+    X(48, 8, 6)               \
+    X(32, 4, 8)
+
 #define COMBO_XWAVE_CONFIGS(X) \
     X(256, 4, 64)              \
     X(128, 2, 64)              \
@@ -1450,8 +1673,20 @@ void xpass_wave_shape(int n1, int& m, int& w) {
 #undef COMBO_XS_CASE
 }
 
-int blocks_x(const Grid& g, int R) {
+int xpass_lds_rows(int n1) {
+#define COMBO_XLR_CASE(LL, PP, QQ) \
+    if (n1 == LL) return XLdsShape<PP, QQ>::R;
+    COMBO_XLDS_CONFIGS(COMBO_XLR_CASE)
+#undef COMBO_XLR_CASE
+    return 0;
+}
+
+int blocks_x(const Grid& g, int R, int mode) {
     const long long nrows = (long long)g.n2 * g.n3;
+    if (mode == X_CG || mode == X_AVG) {
+        const int rows = xpass_lds_rows(g.n1);
+        if (rows > 0) return (int)((nrows + rows - 1) / rows);
+    }
 #define COMBO_XB_CASE(LL, MM, WW) \
     if (g.n1 == LL) return (int)((nrows + (256 / WW) - 1) / (256 / WW));
     COMBO_XWAVE_CONFIGS(COMBO_XB_CASE)
@@ -1482,6 +1717,18 @@ template <typename T>
 hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const BatchLaunch* b) {
     using XA = XArgs<T>;
     const long long nrows = (long long)a.g.n2 * a.g.n3;
+    if (mode == X_CG || mode == X_AVG) {
+#define COMBO_XL_CASE(LL, PP, QQ)                                                                            \
+        if (a.g.n1 == LL) {                                                                                  \
+            const int nblk = (int)((nrows + XLdsShape<PP, QQ>::R - 1) / XLdsShape<PP, QQ>::R);               \
+            if (nb) *nb = nblk;                                                                              \
+            if (mode == X_CG) COMBO_LAUNCH(k_xlds, (T, X_CG, PP, QQ), XA, nblk, 256, 0);                     \
+            else COMBO_LAUNCH(k_xlds, (T, X_AVG, PP, QQ), XA, nblk, 256, 0);                                 \
+            return hipGetLastError();                                                                        \
+        }
+        COMBO_XLDS_CONFIGS(COMBO_XL_CASE)
+#undef COMBO_XL_CASE
+    }
 #define COMBO_XW_CASE(LL, MM, WW)                                                                             \
     if (a.g.n1 == LL) {                                                                                     \
         const int nblk = (int)((nrows + (256 / WW) - 1) / (256 / WW));                                       \
@@ -1497,7 +1744,7 @@ hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const B
     }
     COMBO_XWAVE_CONFIGS(COMBO_XW_CASE)
 #undef COMBO_XW_CASE
-    const int nblk = blocks_x(a.g, a.R);
+    const int nblk = blocks_x(a.g, a.R, X_FWD_REAL);
     if (nb) *nb = nblk;
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n1 + (size_t)5 * a.R * a.g.n1);
     switch (mode) {

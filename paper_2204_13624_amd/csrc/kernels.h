@@ -144,7 +144,11 @@ template <typename T> int z_tile(const Grid& g);
 // (m, W) of the wavefront x pass for a row length n1; m = W = 0 if it has none
 void xpass_wave_shape(int n1, int& m, int& w);
 
-int blocks_x(const Grid& g, int R);
+// workgroups of an x pass in `mode` (the two-stage kernel serves X_CG and X_AVG)
+int blocks_x(const Grid& g, int R, int mode);
+// rows per workgroup of the two-stage x pass for rows of n1, 0 if there is none
+// (then the tangent state keeps the wavefront kernel's lane order, see state_pos)
+int xpass_lds_rows(int n1);
 int blocks_y(const Grid& g, int TX);
 int blocks_z(const Grid& g, int TX);
 int blocks_u(const Grid& g);

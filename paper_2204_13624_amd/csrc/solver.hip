@@ -221,7 +221,8 @@ int ensure_work(combo_ctx* ctx) {
     size_t np = 0;
     for (int prec = 0; prec < 2; ++prec) {
         PassShape s = prec ? shape_for<float>(ctx) : shape_for<double>(ctx);
-        np = std::max(np, (size_t)blocks_x(ctx->g, s.xR) * 9);
+        np = std::max(np, (size_t)blocks_x(ctx->g, s.xR, X_AVG) * 9);
+        np = std::max(np, (size_t)blocks_x(ctx->g, s.xR, X_FWD_REAL) * 9);
         np = std::max(np, (size_t)blocks_z(ctx->g, s.zTX));
     }
     np = std::max(np, (size_t)blocks_u(ctx->g));
@@ -1063,7 +1064,7 @@ void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
             x.real_out = ctx->dF.as<double>();
             xa.push_back(x);
             kx.push_back(key2(ctx->g.n1, x.R));
-            nx.push_back(blocks_x(ctx->g, x.R));
+            nx.push_back(blocks_x(ctx->g, x.R, X_INV_REAL));
         }
         plan_pass(lp, za, kz, nz, [=](const ZArgs<double, T>& a, const BatchLaunch* bl) {
             return launch_z<double, T>(Z_INV_PLAIN, a, s, nullptr, bl);
@@ -1123,7 +1124,7 @@ void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
             x.out = ctx->specA.as<double2>();
             xa.push_back(x);
             kx.push_back(key2(ctx->g.n1, x.R));
-            nx.push_back(blocks_x(ctx->g, x.R));
+            nx.push_back(blocks_x(ctx->g, x.R, X_FWD_REAL));
             YArgs<double> y = yargs<double>(ctx, ctx->specA.p, ctx->specB.p, false);
             ya.push_back(y);
             ky.push_back(key2(ctx->g.n2, y.TX));
@@ -1187,7 +1188,7 @@ void plan_cg(combo_batch* B, std::vector<Member>& ms, const std::vector<int>& li
         x.out = ctx->specA.as<cpx<T>>();
         xa.push_back(x);
         kx.push_back(key2(ctx->g.n1, x.R));
-        nx.push_back(blocks_x(ctx->g, x.R));
+        nx.push_back(blocks_x(ctx->g, x.R, X_CG));
         ua.push_back(uargs<T>(ctx, m.mu0, m.kappa0));
         ku.push_back(0);
         const int nbu = blocks_u(ctx->g);
@@ -1428,7 +1429,7 @@ int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2,
     xpass_wave_shape(n1, xm, xw);
     ctx->g.xm = xm;
     ctx->g.xwbits = -1;
-    if (xw > 0) {
+    if (xw > 0 && xpass_lds_rows(n1) == 0) {
         int b = 0;
         while ((1 << b) < xw) ++b;
         ctx->g.xwbits = b;
