@@ -112,6 +112,7 @@ def batch_bench(combo, synth, steps):
     o.tol_newton = 1e-6
     o.tol_cg = 1e-4
     o.max_cg = 20000
+    o.autotune = 1
     b = combo.combo_batch_create(0)
     combo.combo_batch_set_options(b, o)
     for ms, lc in items:
@@ -141,6 +142,7 @@ def batch_bench(combo, synth, steps):
             setattr(oo, k, getattr(o, k))
         oo.n_increments = lc.n_increments
         combo.combo_set_options(c, oo)
+        combo.combo_autotune(c, combo.COMBO_MIXED)   # cached: same schedules as the batch
         ctxs.append(c)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -173,6 +175,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--increments", type=int, default=0,
                     help="override the workload's load increments (shorter runs for counter collection)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -216,6 +219,7 @@ def main():
         o.n_increments = lc.n_increments
         o.max_cg = 20000
         o.graph_chunk = args.graph_chunk
+        o.autotune = 1 if precision == combo.COMBO_MIXED and not args.no_autotune else 0
         return o
 
     combo.combo_set_options(ctx, options(combo.COMBO_MIXED))
@@ -239,6 +243,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = combo.combo_profile_all(ctx) if not args.no_profile else {}
+    schedule = combo.combo_get_schedule(ctx)[0]
     combo.combo_profile_enable(ctx, False)
     n = ms.nvox
     nh = ms.n[0] // 2 if ms.n[0] % 2 == 0 else (ms.n[0] + 1) // 2
@@ -287,6 +292,7 @@ def main():
                                "4^3-subsample composite boxels, Neo-Hooke (1,2) / contrast 100, uniaxial stretch "
                                "to 20%% in 10 increments, eta<=1e-6, tol_cg %.0e" % (args.n, args.tol_cg),
                    "n_vox": n, "n_composite": nc, "precision": "mixed", "parallelism": "1 GPU"},
+        "fft_schedule_xyz": list(schedule),
         "cg_iters_per_step": cg_total / args.steps,
         "newton_iters_per_step": results[-1]["stats"]["newton_iters"],
         "bytes_per_voxel_cg_iter": round(b_cg, 1),

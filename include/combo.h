@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define COMBO_ABI_VERSION 2
+#define COMBO_ABI_VERSION 3
 
 typedef struct combo_ctx combo_ctx;
 typedef struct combo_batch combo_batch;
@@ -99,6 +99,7 @@ typedef struct {
     int max_step_halvings;    /* Newton step control */
     int max_cutbacks;         /* increment halvings */
     int graph_chunk;          /* CG iterations per captured HIP graph replay; 0 = plain launches */
+    int autotune;             /* 1: pick the FFT schedule of the grid by timing (combo_autotune) before solving */
 } combo_options;
 
 typedef struct {
@@ -184,6 +185,25 @@ int combo_apply_green(combo_ctx* ctx, int which, int precision, const double* ta
 /* q = Gamma0[A : p] with the tangent state of the last combo_eval_law, for a
  * compatible zero-mean field p [9][n]; the linear operator of each Newton step. */
 int combo_apply_operator(combo_ctx* ctx, int precision, const double* p, double* q, int mem_kind);
+
+/* FFT schedules and the autotuner ---------------------------------------------
+ * Each CG pass (x: inverse transform, tangent action, forward transform; y and z
+ * transform pairs with the Green projection) has compiled variants that differ
+ * in radix order, tile width and rows per workgroup; all compute the same
+ * operator (Sec. 3, eq. Gamma0) up to rounding.  The schedule of a context is
+ * one variant per axis (0 = default).  combo_autotune times every variant of
+ * each pass on this context's grid and buffers in `precision` and keeps the
+ * fastest (FP64 passes have variant 0 only).  Results are kept per process and,
+ * when the environment variable COMBO_TUNE_CACHE names a file, appended to it as
+ * text lines "arch n1 n2 n3 precision xv yv zv" and reused by later processes.
+ * Needs grid, materials and microstructure; xv, yv, zv (may be NULL) receive
+ * the schedule.  The timing writes the context's work buffers only. */
+int combo_autotune(combo_ctx* ctx, int precision, int* xv, int* yv, int* zv);
+/* Set the schedule directly; a variant that does not exist for an axis length
+ * runs variant 0.  COMBO_E_INVAL for negative values. */
+int combo_set_schedule(combo_ctx* ctx, int xv, int yv, int zv);
+/* Current schedule and the number of variants per axis of the grid (any may be NULL). */
+int combo_get_schedule(const combo_ctx* ctx, int* xv, int* yv, int* zv, int* nxv, int* nyv, int* nzv);
 
 /* Per-kernel timing ---------------------------------------------------------
  * With profiling on, the context records a HIP event pair on its stream around

@@ -52,6 +52,7 @@ class combo_options(ctypes.Structure):
         ("max_step_halvings", ctypes.c_int),
         ("max_cutbacks", ctypes.c_int),
         ("graph_chunk", ctypes.c_int),
+        ("autotune", ctypes.c_int),
     ]
 
 
@@ -103,6 +104,9 @@ _SIGS = {
     "combo_apply_operator": (_I, [_P, _I, _P, _P, _I]),
     "combo_profile_enable": (_I, [_P, _I]),
     "combo_profile_read": (_I, [_P, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
+    "combo_autotune": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "combo_set_schedule": (_I, [_P, _I, _I, _I]),
+    "combo_get_schedule": (_I, [_P] + [ctypes.POINTER(_I)] * 6),
     "combo_batch_create": (_I, [ctypes.POINTER(_P), _I, _P]),
     "combo_batch_destroy": (_I, [_P]),
     "combo_batch_last_error": (ctypes.c_char_p, [_P]),
@@ -312,6 +316,24 @@ def combo_profile_read(ctx, kernel):
 
 def combo_profile_all(ctx):
     return {name: combo_profile_read(ctx, k) for k, name in enumerate(KERNEL_NAMES)}
+
+
+def combo_autotune(ctx, precision):
+    """Tune (or fetch the cached) schedule of the context's grid; returns (xv, yv, zv)."""
+    v = [ctypes.c_int() for _ in range(3)]
+    _check(ctx, load_library().combo_autotune(ctx, int(precision), *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def combo_set_schedule(ctx, xv, yv, zv):
+    _check(ctx, load_library().combo_set_schedule(ctx, int(xv), int(yv), int(zv)))
+
+
+def combo_get_schedule(ctx):
+    """(xv, yv, zv), (number of x, y, z variants)."""
+    v = [ctypes.c_int() for _ in range(6)]
+    _check(ctx, load_library().combo_get_schedule(ctx, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v[:3]), tuple(x.value for x in v[3:])
 
 
 # ---- batches ---------------------------------------------------------------------

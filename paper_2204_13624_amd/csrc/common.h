@@ -50,6 +50,7 @@ struct Grid {
     long long nspec;      // nh*n2*n3 (complex values per spectral component)
     double xs1, xs2, xs3; // 2 pi / l_d: xi_d(k) = xs_d * k
     int xm, xwbits;       // wavefront x pass: m values per lane, log2 of lanes per row (-1: none)
+    int xv, yv, zv;       // schedule: variant of the x, y and z FFT passes (0 = default)
 };
 
 // Position of voxel `vox` in the tangent-state arrays.  With the wavefront x

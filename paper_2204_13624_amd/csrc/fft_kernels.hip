@@ -419,12 +419,13 @@ __global__ void __launch_bounds__(256) k_xwave_b(const XArgs<T>* __restrict__ as
 // row r); a stage-A item (t, j1) holds x[j1 + P j2], a stage-B item (t, k1)
 // holds X[k1 + Q k2], and the forward stage A starts from the LDS rows.
 // ------------------------------------------------------------------------------
-template <int P, int Q>
+template <int P, int Q, int RR = 0>
 struct XLdsShape {
     static constexpr int L = P * Q;
-    static constexpr int NT = P > Q ? P : Q;    // threads per column
-    static constexpr int R = 256 / (5 * NT);    // rows per workgroup
-    static constexpr int TX = 5 * R;            // columns
+    static constexpr int NT = P > Q ? P : Q;                     // threads per column
+    static constexpr int R = RR > 0 ? RR : 256 / (5 * NT);       // rows per workgroup
+    static constexpr int TX = 5 * R;                             // columns
+    static constexpr int NTH = (TX * NT + 63) / 64 * 64;         // threads per workgroup
     static constexpr int QP = Q + 1;            // padded stage-A row (LDS banks)
     static constexpr int LP = L + 1;            // padded natural row
     static constexpr int EXA = TX * P * QP;     // complex elements of the exchange
@@ -433,10 +434,10 @@ struct XLdsShape {
 
 constexpr int cmax3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
 
-template <typename T, int MODE, int P, int Q>
+template <typename T, int MODE, int P, int Q, int RR>
 __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
-    using S = XLdsShape<P, Q>;
+    using S = XLdsShape<P, Q, RR>;
     constexpr int L = S::L, R = S::R, TX = S::TX, QP = S::QP, LP = S::LP;
     constexpr int FLD = (10 * R * L * (int)sizeof(T) + (int)sizeof(C) - 1) / (int)sizeof(C);
     constexpr int BUFC = cmax3(S::EXA, S::EXN, FLD);
@@ -610,27 +611,38 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
     }
 }
 
-template <typename T, int MODE, int P, int Q>
-__global__ void __launch_bounds__(256) k_xlds(XArgs<T> a) {
-    k_xlds_body<T, MODE, P, Q>(a, blockIdx.x, gridDim.x);
+template <typename T, int MODE, int P, int Q, int RR>
+__global__ void __launch_bounds__((XLdsShape<P, Q, RR>::NTH)) k_xlds(XArgs<T> a) {
+    k_xlds_body<T, MODE, P, Q, RR>(a, blockIdx.x, gridDim.x);
 }
 
-template <typename T, int MODE, int P, int Q>
-__global__ void __launch_bounds__(256) k_xlds_b(const XArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
+template <typename T, int MODE, int P, int Q, int RR>
+__global__ void __launch_bounds__((XLdsShape<P, Q, RR>::NTH)) k_xlds_b(const XArgs<T>* __restrict__ as,
+                                                                         const TileMap* __restrict__ map) {
     const TileMap e = map[blockIdx.x];
-    k_xlds_body<T, MODE, P, Q>(as[e.rve], e.tile, e.ntiles);
+    k_xlds_body<T, MODE, P, Q, RR>(as[e.rve], e.tile, e.ntiles);
 }
 
-// row lengths with a two-stage x pass (CG operator, averaged tangent): L, P, Q
+// row lengths with a two-stage x pass (CG operator, averaged tangent):
+// L, P, Q, rows per workgroup (0 = as many as fit 256 threads), variant.
+// Variants above 0 are autotuner candidates, built for float only.
 #define COMBO_XLDS_CONFIGS(X) \
-    X(256, 16, 16)            \
-    X(128, 8, 16)             \
-    X(384, 16, 24)            \
-    X(192, 16, 12)            \
-    X(96, 8, 12)              \
-    X(64, 8, 8)               \
-    X(48, 8, 6)               \
-    X(32, 4, 8)
+    X(256, 16, 16, 0, 0)      \
+    X(256, 16, 16, 2, 1)      \
+    X(128, 8, 16, 0, 0)       \
+    X(128, 16, 8, 0, 1)       \
+    X(384, 16, 24, 0, 0)      \
+    X(384, 24, 16, 0, 1)      \
+    X(192, 16, 12, 0, 0)      \
+    X(192, 12, 16, 0, 1)      \
+    X(96, 8, 12, 0, 0)        \
+    X(96, 12, 8, 0, 1)        \
+    X(64, 8, 8, 0, 0)         \
+    X(64, 8, 8, 3, 1)         \
+    X(48, 8, 6, 0, 0)         \
+    X(48, 6, 8, 0, 1)         \
+    X(32, 4, 8, 0, 0)         \
+    X(32, 8, 4, 0, 1)
 
 #define COMBO_XWAVE_CONFIGS(X) \
     X(256, 4, 64)              \
@@ -1616,24 +1628,49 @@ __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_inv_b(const Z
 
 // Supported fast-path lengths: (P, Q, TX) per precision; TX keeps the exchange
 // buffer near 35 KB so four workgroups fit in the 160 KB LDS of a CU.
-#define COMBO_FFT2_CONFIGS(X)        \
-    X(float, 256, 16, 16, 16)        \
-    X(float, 128, 8, 16, 16)         \
-    X(float, 96, 8, 12, 16)          \
-    X(float, 64, 8, 8, 32)           \
-    X(float, 48, 8, 6, 24)           \
-    X(float, 32, 4, 8, 32)           \
-    X(double, 256, 16, 16, 8)        \
-    X(double, 128, 8, 16, 8)         \
-    X(double, 96, 8, 12, 16)         \
-    X(double, 64, 8, 8, 16)          \
-    X(double, 48, 8, 6, 24)          \
-    X(double, 32, 4, 8, 16)
+// two-stage y/z configurations: element type, length, P, Q, tile width TX, variant.
+// Variant 0 is the default; the others are candidates of the autotuner (float,
+// the precision of the CG passes in mixed mode).
+#define COMBO_FFT2_CONFIGS(X)           \
+    X(float, 256, 16, 16, 16, 0)        \
+    X(float, 256, 16, 16, 8, 1)         \
+    X(float, 128, 8, 16, 16, 0)         \
+    X(float, 128, 16, 8, 16, 1)         \
+    X(float, 96, 8, 12, 16, 0)          \
+    X(float, 96, 12, 8, 16, 1)          \
+    X(float, 64, 8, 8, 32, 0)           \
+    X(float, 64, 8, 8, 16, 1)           \
+    X(float, 48, 8, 6, 24, 0)           \
+    X(float, 48, 6, 8, 24, 1)           \
+    X(float, 32, 4, 8, 32, 0)           \
+    X(float, 32, 8, 4, 32, 1)           \
+    X(double, 256, 16, 16, 8, 0)        \
+    X(double, 128, 8, 16, 8, 0)         \
+    X(double, 96, 8, 12, 16, 0)         \
+    X(double, 64, 8, 8, 16, 0)          \
+    X(double, 48, 8, 6, 24, 0)          \
+    X(double, 32, 4, 8, 16, 0)
+
+// variants of the two-stage y/z pass for rows of L (0: none, slow LDS path)
+template <typename T>
+int fft2_variants(int L) {
+    int n = 0;
+#define COMBO_NV_CASE(TT, LL, PP, QQ, TXX, VV) \
+    if (std::is_same<T, TT>::value && L == LL) ++n;
+    COMBO_FFT2_CONFIGS(COMBO_NV_CASE)
+#undef COMBO_NV_CASE
+    return n;
+}
+
+// the variant that runs for a requested one (unknown variants fall back to 0)
+template <typename T>
+int fft2_pick(int L, int v) { return (v > 0 && v < fft2_variants<T>(L)) ? v : 0; }
 
 template <typename T>
-int fft2_tx(int L) {
-#define COMBO_TX_CASE(TT, LL, PP, QQ, TXX) \
-    if (std::is_same<T, TT>::value && L == LL) return TXX;
+int fft2_tx(int L, int v) {
+    const int vv = fft2_pick<T>(L, v);
+#define COMBO_TX_CASE(TT, LL, PP, QQ, TXX, VV) \
+    if (std::is_same<T, TT>::value && L == LL && vv == VV) return TXX;
     COMBO_FFT2_CONFIGS(COMBO_TX_CASE)
 #undef COMBO_TX_CASE
     return 0;
@@ -1641,14 +1678,14 @@ int fft2_tx(int L) {
 
 template <typename T>
 int y_tile(const Grid& g) {
-    const int tx = fft2_tx<T>(g.n2);
+    const int tx = fft2_tx<T>(g.n2, g.yv);
     if (tx) return tx;
     return std::max(1, std::min(g.nh, max_elems<T>() / g.n2));
 }
 
 template <typename T>
 int z_tile(const Grid& g) {
-    const int tx = fft2_tx<T>(g.n3);
+    const int tx = fft2_tx<T>(g.n3, g.zv);
     if (tx) return tx;
     return (int)std::max<long long>(1, std::min<long long>((long long)g.n2 * g.nh, max_elems<T>() / g.n3));
 }
@@ -1657,6 +1694,8 @@ template int y_tile<float>(const Grid&);
 template int y_tile<double>(const Grid&);
 template int z_tile<float>(const Grid&);
 template int z_tile<double>(const Grid&);
+template int fft2_variants<float>(int);
+template int fft2_variants<double>(int);
 
 // ------------------------------------------------------------------------------
 // launchers
@@ -1673,18 +1712,33 @@ void xpass_wave_shape(int n1, int& m, int& w) {
 #undef COMBO_XS_CASE
 }
 
-int xpass_lds_rows(int n1) {
-#define COMBO_XLR_CASE(LL, PP, QQ) \
-    if (n1 == LL) return XLdsShape<PP, QQ>::R;
+int xpass_lds_variants(int n1) {
+    int n = 0;
+#define COMBO_XNV_CASE(LL, PP, QQ, RR, VV) \
+    if (n1 == LL) ++n;
+    COMBO_XLDS_CONFIGS(COMBO_XNV_CASE)
+#undef COMBO_XNV_CASE
+    return n;
+}
+
+// variant that runs for a requested one: double has variant 0 only
+int xpass_lds_pick(int n1, int v, bool is_float) {
+    return (is_float && v > 0 && v < xpass_lds_variants(n1)) ? v : 0;
+}
+
+int xpass_lds_rows(int n1, int v, bool is_float) {
+    const int vv = xpass_lds_pick(n1, v, is_float);
+#define COMBO_XLR_CASE(LL, PP, QQ, RR, VV) \
+    if (n1 == LL && vv == VV) return XLdsShape<PP, QQ, RR>::R;
     COMBO_XLDS_CONFIGS(COMBO_XLR_CASE)
 #undef COMBO_XLR_CASE
     return 0;
 }
 
-int blocks_x(const Grid& g, int R, int mode) {
+int blocks_x(const Grid& g, int R, int mode, bool is_float) {
     const long long nrows = (long long)g.n2 * g.n3;
     if (mode == X_CG || mode == X_AVG) {
-        const int rows = xpass_lds_rows(g.n1);
+        const int rows = xpass_lds_rows(g.n1, g.xv, is_float);
         if (rows > 0) return (int)((nrows + rows - 1) / rows);
     }
 #define COMBO_XB_CASE(LL, MM, WW) \
@@ -1718,13 +1772,17 @@ hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const B
     using XA = XArgs<T>;
     const long long nrows = (long long)a.g.n2 * a.g.n3;
     if (mode == X_CG || mode == X_AVG) {
-#define COMBO_XL_CASE(LL, PP, QQ)                                                                            \
-        if (a.g.n1 == LL) {                                                                                  \
-            const int nblk = (int)((nrows + XLdsShape<PP, QQ>::R - 1) / XLdsShape<PP, QQ>::R);               \
-            if (nb) *nb = nblk;                                                                              \
-            if (mode == X_CG) COMBO_LAUNCH(k_xlds, (T, X_CG, PP, QQ), XA, nblk, 256, 0);                     \
-            else COMBO_LAUNCH(k_xlds, (T, X_AVG, PP, QQ), XA, nblk, 256, 0);                                 \
-            return hipGetLastError();                                                                        \
+        const int vv = xpass_lds_pick(a.g.n1, a.g.xv, std::is_same<T, float>::value);
+#define COMBO_XL_CASE(LL, PP, QQ, RR, VV)                                                                    \
+        if constexpr (VV == 0 || std::is_same<T, float>::value) {                                            \
+            if (a.g.n1 == LL && vv == VV) {                                                                  \
+                using SH = XLdsShape<PP, QQ, RR>;                                                            \
+                const int nblk = (int)((nrows + SH::R - 1) / SH::R);                                         \
+                if (nb) *nb = nblk;                                                                          \
+                if (mode == X_CG) COMBO_LAUNCH(k_xlds, (T, X_CG, PP, QQ, RR), XA, nblk, SH::NTH, 0);         \
+                else COMBO_LAUNCH(k_xlds, (T, X_AVG, PP, QQ, RR), XA, nblk, SH::NTH, 0);                     \
+                return hipGetLastError();                                                                    \
+            }                                                                                                \
         }
         COMBO_XLDS_CONFIGS(COMBO_XL_CASE)
 #undef COMBO_XL_CASE
@@ -1744,7 +1802,7 @@ hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const B
     }
     COMBO_XWAVE_CONFIGS(COMBO_XW_CASE)
 #undef COMBO_XW_CASE
-    const int nblk = blocks_x(a.g, a.R, X_FWD_REAL);
+    const int nblk = blocks_x(a.g, a.R, X_FWD_REAL, std::is_same<T, float>::value);
     if (nb) *nb = nblk;
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n1 + (size_t)5 * a.R * a.g.n1);
     switch (mode) {
@@ -1771,9 +1829,10 @@ hipError_t launch_y(int dir, const YArgs<T>& a0, hipStream_t s, const BatchLaunc
     YArgs<T> a = a0;
     y_fill_tiles(a);
     const int nblk = a.g.n3 * a.ntile;
-#define COMBO_Y_CASE(TT, LL, PP, QQ, TXX)                                                                       \
+    const int vv = fft2_pick<T>(a.g.n2, a.g.yv);
+#define COMBO_Y_CASE(TT, LL, PP, QQ, TXX, VV)                                                                   \
     if constexpr (std::is_same<T, TT>::value) {                                                               \
-        if (a.g.n2 == LL) {                                                                                    \
+        if (a.g.n2 == LL && vv == VV) {                                                                        \
             constexpr int nt = fft2_threads<PP, QQ, TXX>();                                                    \
             if (dir < 0) COMBO_LAUNCH(k_y2_fwd, (PP, QQ, TXX, T), YA, nblk, nt, 0);                      \
             else COMBO_LAUNCH(k_y2_inv, (PP, QQ, TXX, T), YA, nblk, nt, 0);                              \
@@ -1795,9 +1854,10 @@ hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb, co
     a.TX = z_tile<T>(a.g);
     const int nblk = blocks_z(a.g, a.TX);
     if (nb) *nb = nblk;
-#define COMBO_Z_CASE(TT, LL, PP, QQ, TXX)                                                                      \
+    const int vv = fft2_pick<T>(a.g.n3, a.g.zv);
+#define COMBO_Z_CASE(TT, LL, PP, QQ, TXX, VV)                                                                  \
     if constexpr (std::is_same<T, TT>::value) {                                                              \
-        if (a.g.n3 == LL) {                                                                                   \
+        if (a.g.n3 == LL && vv == VV) {                                                                       \
             constexpr int nt = fft2_threads<PP, QQ, TXX>();                                                   \
             switch (mode) {                                                                                   \
                 case Z_CG: COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_CG), ZA, nblk, nt, 0); break;        \

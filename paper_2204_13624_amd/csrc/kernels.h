@@ -145,10 +145,14 @@ template <typename T> int z_tile(const Grid& g);
 void xpass_wave_shape(int n1, int& m, int& w);
 
 // workgroups of an x pass in `mode` (the two-stage kernel serves X_CG and X_AVG)
-int blocks_x(const Grid& g, int R, int mode);
-// rows per workgroup of the two-stage x pass for rows of n1, 0 if there is none
-// (then the tangent state keeps the wavefront kernel's lane order, see state_pos)
-int xpass_lds_rows(int n1);
+int blocks_x(const Grid& g, int R, int mode, bool is_float);
+// two-stage x pass for rows of n1: number of variants (0: there is none, and the
+// tangent state keeps the wavefront kernel's lane order, see state_pos), and rows
+// per workgroup of the variant that runs for variant v
+int xpass_lds_variants(int n1);
+int xpass_lds_rows(int n1, int v, bool is_float);
+// variants of the two-stage y/z passes for rows of L (0: none)
+template <typename T> int fft2_variants(int L);
 int blocks_y(const Grid& g, int TX);
 int blocks_z(const Grid& g, int TX);
 int blocks_u(const Grid& g);

@@ -30,6 +30,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -220,10 +222,21 @@ int ensure_work(combo_ctx* ctx) {
     // partial sums: the largest consumer over all kernels
     size_t np = 0;
     for (int prec = 0; prec < 2; ++prec) {
-        PassShape s = prec ? shape_for<float>(ctx) : shape_for<double>(ctx);
-        np = std::max(np, (size_t)blocks_x(ctx->g, s.xR, X_AVG) * 9);
-        np = std::max(np, (size_t)blocks_x(ctx->g, s.xR, X_FWD_REAL) * 9);
-        np = std::max(np, (size_t)blocks_z(ctx->g, s.zTX));
+        // every schedule variant the autotuner may pick
+        const bool f = prec == 1;
+        PassShape s = f ? shape_for<float>(ctx) : shape_for<double>(ctx);
+        Grid g = ctx->g;
+        const int nxv = std::max(1, xpass_lds_variants(g.n1));
+        const int nzv = std::max(1, f ? fft2_variants<float>(g.n3) : fft2_variants<double>(g.n3));
+        for (int v = 0; v < nxv; ++v) {
+            g.xv = v;
+            np = std::max(np, (size_t)blocks_x(g, s.xR, X_AVG, f) * 9);
+        }
+        np = std::max(np, (size_t)blocks_x(g, s.xR, X_FWD_REAL, f) * 9);
+        for (int v = 0; v < nzv; ++v) {
+            g.zv = v;
+            np = std::max(np, (size_t)blocks_z(g, f ? z_tile<float>(g) : z_tile<double>(g)));
+        }
     }
     np = std::max(np, (size_t)blocks_u(ctx->g));
     np = std::max(np, (size_t)material_blocks_pure(n) * 19);
@@ -532,6 +545,166 @@ int cg_solve(combo_ctx* ctx, double mu0, double kappa0, int& iters) {
     return COMBO_OK;
 }
 
+// ------------------------------------------------------------------------------
+// autotuner: the schedule (variant of the x, y and z passes) of a CG iteration
+// ------------------------------------------------------------------------------
+struct Schedule {
+    int xv = 0, yv = 0, zv = 0;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, Schedule> g_tune;   // per process: "arch n1 n2 n3 precision"
+bool g_tune_file_read = false;
+
+std::string tune_key(const combo_ctx* ctx, int precision) {
+    hipDeviceProp_t prop;
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        for (char& c : arch)
+            if (c == ' ') c = '_';
+    }
+    return arch + " " + std::to_string(ctx->g.n1) + " " + std::to_string(ctx->g.n2) + " " +
+           std::to_string(ctx->g.n3) + " " + (precision == COMBO_MIXED ? "mixed" : "fp64");
+}
+
+// COMBO_TUNE_CACHE names a text file: one line "arch n1 n2 n3 precision xv yv zv" per tuned grid
+void tune_file_read_locked() {
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char* path = getenv("COMBO_TUNE_CACHE");
+    if (!path || !path[0]) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char arch[128], prec[16];
+    int n1, n2, n3;
+    Schedule sc;
+    while (fscanf(f, "%127s %d %d %d %15s %d %d %d", arch, &n1, &n2, &n3, prec, &sc.xv, &sc.yv, &sc.zv) == 8) {
+        const std::string key = std::string(arch) + " " + std::to_string(n1) + " " + std::to_string(n2) + " " +
+                                std::to_string(n3) + " " + prec;
+        g_tune[key] = sc;
+    }
+    fclose(f);
+}
+
+void tune_file_append_locked(const std::string& key, const Schedule& sc) {
+    const char* path = getenv("COMBO_TUNE_CACHE");
+    if (!path || !path[0]) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d\n", key.c_str(), sc.xv, sc.yv, sc.zv);
+    fclose(f);
+}
+
+// average milliseconds of `launch` (enqueues one pass) on the context's stream
+int time_pass(combo_ctx* ctx, const std::function<hipError_t()>& launch, int reps, double& ms) {
+    hipEvent_t e0 = prof_event(ctx), e1 = prof_event(ctx);
+    if (!e0 || !e1) return set_err(ctx, COMBO_E_HIP, "event creation failed");
+    for (int k = 0; k < 2; ++k) HIP_OR_FAIL(launch());
+    HIP_OR_FAIL(hipEventRecord(e0, ctx->stream));
+    for (int k = 0; k < reps; ++k) HIP_OR_FAIL(launch());
+    HIP_OR_FAIL(hipEventRecord(e1, ctx->stream));
+    HIP_OR_FAIL(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIP_OR_FAIL(hipEventElapsedTime(&t, e0, e1));
+    ms = double(t) / reps;
+    ctx->prof_pool.push_back(e0);
+    ctx->prof_pool.push_back(e1);
+    return COMBO_OK;
+}
+
+// Times every compiled variant of each CG pass (x operator pass; y inverse +
+// forward; z inverse + forward) on the context's buffers and keeps the fastest.
+// The data in the buffers is whatever they hold: only the timing matters, and
+// every index the kernels use (slot map, composites) is valid.
+template <typename T>
+int autotune_impl(combo_ctx* ctx, Schedule& best) {
+    double mu0, kappa0;
+    reference_medium(ctx, mu0, kappa0);
+    hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, ctx->stream, ctx->cgst.as<CGState>());
+    HIP_OR_FAIL(hipGetLastError());
+    const Grid g0 = ctx->g;
+    const bool f = sizeof(T) == 4;
+    const int nxv = f ? std::max(1, xpass_lds_variants(g0.n1)) : 1;
+    const int nyv = std::max(1, fft2_variants<T>(g0.n2));
+    const int nzv = std::max(1, fft2_variants<T>(g0.n3));
+    const int reps = (int)std::min<long long>(100, std::max<long long>(5, 30000000LL / std::max(1LL, g0.n)));
+    double bx = 1e30, by = 1e30, bz = 1e30, ms = 0.0;
+    int st = COMBO_OK;
+    for (int v = 0; v < nxv && !st; ++v) {
+        ctx->g = g0;
+        ctx->g.xv = v;
+        XArgs<T> xa = xargs<T>(ctx);
+        xa.in = ctx->specB.as<cpx<T>>();
+        xa.out = ctx->specA.as<cpx<T>>();
+        st = time_pass(ctx, [&]() { return launch_x<T>(X_CG, xa, ctx->stream); }, reps, ms);
+        if (!st && ms < bx) bx = ms, best.xv = v;
+    }
+    for (int v = 0; v < nyv && !st; ++v) {
+        ctx->g = g0;
+        ctx->g.yv = v;
+        const YArgs<T> yi = yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true);
+        const YArgs<T> yf = yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true);
+        st = time_pass(ctx, [&]() {
+            hipError_t e = launch_y<T>(+1, yi, ctx->stream);
+            return e != hipSuccess ? e : launch_y<T>(-1, yf, ctx->stream);
+        }, reps, ms);
+        if (!st && ms < by) by = ms, best.yv = v;
+    }
+    for (int v = 0; v < nzv && !st; ++v) {
+        ctx->g = g0;
+        ctx->g.zv = v;
+        ZArgs<T, T> zi = zargs<T, T>(ctx, mu0, kappa0);
+        zi.out = ctx->specA.as<cpx<T>>();
+        ZArgs<T, T> zf = zargs<T, T>(ctx, mu0, kappa0);
+        zf.in = ctx->specB.as<cpx<T>>();
+        zf.out = nullptr;
+        st = time_pass(ctx, [&]() {
+            hipError_t e = launch_z<T, T>(Z_INV_CG, zi, ctx->stream);
+            return e != hipSuccess ? e : launch_z<T, T>(Z_CG, zf, ctx->stream);
+        }, reps, ms);
+        if (!st && ms < bz) bz = ms, best.zv = v;
+    }
+    ctx->g = g0;
+    if (st) return st;
+    if (verbose())
+        fprintf(stderr, "[combo] autotune %dx%dx%d %s: x %d (%.1f us) y %d (%.1f us) z %d (%.1f us)\n", g0.n1, g0.n2,
+                g0.n3, f ? "mixed" : "fp64", best.xv, bx * 1e3, best.yv, by * 1e3, best.zv, bz * 1e3);
+    return COMBO_OK;
+}
+
+void apply_schedule(combo_ctx* ctx, const Schedule& sc) {
+    ctx->g.xv = sc.xv;
+    ctx->g.yv = sc.yv;
+    ctx->g.zv = sc.zv;
+    for (auto& gr : ctx->graph) gr.reset();
+}
+
+int autotune(combo_ctx* ctx, int precision) {
+    const std::string key = tune_key(ctx, precision);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_file_read_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            apply_schedule(ctx, it->second);
+            return COMBO_OK;
+        }
+    }
+    Schedule sc;
+    int st = precision == COMBO_MIXED ? autotune_impl<float>(ctx, sc) : autotune_impl<double>(ctx, sc);
+    if (st) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (!g_tune.count(key)) {
+            g_tune[key] = sc;
+            tune_file_append_locked(key, sc);
+        }
+    }
+    apply_schedule(ctx, sc);
+    return COMBO_OK;
+}
+
 // dF (FP64 field) from the CG solution x (precision TU)
 template <typename TU>
 int newton_direction(combo_ctx* ctx) {
@@ -818,7 +991,8 @@ void plan_finalize(LaunchPlan& lp, int mode, const std::vector<FinArgs>& f, hipS
     });
 }
 
-long long key2(long long a, long long b) { return (a << 32) | b; }
+// launch-group key: axis length, schedule variant, tile width or rows
+long long key2(long long len, long long tile, int variant = 0) { return (len << 40) | ((long long)variant << 32) | tile; }
 
 enum MemberPhase { PH_INC = 0, PH_RES, PH_CG, PH_STEP, PH_DONE, PH_FAIL };
 
@@ -1053,18 +1227,18 @@ void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
             ZArgs<double, T> z = zargs<double, T>(ctx, 1.0, 0.0);
             z.out = ctx->specA.as<double2>();
             za.push_back(z);
-            kz.push_back(key2(ctx->g.n3, z.TX));
+            kz.push_back(key2(ctx->g.n3, z.TX, ctx->g.zv));
             nz.push_back(blocks_z(ctx->g, z.TX));
             YArgs<double> y = yargs<double>(ctx, ctx->specA.p, ctx->specB.p, false);
             ya.push_back(y);
-            ky.push_back(key2(ctx->g.n2, y.TX));
+            ky.push_back(key2(ctx->g.n2, y.TX, ctx->g.yv));
             ny.push_back(blocks_y(ctx->g, y.TX));
             XArgs<double> x = xargs<double>(ctx);
             x.in = ctx->specB.as<double2>();
             x.real_out = ctx->dF.as<double>();
             xa.push_back(x);
-            kx.push_back(key2(ctx->g.n1, x.R));
-            nx.push_back(blocks_x(ctx->g, x.R, X_INV_REAL));
+            kx.push_back(key2(ctx->g.n1, x.R, ctx->g.xv));
+            nx.push_back(blocks_x(ctx->g, x.R, X_INV_REAL, false));
         }
         plan_pass(lp, za, kz, nz, [=](const ZArgs<double, T>& a, const BatchLaunch* bl) {
             return launch_z<double, T>(Z_INV_PLAIN, a, s, nullptr, bl);
@@ -1123,16 +1297,16 @@ void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
             x.real_in = ctx->P.as<double>();
             x.out = ctx->specA.as<double2>();
             xa.push_back(x);
-            kx.push_back(key2(ctx->g.n1, x.R));
-            nx.push_back(blocks_x(ctx->g, x.R, X_FWD_REAL));
+            kx.push_back(key2(ctx->g.n1, x.R, ctx->g.xv));
+            nx.push_back(blocks_x(ctx->g, x.R, X_FWD_REAL, false));
             YArgs<double> y = yargs<double>(ctx, ctx->specA.p, ctx->specB.p, false);
             ya.push_back(y);
-            ky.push_back(key2(ctx->g.n2, y.TX));
+            ky.push_back(key2(ctx->g.n2, y.TX, ctx->g.yv));
             ny.push_back(blocks_y(ctx->g, y.TX));
             ZArgs<double, T> z = zargs<double, T>(ctx, m.mu0, m.kappa0);
             z.in = ctx->specB.as<double2>();
             za.push_back(z);
-            kz.push_back(key2(ctx->g.n3, z.TX));
+            kz.push_back(key2(ctx->g.n3, z.TX, ctx->g.zv));
             const int nbz = blocks_z(ctx->g, z.TX);
             nz.push_back(nbz);
             ua.push_back(uargs<T>(ctx, m.mu0, m.kappa0));
@@ -1175,20 +1349,20 @@ void plan_cg(combo_batch* B, std::vector<Member>& ms, const std::vector<int>& li
         z.in = ctx->specB.as<cpx<T>>();
         z.out = nullptr;
         zf.push_back(z);
-        kz.push_back(key2(ctx->g.n3, z.TX));
+        kz.push_back(key2(ctx->g.n3, z.TX, ctx->g.zv));
         const int nbz = blocks_z(ctx->g, z.TX);
         nz.push_back(nbz);
         YArgs<T> yv = yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true);
         yi.push_back(yv);
         yf.push_back(yv);
-        ky.push_back(key2(ctx->g.n2, yv.TX));
+        ky.push_back(key2(ctx->g.n2, yv.TX, ctx->g.yv));
         ny.push_back(blocks_y(ctx->g, yv.TX));
         XArgs<T> x = xargs<T>(ctx);
         x.in = ctx->specB.as<cpx<T>>();
         x.out = ctx->specA.as<cpx<T>>();
         xa.push_back(x);
-        kx.push_back(key2(ctx->g.n1, x.R));
-        nx.push_back(blocks_x(ctx->g, x.R, X_CG));
+        kx.push_back(key2(ctx->g.n1, x.R, ctx->g.xv));
+        nx.push_back(blocks_x(ctx->g, x.R, X_CG, sizeof(T) == 4));
         ua.push_back(uargs<T>(ctx, m.mu0, m.kappa0));
         ku.push_back(0);
         const int nbu = blocks_u(ctx->g);
@@ -1256,7 +1430,7 @@ const char* options_error(const combo_options* o) {
     if (o->precision != COMBO_FP64 && o->precision != COMBO_MIXED) return "precision must be COMBO_FP64 or COMBO_MIXED";
     if (!(o->tol_newton > 0) || !(o->tol_cg > 0) || o->max_newton < 0 || o->max_cg < 1 || o->max_laminate < 0 ||
         o->max_laminate > 64 || o->n_increments < 1 || o->max_step_halvings < 0 || o->max_cutbacks < 0 ||
-        o->graph_chunk < 0 || o->graph_chunk > 256)
+        o->graph_chunk < 0 || o->graph_chunk > 256 || o->autotune < 0 || o->autotune > 1)
         return "option out of range";
     return nullptr;
 }
@@ -1334,6 +1508,7 @@ void combo_default_options(combo_options* o) {
     o->max_step_halvings = 10;
     o->max_cutbacks = 5;
     o->graph_chunk = 0;
+    o->autotune = 0;
 }
 
 int combo_check_size(int n) { return size_ok(n) ? COMBO_OK : COMBO_E_SIZE; }
@@ -1418,6 +1593,7 @@ int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2,
     ctx->g.n1 = n1;
     ctx->g.n2 = n2;
     ctx->g.n3 = n3;
+    ctx->g.xv = ctx->g.yv = ctx->g.zv = 0;
     ctx->g.nh = (n1 % 2 == 0) ? n1 / 2 : (n1 + 1) / 2;
     ctx->g.n = (long long)n1 * n2 * n3;
     ctx->g.nspec = (long long)ctx->g.nh * n2 * n3;
@@ -1429,7 +1605,7 @@ int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2,
     xpass_wave_shape(n1, xm, xw);
     ctx->g.xm = xm;
     ctx->g.xwbits = -1;
-    if (xw > 0 && xpass_lds_rows(n1) == 0) {
+    if (xw > 0 && xpass_lds_variants(n1) == 0) {
         int b = 0;
         while ((1 << b) < xw) ++b;
         ctx->g.xwbits = b;
@@ -1614,6 +1790,10 @@ int combo_solve(combo_ctx* ctx, const double Fbar[9], const double* F_init, doub
         HIP_OR_FAIL(hipGetLastError());
         for (int c = 0; c < 9; ++c) Fbar0[c] = (c % 4 == 0) ? 1.0 : 0.0;
     }
+    if (ctx->opt.autotune) {
+        st = autotune(ctx, ctx->opt.precision);
+        if (st) return st;
+    }
     hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, ctx->stream, ctx->cgst.as<CGState>());
     SolveOut so;
     double Atmp[81];
@@ -1785,6 +1965,43 @@ int combo_apply_operator(combo_ctx* ctx, int precision, const double* p, double*
     return COMBO_OK;
 }
 
+int combo_autotune(combo_ctx* ctx, int precision, int* xv, int* yv, int* zv) {
+    int st = require_ready(ctx);
+    if (st) return st;
+    if (precision != COMBO_FP64 && precision != COMBO_MIXED) return set_err(ctx, COMBO_E_INVAL, "bad precision");
+    HIP_OR_FAIL(hipSetDevice(ctx->device));
+    st = autotune(ctx, precision);
+    if (st) return st;
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    if (xv) *xv = ctx->g.xv;
+    if (yv) *yv = ctx->g.yv;
+    if (zv) *zv = ctx->g.zv;
+    return COMBO_OK;
+}
+
+int combo_set_schedule(combo_ctx* ctx, int xv, int yv, int zv) {
+    if (!ctx) return COMBO_E_INVAL;
+    if (!ctx->has_grid) return set_err(ctx, COMBO_E_STATE, "combo_set_grid has not been called");
+    if (xv < 0 || yv < 0 || zv < 0) return set_err(ctx, COMBO_E_INVAL, "schedule variants must be >= 0");
+    Schedule sc;
+    sc.xv = xv;
+    sc.yv = yv;
+    sc.zv = zv;
+    apply_schedule(ctx, sc);
+    return COMBO_OK;
+}
+
+int combo_get_schedule(const combo_ctx* ctx, int* xv, int* yv, int* zv, int* nxv, int* nyv, int* nzv) {
+    if (!ctx) return COMBO_E_INVAL;
+    if (xv) *xv = ctx->g.xv;
+    if (yv) *yv = ctx->g.yv;
+    if (zv) *zv = ctx->g.zv;
+    if (nxv) *nxv = std::max(1, xpass_lds_variants(ctx->g.n1));
+    if (nyv) *nyv = std::max(1, fft2_variants<float>(ctx->g.n2));
+    if (nzv) *nzv = std::max(1, fft2_variants<float>(ctx->g.n3));
+    return COMBO_OK;
+}
+
 int combo_profile_enable(combo_ctx* ctx, int enable) {
     if (!ctx) return COMBO_E_INVAL;
     HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
@@ -1903,6 +2120,14 @@ int combo_batch_solve(combo_batch* B, const double* Fbar, const int* n_increment
         B->hscal = nullptr;
         BHIP_OR_FAIL(hipHostMalloc((void**)&B->hscal, stride * nm, hipHostMallocDefault));
         B->hscal_bytes = stride * nm;
+    }
+    if (B->opt.autotune) {
+        for (size_t i = 0; i < nm; ++i) {
+            combo_ctx* ctx = B->members[i];
+            ctx->cgst.borrow(static_cast<char*>(B->scal.p) + i * stride, sizeof(CGState));
+            const int st = autotune(ctx, B->opt.precision);
+            if (st) return bset_err(B, st, "member " + std::to_string(i) + ": " + ctx->err);
+        }
     }
     std::vector<Member> ms(nm);
     for (size_t i = 0; i < nm; ++i) {
