@@ -15,7 +15,9 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libcombo.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["fft_kernels.hip", "material_kernels.hip", "solver.hip"]
+# (source, defines): the FFT kernel file is compiled once per part, in parallel
+SOURCES = [("fft_kernels.hip", ["-DCOMBO_PART=%d" % k]) for k in range(1, 7)] + [
+    ("material_kernels.hip", []), ("solver.hip", [])]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -27,9 +29,11 @@ FLAGS = [
 ]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(item):
+    src, defs = item
+    tag = "".join(d.split("=")[-1] for d in defs)
+    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + (("_" + tag) if tag else "") + ".o")
+    cmd = [HIPCC] + FLAGS + defs + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-6000:]))
@@ -41,7 +45,7 @@ def build(verbose=False):
     if not os.path.exists(HIPCC):
         raise RuntimeError("hipcc not found at %s" % HIPCC)
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), max(1, min(16, os.cpu_count() or 1)))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs

@@ -32,6 +32,20 @@
 #include "kernels.h"
 #include "wave_fft.h"
 
+// The build compiles this file once per part (COMBO_PART = 1..6, in parallel);
+// kernel templates are instantiated only by the launchers of their part.
+// Without COMBO_PART everything is compiled in one unit.
+#ifndef COMBO_PART
+#define COMBO_PART 0
+#endif
+#define COMBO_IN_PART(k) (COMBO_PART == 0 || COMBO_PART == (k))
+#define COMBO_PART_XF 1   // x pass, float
+#define COMBO_PART_XD 2   // x pass, double
+#define COMBO_PART_Y 3    // y passes
+#define COMBO_PART_ZF 4   // z passes, float
+#define COMBO_PART_ZD 5   // z passes with double transforms
+#define COMBO_PART_CG 6   // CG vector kernels, finalisers, host helpers
+
 namespace combo {
 
 // ------------------------------------------------------------------------------
@@ -1260,6 +1274,7 @@ __global__ void __launch_bounds__(kBlock) k_antiherm_b(const UArgs<TU>* __restri
     k_antiherm_body<TU>(as[e.rve], e.tile, e.ntiles);
 }
 
+#if COMBO_IN_PART(COMBO_PART_CG)
 // ------------------------------------------------------------------------------
 // finalisers: one workgroup, fixed summation order (deterministic)
 // ------------------------------------------------------------------------------
@@ -1329,6 +1344,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_columns(const double* partial
         if (threadIdx.x == 0) out[c] = t;
     }
 }
+#endif
 
 // ------------------------------------------------------------------------------
 // Two-stage register FFT versions of the y and z passes (fft_reg.h): each 1D
@@ -1690,6 +1706,7 @@ int z_tile(const Grid& g) {
     return (int)std::max<long long>(1, std::min<long long>((long long)g.n2 * g.nh, max_elems<T>() / g.n3));
 }
 
+#if COMBO_IN_PART(COMBO_PART_CG)
 template int y_tile<float>(const Grid&);
 template int y_tile<double>(const Grid&);
 template int z_tile<float>(const Grid&);
@@ -1754,6 +1771,8 @@ int blocks_u(const Grid& g) {
     return (int)(b < 4096 ? b : 4096);
 }
 
+#endif  // host helpers
+
 #define COMBO_UNPAREN(...) __VA_ARGS__
 // launch KNAME<TARGS> with the argument block `a`, or its batched twin KNAME_b<TARGS>
 // over the tile map of `b` (KARGS_T: the argument block type, one token)
@@ -1767,6 +1786,7 @@ int blocks_u(const Grid& g) {
         }                                                                                                     \
     } while (0)
 
+#if COMBO_IN_PART(COMBO_PART_XF) || COMBO_IN_PART(COMBO_PART_XD)
 template <typename T>
 hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const BatchLaunch* b) {
     using XA = XArgs<T>;
@@ -1815,6 +1835,9 @@ hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const B
     return hipGetLastError();
 }
 
+#endif
+
+#if COMBO_IN_PART(COMBO_PART_Y)
 // y and z launchers: the caller's TX/ntile are replaced by the tile width of the
 // kernel that runs (two-stage fast path or LDS Stockham)
 template <typename T>
@@ -1847,6 +1870,9 @@ hipError_t launch_y(int dir, const YArgs<T>& a0, hipStream_t s, const BatchLaunc
     return hipGetLastError();
 }
 
+#endif
+
+#if COMBO_IN_PART(COMBO_PART_ZF) || COMBO_IN_PART(COMBO_PART_ZD)
 template <typename T, typename TU>
 hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb, const BatchLaunch* b) {
     using ZA = ZArgs<T, TU>;
@@ -1882,6 +1908,9 @@ hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb, co
     return hipGetLastError();
 }
 
+#endif
+
+#if COMBO_IN_PART(COMBO_PART_CG)
 template <typename TU>
 hipError_t launch_update(const UArgs<TU>& a, hipStream_t s, int* nb, const BatchLaunch* b) {
     using UA = UArgs<TU>;
@@ -1914,16 +1943,30 @@ hipError_t launch_reduce_columns(const double* partials, int rows, int cols, dou
     return hipGetLastError();
 }
 
+#endif
+
+#if COMBO_IN_PART(COMBO_PART_XF)
 template hipError_t launch_x<float>(int, const XArgs<float>&, hipStream_t, int*, const BatchLaunch*);
+#endif
+#if COMBO_IN_PART(COMBO_PART_XD)
 template hipError_t launch_x<double>(int, const XArgs<double>&, hipStream_t, int*, const BatchLaunch*);
+#endif
+#if COMBO_IN_PART(COMBO_PART_Y)
 template hipError_t launch_y<float>(int, const YArgs<float>&, hipStream_t, const BatchLaunch*);
 template hipError_t launch_y<double>(int, const YArgs<double>&, hipStream_t, const BatchLaunch*);
+#endif
+#if COMBO_IN_PART(COMBO_PART_ZF)
 template hipError_t launch_z<float, float>(int, const ZArgs<float, float>&, hipStream_t, int*, const BatchLaunch*);
+#endif
+#if COMBO_IN_PART(COMBO_PART_ZD)
 template hipError_t launch_z<double, double>(int, const ZArgs<double, double>&, hipStream_t, int*, const BatchLaunch*);
 template hipError_t launch_z<double, float>(int, const ZArgs<double, float>&, hipStream_t, int*, const BatchLaunch*);
+#endif
+#if COMBO_IN_PART(COMBO_PART_CG)
 template hipError_t launch_update<float>(const UArgs<float>&, hipStream_t, int*, const BatchLaunch*);
 template hipError_t launch_update<double>(const UArgs<double>&, hipStream_t, int*, const BatchLaunch*);
 template hipError_t launch_antiherm<float>(const UArgs<float>&, hipStream_t, const BatchLaunch*);
 template hipError_t launch_antiherm<double>(const UArgs<double>&, hipStream_t, const BatchLaunch*);
+#endif
 
 }  // namespace combo

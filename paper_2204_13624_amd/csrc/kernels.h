@@ -151,6 +151,7 @@ int blocks_x(const Grid& g, int R, int mode, bool is_float);
 // per workgroup of the variant that runs for variant v
 int xpass_lds_variants(int n1);
 int xpass_lds_rows(int n1, int v, bool is_float);
+int xpass_lds_pick(int n1, int v, bool is_float);   // the variant that runs for variant v
 // variants of the two-stage y/z passes for rows of L (0: none)
 template <typename T> int fft2_variants(int L);
 int blocks_y(const Grid& g, int TX);
