@@ -461,7 +461,8 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
     __shared__ double red[16];
     T* fld = reinterpret_cast<T*>(buf);   // real rows [9][R][L] and a sink row block
     const int tid = threadIdx.x;
-    const int nh = a.g.nh;
+    static_assert(L % 2 == 0, "two-stage x pass rows have even length");
+    constexpr int nh = L / 2;   // stored x frequencies (the Nyquist bin is not stored)
     const long long nspec = a.g.nspec;
     const long long nrows = (long long)a.g.n2 * a.g.n3;
     const long long row0 = (long long)tile_ * R;
@@ -826,18 +827,49 @@ struct Freq {
     double w;               // Parseval weight of the half spectrum (1 or 2)
 };
 
-__device__ __forceinline__ Freq freq_at(const Grid& g, long long m, int z) {
+// frequency data of one (y, x) column m = ky nh + kx of the half spectrum
+// (m < 2^31 for every supported grid: 32-bit index arithmetic)
+struct ColFreq {
+    double x1, x2, s12;     // xi_1, xi_2, xi_1^2 + xi_2^2
+    double w;               // Parseval weight (1 on the kx = 0 plane, else 2)
+    int kx, ky;
+    bool zero12;            // kx = 0 and ky = 0
+    bool nyq2;              // Nyquist plane of y
+};
+
+__device__ __forceinline__ ColFreq col_freq_k(const Grid& g, int ky, int kx) {
+    ColFreq c;
+    c.ky = ky;
+    c.kx = kx;
+    const int fy = freq_of(c.ky, g.n2);
+    c.x1 = g.xs1 * c.kx;
+    c.x2 = g.xs2 * fy;
+    c.s12 = c.x1 * c.x1 + c.x2 * c.x2;
+    c.w = (c.kx == 0) ? 1.0 : 2.0;
+    c.zero12 = (c.kx == 0 && fy == 0);
+    c.nyq2 = is_nyquist(c.ky, g.n2);
+    return c;
+}
+
+__device__ __forceinline__ ColFreq col_freq(const Grid& g, int m) {
+    const int ky = m / g.nh;
+    return col_freq_k(g, ky, m - ky * g.nh);
+}
+
+__device__ __forceinline__ Freq freq_z(const Grid& g, const ColFreq& c, int z) {
     Freq f;
-    const int ky = (int)(m / g.nh);
-    const int kx = (int)(m - (long long)ky * g.nh);
-    const int fy = freq_of(ky, g.n2), fz = freq_of(z, g.n3);
-    f.x1 = g.xs1 * kx;
-    f.x2 = g.xs2 * fy;
+    const int fz = freq_of(z, g.n3);
+    f.x1 = c.x1;
+    f.x2 = c.x2;
     f.x3 = g.xs3 * fz;
-    f.s = f.x1 * f.x1 + f.x2 * f.x2 + f.x3 * f.x3;
-    f.zero = (kx == 0 && fy == 0 && fz == 0) || is_nyquist(ky, g.n2) || is_nyquist(z, g.n3);
-    f.w = (kx == 0) ? 1.0 : 2.0;
+    f.s = c.s12 + f.x3 * f.x3;
+    f.zero = (c.zero12 && fz == 0) || c.nyq2 || is_nyquist(z, g.n3);
+    f.w = c.w;
     return f;
+}
+
+__device__ __forceinline__ Freq freq_at(const Grid& g, long long m, int z) {
+    return freq_z(g, col_freq(g, (int)m), z);
 }
 
 // w = K^{-1} v with K = mu0 |xi|^2 I + kappa0 xi (x) xi
@@ -876,12 +908,12 @@ __device__ __forceinline__ void kmul(const Freq& f, double mu0, double kappa0, c
 //   Z_RHS:  r = b = -K^{-1} v, x = 0, accumulate <b, b>_K and |G P|^2 = |v|^2/|xi|^2
 //   Z_PROJ: x = K^{-1} v
 template <typename T, typename TU, int MODE>
-__device__ __forceinline__ void z_epilogue(const ZArgs<T, TU>& a, long long m, int z, const cpx<T>* vv, double& s1,
-                                           double& s2) {
+__device__ __forceinline__ void z_epilogue(const ZArgs<T, TU>& a, const ColFreq& cf, long long m, int z, const cpx<T>* vv,
+                                           double& s1, double& s2) {
     using C = cpx<T>;
     using CU = cpx<TU>;
     const long long M = (long long)a.g.n2 * a.g.nh;
-    const Freq f = freq_at(a.g, m, z);
+    const Freq f = freq_z(a.g, cf, z);
     const long long idx = (long long)z * M + m;
     C w[3];
     if (f.zero) {
@@ -1009,7 +1041,7 @@ __device__ __forceinline__ void k_zpass_fwd_body(const ZArgs<T, TU>& a, int tile
         const long long m = m0 + t;
         if (m >= M) continue;
         C vv[3] = {v[0][q], v[1][q], v[2][q]};
-        z_epilogue<T, TU, MODE>(a, m, z, vv, s1, s2);
+        z_epilogue<T, TU, MODE>(a, col_freq(a.g, (int)m), m, z, vv, s1, s2);
     }
     if (MODE == Z_CG || MODE == Z_RHS) {
         const double t1 = block_sum(s1, red);
@@ -1166,10 +1198,9 @@ __device__ __forceinline__ double cg_update_one(const UArgs<TU>& a, long long id
     return 0.0;
 }
 
+// w Re(r^H K r) at one frequency
 template <typename TU>
-__device__ __forceinline__ double rkr(const UArgs<TU>& a, const cpx<TU>* rr, long long M, long long idx) {
-    const int z = (int)(idx / M);
-    const Freq f = freq_at(a.g, idx - (long long)z * M, z);
+__device__ __forceinline__ double rkr(const UArgs<TU>& a, const cpx<TU>* rr, const Freq& f) {
     if (f.zero) return 0.0;
     double kr[3], ki[3];
     kmul(f, a.mu0, a.kappa0, rr, kr, ki);
@@ -1179,6 +1210,14 @@ __device__ __forceinline__ double rkr(const UArgs<TU>& a, const cpx<TU>* rr, lon
     return f.w * t;
 }
 
+// element e of the half spectrum (e < 2^31): row = z n2 + ky, kx
+__device__ __forceinline__ void split_index(const Grid& g, int e, int& z, int& ky, int& kx) {
+    const int row = e / g.nh;
+    kx = e - row * g.nh;
+    z = row / g.n2;
+    ky = row - z * g.n2;
+}
+
 template <typename TU>
 __device__ __forceinline__ void k_cg_update_body(const UArgs<TU>& a, int tile_, int ntiles_) {
     using CU = cpx<TU>;
@@ -1186,19 +1225,18 @@ __device__ __forceinline__ void k_cg_update_body(const UArgs<TU>& a, int tile_, 
     __shared__ double red[16];
     const double alpha = a.st->alpha;
     const long long M = (long long)a.g.n2 * a.g.nh;
+    const int nspec = (int)a.g.nspec;
     double s = 0.0;
-    for (long long idx = (long long)tile_ * blockDim.x + threadIdx.x; idx < a.g.nspec;
-         idx += (long long)ntiles_ * blockDim.x) {
-        const int z = (int)(idx / M);
-        const long long m = idx - (long long)z * M;
-        const int ky = (int)(m / a.g.nh);
-        const int kx = (int)(m - (long long)ky * a.g.nh);
+    for (int idx = tile_ * (int)blockDim.x + (int)threadIdx.x; idx < nspec; idx += ntiles_ * (int)blockDim.x) {
+        int z, ky, kx;
+        split_index(a.g, idx, z, ky, kx);
+        const ColFreq cf = col_freq_k(a.g, ky, kx);
         CU r1[3];
         if (kx != 0) {
             cg_update_one(a, idx, alpha, r1);
 #pragma unroll
             for (int i = 0; i < 3; ++i) a.r[i * a.g.nspec + idx] = r1[i];
-            s += rkr(a, r1, M, idx);
+            s += rkr(a, r1, freq_z(a.g, cf, z));
             continue;
         }
         const long long idx2 = kx0_partner(a.g, M, z, ky);
@@ -1215,11 +1253,12 @@ __device__ __forceinline__ void k_cg_update_body(const UArgs<TU>& a, int tile_, 
                 antiherm_pair(r1[i], r2[i]);
                 a.r[i * a.g.nspec + idx2] = r2[i];
             }
-            s += rkr(a, r2, M, idx2);
+            const int z2 = (a.g.n3 - z) % a.g.n3, ky2 = (a.g.n2 - ky) % a.g.n2;
+            s += rkr(a, r2, freq_z(a.g, col_freq_k(a.g, ky2, 0), z2));
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) a.r[i * a.g.nspec + idx] = r1[i];
-        s += rkr(a, r1, M, idx);
+        s += rkr(a, r1, freq_z(a.g, cf, z));
     }
     const double tot = block_sum(s, red);
     if (threadIdx.x == 0) a.partials[tile_] = tot;
@@ -1373,18 +1412,25 @@ __device__ __forceinline__ void k_y2_fwd_body(const YArgs<T>& a, int tile_, int 
     const T xs2 = T(a.g.xs2);
     __syncthreads();
     C acc[P];
+    // component c's column, loaded one step ahead so that its loads are in flight
+    // during the previous component's transform
+    C nx[Q];
+    auto load = [&](int c) {
+        const C* src = a.in + c * a.g.nspec + zoff + kx0;   // uniform
+#pragma unroll
+        for (int j2 = 0; j2 < Q; ++j2) nx[j2] = (hasA && colA) ? src[tA + (j1 + P * j2) * nh] : mk<T>(0, 0);
+    };
+    load(0);
 #pragma unroll 1
     for (int i = 0; i < 3; ++i) {
 #pragma unroll 1
         for (int sub = 0; sub < 3; ++sub) {
             const int c = 3 * i + sub;
-            if (hasA) {
-                C x[Q];
-                const C* src = a.in + c * a.g.nspec + zoff + kx0;   // uniform
+            C x[Q];
 #pragma unroll
-                for (int j2 = 0; j2 < Q; ++j2) x[j2] = colA ? src[tA + (j1 + P * j2) * nh] : mk<T>(0, 0);
-                fft2_stageA<P, Q, TX, -1, T>(x, tA, j1, ex, tw);
-            }
+            for (int j2 = 0; j2 < Q; ++j2) x[j2] = nx[j2];
+            if (c + 1 < 9) load(c + 1);
+            if (hasA) fft2_stageA<P, Q, TX, -1, T>(x, tA, j1, ex, tw);
             __syncthreads();
             if (hasB) {
                 C y[P];
@@ -1438,22 +1484,28 @@ __device__ __forceinline__ void k_y2_inv_body(const YArgs<T>& a, int tile_, int 
     const bool colA = kx0 + tA < nh, colB = kx0 + tB < nh;
     const T xs2 = T(a.g.xs2);
     __syncthreads();
+    // step 3 i + sub reads component (sub == 2 ? 3 + i : i), one step ahead
+    C nx[Q];
+    auto load = [&](int step) {
+        const int i = step / 3, sub = step - 3 * i;
+        const C* src = a.in + (sub == 2 ? 3 + i : i) * a.g.nspec + zoff + kx0;   // uniform
+#pragma unroll
+        for (int j2 = 0; j2 < Q; ++j2) nx[j2] = (hasA && colA) ? src[tA + (j1 + P * j2) * nh] : mk<T>(0, 0);
+    };
+    load(0);
 #pragma unroll 1
     for (int i = 0; i < 3; ++i) {
 #pragma unroll 1
         for (int sub = 0; sub < 3; ++sub) {
             // sub 0: A_i, sub 1: xi_2 A_i (A_i re-read, normally from L2), sub 2: B_i
-            if (hasA) {
-                C x[Q];
-                const C* src = a.in + (sub == 2 ? 3 + i : i) * a.g.nspec + zoff + kx0;   // uniform
+            C x[Q];
 #pragma unroll
-                for (int j2 = 0; j2 < Q; ++j2) {
-                    const int y = j1 + P * j2;
-                    C v = colA ? src[tA + y * nh] : mk<T>(0, 0);
-                    x[j2] = (sub == 1) ? cscale(v, xs2 * T(freq_of(y, L))) : v;
-                }
-                fft2_stageA<P, Q, TX, +1, T>(x, tA, j1, ex, tw);
+            for (int j2 = 0; j2 < Q; ++j2) {
+                const int y = j1 + P * j2;
+                x[j2] = (sub == 1) ? cscale(nx[j2], xs2 * T(freq_of(y, L))) : nx[j2];
             }
+            if (3 * i + sub + 1 < 9) load(3 * i + sub + 1);
+            if (hasA) fft2_stageA<P, Q, TX, +1, T>(x, tA, j1, ex, tw);
             __syncthreads();
             if (hasB && colB) {
                 C y[P];
@@ -1497,19 +1549,25 @@ __device__ __forceinline__ void k_z2_fwd_body(const ZArgs<T, TU>& a, int tile_, 
     const T xs3 = T(a.g.xs3);
     __syncthreads();
     C v[3][P];
+    // step 2 i + sub reads component (sub ? 3 + i : i), one step ahead
+    C nx[Q];
+    auto load = [&](int step) {
+        const int c = (step & 1) ? 3 + (step >> 1) : (step >> 1);
+        const C* src = a.in + c * a.g.nspec + m0;   // uniform
+        const int Mi = (int)M;
+#pragma unroll
+        for (int j2 = 0; j2 < Q; ++j2) nx[j2] = (hasA && colA) ? src[tA + (j1 + P * j2) * Mi] : mk<T>(0, 0);
+    };
+    load(0);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
 #pragma unroll 1
         for (int sub = 0; sub < 2; ++sub) {
-            const int c = sub ? 3 + i : i;
-            if (hasA) {
-                C x[Q];
-                const C* src = a.in + c * a.g.nspec + m0;   // uniform
-                const int Mi = (int)M;
+            C x[Q];
 #pragma unroll
-                for (int j2 = 0; j2 < Q; ++j2) x[j2] = colA ? src[tA + (j1 + P * j2) * Mi] : mk<T>(0, 0);
-                fft2_stageA<P, Q, TX, -1, T>(x, tA, j1, ex, tw);
-            }
+            for (int j2 = 0; j2 < Q; ++j2) x[j2] = nx[j2];
+            if (2 * i + sub + 1 < 6) load(2 * i + sub + 1);
+            if (hasA) fft2_stageA<P, Q, TX, -1, T>(x, tA, j1, ex, tw);
             __syncthreads();
             if (hasB) {
                 C y[P];
@@ -1525,10 +1583,11 @@ __device__ __forceinline__ void k_z2_fwd_body(const ZArgs<T, TU>& a, int tile_, 
     }
     double s1 = 0.0, s2 = 0.0;
     if (hasB && colB) {
+        const ColFreq cf = col_freq(a.g, (int)(m0 + tB));   // one column per thread
 #pragma unroll
         for (int k2 = 0; k2 < P; ++k2) {
             C vv[3] = {v[0][k2], v[1][k2], v[2][k2]};
-            z_epilogue<T, TU, MODE>(a, m0 + tB, k1 + Q * k2, vv, s1, s2);
+            z_epilogue<T, TU, MODE>(a, cf, m0 + tB, k1 + Q * k2, vv, s1, s2);
         }
     }
     if (MODE == Z_CG || MODE == Z_RHS) {
