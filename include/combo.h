@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define COMBO_ABI_VERSION 3
+#define COMBO_ABI_VERSION 4
 
 typedef struct combo_ctx combo_ctx;
 typedef struct combo_batch combo_batch;
@@ -100,6 +100,8 @@ typedef struct {
     int max_cutbacks;         /* increment halvings */
     int graph_chunk;          /* CG iterations per captured HIP graph replay; 0 = plain launches */
     int autotune;             /* 1: pick the FFT schedule of the grid by timing (combo_autotune) before solving */
+    int line_search;          /* 1 (default): a Newton step F + s dF is taken only if the residual decreases,
+                                 eta(s) <= (1 - 1e-4 s) eta, halving s otherwise (max_step_halvings) */
 } combo_options;
 
 typedef struct {
@@ -128,7 +130,8 @@ int combo_abi_version(void);
 const char* combo_strerror(int status);
 /* Fill opt with the defaults: FP64, tol_newton 1e-8, tol_cg 1e-10, max_newton 30,
  * max_cg 5000, max_laminate 50, 1 increment, default C0, warm start on,
- * no tangent, 10 step halvings, 5 cutbacks, graph_chunk 0. */
+ * no tangent, 10 step halvings, 5 cutbacks, graph_chunk 0, no autotuning,
+ * line search on. */
 void combo_default_options(combo_options* opt);
 
 /* Host-only validation of a microstructure (no GPU needed).  Checks phase ids,

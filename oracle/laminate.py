@@ -31,7 +31,9 @@ appendix writes the volume average of the two tangents, which is what is used.)
 
 Readings where the paper is silent:
   * the stopping tolerance eps is not given: |f| <= 1e-12 max(|P+ N|, |P- N|,
-    1e-3 max(mu+, mu-)), or -- where round-off in f stalls above that, as for
+    1e-3 max(mu+, mu-), 1e-2 max(lambda+, lambda-)) -- the last term keeps the
+    test above the round-off of lambda ln J (about eps lambda) in nearly
+    incompressible phases -- or, where round-off in f stalls above that, as for
     a nearly collapsed soft phase -- a Newton correction |Delta^{-1} f| <=
     1e-13 max(|a|, 1e-3) (the current iterate is kept); at most 50 updates;
   * the oracle always starts from a = 0 (the paper's stated initialisation);
@@ -113,7 +115,10 @@ def solve(Fbox, c, N, mat_minus, mat_plus, backprojection=True, maxit=MAX_ITERS,
     nbp = np.zeros(m, dtype=int)
     active = good.copy()
     history = [a.copy()] if trace else None
-    floor = 1e-3 * max(mu_m, mu_p)
+    # scale floor of the traction test: 1e-3 max mu for small loads, and 1e-2 max lambda
+    # so that the tolerance (1e-14 lambda ~ 45 eps lambda) stays above the round-off of
+    # lambda ln J in nearly incompressible phases, where |f| cannot get below ~eps lambda
+    floor = max(1e-3 * max(mu_m, mu_p), 1e-2 * max(lam_m, lam_p))
     while True:
         Fp, Fm = phase_deformations(Fsafe, a, c, N)
         with np.errstate(invalid="ignore", divide="ignore"):

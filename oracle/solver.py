@@ -32,8 +32,10 @@ Readings where the paper is silent (the GPU solver uses the same ones):
   * load path Fbar_k = Fbar_0 + (k/K)(Fbar - Fbar_0), homogeneous predictor
     F += Fbar_k - Fbar_{k-1};
   * step control: F + s dF with s = 1, halved (at most 10 times) while any
-    voxel has det F <= 0 or a laminate fails; if that, the predictor or the
-    Newton loop fails, the increment is halved (at most 5 times);
+    voxel has det F <= 0 or a laminate fails, or (line search, on by default)
+    while the residual does not decrease, eta(s) > (1 - 1e-4 s) eta; if that,
+    the predictor or the Newton loop fails, the increment is halved (at most
+    5 times);
   * effective tangent: for each unit macro perturbation E = e_k (x) e_L solve
     Gamma^0 [A:dF] = -Gamma^0 [A:E] at the converged state and set
     Abar[:, 3k+L] = <A:(E + dF)>.
@@ -48,6 +50,7 @@ OK = 0
 E_NOCONV = -5
 E_INADMISSIBLE = -6
 E_NUMERIC = -7
+LS_ARMIJO = 1e-4   # sufficient decrease of the line search: eta(s) <= (1 - 1e-4 s) eta
 
 
 @dataclasses.dataclass
@@ -62,6 +65,7 @@ class Options:
     want_tangent: bool = False
     max_step_halvings: int = 10
     max_cutbacks: int = 5
+    line_search: bool = True   # accept F + s dF only if the residual decreases (Armijo)
 
 
 @dataclasses.dataclass
@@ -300,14 +304,17 @@ def solve(prob, Fbar, opts=None, F_init=None):
                     stats["cg_iters"] += it
                     stats["newton_iters"] += 1
                     s = 1.0
+                    accepted = False
                     for h in range(opts.max_step_halvings + 1):
                         Ft = F + s * dF
                         P_t, Av_t, ok_t, lst, lp_t = evaluate(Ft, prob)
-                        if ok_t:
+                        if ok_t and (not opts.line_search or
+                                     residual(P_t, prob) <= (1.0 - LS_ARMIJO * s) * eta):
+                            accepted = True
                             break
                         s *= 0.5
                         stats["step_halvings"] += 1
-                    if not ok_t:
+                    if not accepted:
                         break
                     F, P, Av, lam_parts = Ft, P_t, Av_t, lp_t
             if converged:

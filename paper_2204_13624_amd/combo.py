@@ -53,6 +53,7 @@ class combo_options(ctypes.Structure):
         ("max_cutbacks", ctypes.c_int),
         ("graph_chunk", ctypes.c_int),
         ("autotune", ctypes.c_int),
+        ("line_search", ctypes.c_int),
     ]
 
 

@@ -17,7 +17,8 @@
 //   P_box = c+ P+ + c- P-                                         (eq. Peff:Seff)
 //   A_box = c+ A+ + c- A- - dA D Delta^{-1} D^T dA,  with (D^T dA)_{k,pq} = dB_{k,pq},
 //   B_{k,pq} = sum_J N_J A_kJpq = mu d_kp N_q + lambda g_k Finv_qp + m g_p Finv_qk.
-// Stopping rule: |f| <= 1e-12 max(|P+ N|, |P- N|, 1e-3 max mu) or a Newton
+// Stopping rule: |f| <= 1e-12 max(|P+ N|, |P- N|, 1e-3 max mu, 1e-2 max lambda)
+// (the last term keeps the test above the round-off of lambda ln J) or a Newton
 // correction |Delta^{-1} f| <= 1e-13 max(|a|, 1e-3) (round-off stagnation);
 // at most max_laminate updates.  One thread per composite voxel.
 #include <hip/hip_runtime.h>
@@ -173,7 +174,7 @@ __device__ __forceinline__ void k_material_laminate_body(const MatArgs<T>& a, in
 #pragma unroll
         for (int d = 0; d < 3; ++d) N[d] = a.NN[(long long)d * a.nc + ic];
         const double mup = a.mu[1], lamp = a.lam[1], mum = a.mu[0], lamm = a.lam[0];
-        const double floor_t = 1e-3 * fmax(mup, mum);
+        const double floor_t = fmax(1e-3 * fmax(mup, mum), 1e-2 * fmax(lamp, lamm));
 
         int status = 1;   // 0 ok, 1 iteration limit, 2 bad F_box, 3 inadmissible
         int iters = 0, nbp = 0;

@@ -46,6 +46,9 @@ namespace {
 // non-positive curvature; x holds the iterate reached before it
 constexpr int kNegCurv = 1;
 
+// sufficient decrease of the Newton line search: eta(s) <= (1 - kArmijo s) eta
+constexpr double kArmijo = 1e-4;
+
 int set_err(combo_ctx* ctx, int status, const std::string& msg) {
     if (ctx) ctx->err = msg;
     return status;
@@ -805,11 +808,15 @@ int solve_impl(combo_ctx* ctx, const double Fbar[9], const double Fbar0[9], Solv
                 std::swap(ctx->a_prev.p, ctx->a_trial.p);
                 Fc = ctx->F_cur.as<double>();
                 Ft = ctx->F_trial.as<double>();
+                bool have_eta = false;   // the line search left the residual of the accepted step
                 for (int it_n = 0; it_n <= ctx->opt.max_newton; ++it_n) {
-                    auto tr = clk::now();
-                    st = residual<T>(ctx, mu0, kappa0, tol_cg, eta);
-                    S.time_ms_residual += ms_since(tr);
-                    if (st) return st;
+                    if (!have_eta) {
+                        auto tr = clk::now();
+                        st = residual<T>(ctx, mu0, kappa0, tol_cg, eta);
+                        S.time_ms_residual += ms_since(tr);
+                        if (st) return st;
+                    }
+                    have_eta = false;
                     if (verbose())
                         fprintf(stderr, "[combo] increment %d t=%.4f newton %d eta %.3e rho0 %.3e fails %g\n", k, tn,
                                 it_n, eta, ctx->hs->cg.rho0, material_failures(ctx));
@@ -838,6 +845,8 @@ int solve_impl(combo_ctx* ctx, const double Fbar[9], const double Fbar0[9], Solv
                     S.newton_iters += 1;
                     st = newton_direction<T>(ctx);
                     if (st) return st;
+                    // step control: admissible law everywhere and, with the line search,
+                    // sufficient decrease of the residual, eta(s) <= (1 - 1e-4 s) eta
                     double s = 1.0;
                     bool ok = false;
                     for (int h = 0; h <= ctx->opt.max_step_halvings; ++h) {
@@ -847,8 +856,21 @@ int solve_impl(combo_ctx* ctx, const double Fbar[9], const double Fbar0[9], Solv
                         S.time_ms_material += ms_since(tm);
                         if (st) return st;
                         if (material_failures(ctx) == 0.0) {
-                            ok = true;
-                            break;
+                            if (!ctx->opt.line_search) {
+                                ok = true;
+                                break;
+                            }
+                            double eta_t = 0.0;
+                            auto tr = clk::now();
+                            st = residual<T>(ctx, mu0, kappa0, tol_cg, eta_t);
+                            S.time_ms_residual += ms_since(tr);
+                            if (st) return st;
+                            if (eta_t <= (1.0 - kArmijo * s) * eta) {
+                                eta = eta_t;
+                                have_eta = true;
+                                ok = true;
+                                break;
+                            }
                         }
                         s *= 0.5;
                         S.step_halvings += 1;
@@ -994,7 +1016,7 @@ void plan_finalize(LaunchPlan& lp, int mode, const std::vector<FinArgs>& f, hipS
 // launch-group key: axis length, schedule variant, tile width or rows
 long long key2(long long len, long long tile, int variant = 0) { return (len << 40) | ((long long)variant << 32) | tile; }
 
-enum MemberPhase { PH_INC = 0, PH_RES, PH_CG, PH_STEP, PH_DONE, PH_FAIL };
+enum MemberPhase { PH_INC = 0, PH_RES, PH_CG, PH_STEP, PH_LSRES, PH_DONE, PH_FAIL };
 
 struct Member {
     combo_ctx* ctx = nullptr;
@@ -1069,6 +1091,59 @@ void member_finish(Member& m) {
     m.phase = PH_DONE;
 }
 
+// eta of the member's last residual evaluation
+double member_eta(const Member& m) {
+    const combo_ctx* ctx = m.ctx;
+    double Pbar[9];
+    material_pbar(ctx, Pbar);
+    const double den = (double)ctx->g.n * std::max(frob9(Pbar), 1e-300);
+    return std::sqrt(std::max(ctx->hs->cg.eta2, 0.0)) / den;
+}
+
+// Newton test after a residual at the current F (m.eta set)
+int member_after_residual(Member& m) {
+    combo_ctx* ctx = m.ctx;
+    combo_stats& S = m.out.st;
+    if (verbose())
+        fprintf(stderr, "[combo] member %d increment %d t=%.4f newton %d eta %.3e\n", m.index, m.k, m.tn, m.it_n,
+                m.eta);
+    if (!(m.eta == m.eta)) {
+        member_fail(m, COMBO_E_NUMERIC, "NaN in the equilibrium residual");
+        return COMBO_OK;
+    }
+    if (m.eta <= ctx->opt.tol_newton) {
+        const double* sm = ctx->hs->sums;
+        S.laminate_iters_total += (long long)sm[47];
+        S.laminate_backprojections += (long long)sm[48];
+        S.laminate_iters_max = std::max(S.laminate_iters_max, (int)sm[49]);
+        S.increments_done += 1;
+        m.t = m.tn;
+        if (m.t < m.t1 - 1e-15) {
+            member_begin_substep(m);
+        } else if (m.k < m.K) {
+            m.k += 1;
+            member_begin_increment(m);
+        } else {
+            member_finish(m);
+        }
+        return COMBO_OK;
+    }
+    if (m.it_n == ctx->opt.max_newton) return member_cutback(m);
+    m.cg_rounds = 0;
+    m.phase = PH_CG;
+    return COMBO_OK;
+}
+
+// the trial step was rejected: halve it, or give up the increment
+int member_halve_step(Member& m) {
+    m.s *= 0.5;
+    m.out.st.step_halvings += 1;
+    m.h += 1;
+    if (m.h > m.ctx->opt.max_step_halvings) return member_cutback(m);
+    m.phase = PH_STEP;
+    return COMBO_OK;
+}
+
 // host decision after the tick's scalars have been read back
 int member_advance(Member& m) {
     combo_ctx* ctx = m.ctx;
@@ -1082,40 +1157,9 @@ int member_advance(Member& m) {
                 return COMBO_OK;
             }
             return member_cutback(m);
-        case PH_RES: {
-            double Pbar[9];
-            material_pbar(ctx, Pbar);
-            const double den = (double)ctx->g.n * std::max(frob9(Pbar), 1e-300);
-            m.eta = std::sqrt(std::max(ctx->hs->cg.eta2, 0.0)) / den;
-            if (verbose())
-                fprintf(stderr, "[combo] member %d increment %d t=%.4f newton %d eta %.3e\n", m.index, m.k, m.tn,
-                        m.it_n, m.eta);
-            if (!(m.eta == m.eta)) {
-                member_fail(m, COMBO_E_NUMERIC, "NaN in the equilibrium residual");
-                return COMBO_OK;
-            }
-            if (m.eta <= ctx->opt.tol_newton) {
-                const double* sm = ctx->hs->sums;
-                S.laminate_iters_total += (long long)sm[47];
-                S.laminate_backprojections += (long long)sm[48];
-                S.laminate_iters_max = std::max(S.laminate_iters_max, (int)sm[49]);
-                S.increments_done += 1;
-                m.t = m.tn;
-                if (m.t < m.t1 - 1e-15) {
-                    member_begin_substep(m);
-                } else if (m.k < m.K) {
-                    m.k += 1;
-                    member_begin_increment(m);
-                } else {
-                    member_finish(m);
-                }
-                return COMBO_OK;
-            }
-            if (m.it_n == ctx->opt.max_newton) return member_cutback(m);
-            m.cg_rounds = 0;
-            m.phase = PH_CG;
-            return COMBO_OK;
-        }
+        case PH_RES:
+            m.eta = member_eta(m);
+            return member_after_residual(m);
         case PH_CG: {
             const CGState& cg = ctx->hs->cg;
             if (!cg.done) {
@@ -1145,16 +1189,27 @@ int member_advance(Member& m) {
         }
         case PH_STEP:
             if (material_failures(ctx) == 0.0) {
+                if (ctx->opt.line_search) {
+                    m.phase = PH_LSRES;   // residual of the trial before it is taken
+                    return COMBO_OK;
+                }
                 member_accept_swap(m);
                 m.it_n += 1;
                 m.phase = PH_RES;
                 return COMBO_OK;
             }
-            m.s *= 0.5;
-            S.step_halvings += 1;
-            m.h += 1;
-            if (m.h > ctx->opt.max_step_halvings) return member_cutback(m);
-            return COMBO_OK;
+            return member_halve_step(m);
+        case PH_LSRES: {
+            const double eta_t = member_eta(m);
+            if (eta_t <= (1.0 - kArmijo * m.s) * m.eta) {
+                member_accept_swap(m);
+                m.it_n += 1;
+                m.eta = eta_t;
+                return member_after_residual(m);
+            }
+            m.phase = PH_STEP;
+            return member_halve_step(m);
+        }
         default: return COMBO_OK;
     }
 }
@@ -1291,7 +1346,7 @@ void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
         std::vector<long long> kx, ky, kz, ku;
         std::vector<int> nx, ny, nz, nu;
         for (Member& m : ms) {
-            if (m.phase != PH_RES) continue;
+            if (m.phase != PH_RES && m.phase != PH_LSRES) continue;
             combo_ctx* ctx = m.ctx;
             XArgs<double> x = xargs<double>(ctx);
             x.real_in = ctx->P.as<double>();
@@ -1430,7 +1485,8 @@ const char* options_error(const combo_options* o) {
     if (o->precision != COMBO_FP64 && o->precision != COMBO_MIXED) return "precision must be COMBO_FP64 or COMBO_MIXED";
     if (!(o->tol_newton > 0) || !(o->tol_cg > 0) || o->max_newton < 0 || o->max_cg < 1 || o->max_laminate < 0 ||
         o->max_laminate > 64 || o->n_increments < 1 || o->max_step_halvings < 0 || o->max_cutbacks < 0 ||
-        o->graph_chunk < 0 || o->graph_chunk > 256 || o->autotune < 0 || o->autotune > 1)
+        o->graph_chunk < 0 || o->graph_chunk > 256 || o->autotune < 0 || o->autotune > 1 ||
+        o->line_search < 0 || o->line_search > 1)
         return "option out of range";
     return nullptr;
 }
@@ -1509,6 +1565,7 @@ void combo_default_options(combo_options* o) {
     o->max_cutbacks = 5;
     o->graph_chunk = 0;
     o->autotune = 0;
+    o->line_search = 1;
 }
 
 int combo_check_size(int n) { return size_ok(n) ? COMBO_OK : COMBO_E_SIZE; }
