@@ -73,6 +73,30 @@ def test_law_matches_oracle_per_voxel(ctx, n, seed, amp):
         assert np.abs(ag - lp["a"]).max() <= 1e-11 * max(1.0, np.abs(lp["a"]).max())
 
 
+def test_law_nearly_incompressible_matches_oracle(ctx):
+    """lambda/mu = 1000 in both phases, fibre contrast 1000 (the fibre workload's materials): the FP64
+    det F / ln J path and the laminate's round-off floor."""
+    n = (16, 12, 6)
+    mats = ((1.0, 1000.0), (1000.0, 1.0e6))
+    ms = synth.random_composite_field(n, 4, frac_composite=0.6)
+    setup(ctx, ms, mats)
+    nv = ms.nvox
+    for amp in (1e-4, 0.02):
+        F = synth.random_F_field(n, 8, amplitude=amp)
+        P = np.zeros_like(F)
+        A = np.zeros((81,) + F.shape[1:])
+        a = np.zeros((3,) + F.shape[1:])
+        it = np.zeros(F.shape[1:], dtype=np.int32)
+        assert combo.combo_eval_law(ctx, F, P, A, a, it) == combo.COMBO_OK, combo.combo_last_error(ctx)
+        Po, Av, ok, st, lp = osol.evaluate(F.reshape(3, 3, *F.shape[1:]), oracle_problem(ms, mats))
+        assert ok and st["lam_fail"] == 0
+        assert rel(P.reshape(9, nv), Po.reshape(9, nv)) <= 1e-11, amp
+        assert rel(np.moveaxis(A.reshape(81, nv), 0, 1), Av.reshape(nv, 81)) <= 1e-9, amp
+        ag = a.reshape(3, nv)[:, lp["idx"]].T
+        assert np.abs(ag - lp["a"]).max() <= 1e-9 * max(1e-3, np.abs(lp["a"]).max()), amp
+        assert int(it.max()) < 50   # no laminate at the update cap
+
+
 def test_law_backprojection_cases_match_oracle(ctx):
     """Extreme fractions, contrast 1000 and compression: the back-projection path."""
     n = (16, 8, 4)
@@ -200,6 +224,20 @@ def test_homogeneous_and_laminate_pins_on_gpu(ctx):
     r = combo.combo_solve(ctx, FBAR)
     ref = osol.solve(oracle_problem(ms), FBAR, osol.Options(tol_newton=1e-12, tol_cg=1e-12))
     assert rel(r["Pbar"], ref["Pbar"]) <= 1e-11
+
+
+def test_nearly_incompressible_solve_matches_oracle(ctx):
+    """Stiff nearly incompressible sphere in a nearly incompressible matrix under shear."""
+    ms = synth.single_sphere((12, 12, 12), radius=0.3, center=(0.03, -0.02, 0.01))
+    mats = ((1.0, 1000.0), (30.0, 30000.0))
+    Fb = synth.shear12(0.02)
+    ref = osol.solve(oracle_problem(ms, mats), Fb, osol.Options(tol_newton=1e-10, tol_cg=1e-12, n_increments=2))
+    setup(ctx, ms, mats, tol_newton=1e-10, tol_cg=1e-12, n_increments=2)
+    r = combo.combo_solve(ctx, Fb)
+    assert rel(r["Pbar"], ref["Pbar"]) <= 1e-8
+    setup(ctx, ms, mats, tol_newton=1e-7, tol_cg=1e-5, n_increments=2, precision=combo.COMBO_MIXED)
+    rm = combo.combo_solve(ctx, Fb)
+    assert rel(rm["Pbar"], ref["Pbar"]) <= 1e-6
 
 
 def test_effective_tangent_matches_oracle(ctx):
