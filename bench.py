@@ -113,6 +113,7 @@ def batch_bench(combo, synth, steps):
     o.tol_cg = 1e-4
     o.max_cg = 20000
     o.autotune = 1
+    o.graph_chunk = 0   # plain launches: captured chunks measured no faster (GPU-bound)
     b = combo.combo_batch_create(0)
     combo.combo_batch_set_options(b, o)
     for ms, lc in items:
@@ -141,6 +142,7 @@ def batch_bench(combo, synth, steps):
         for k, _ in o._fields_:
             setattr(oo, k, getattr(o, k))
         oo.n_increments = lc.n_increments
+        oo.graph_chunk = 0
         combo.combo_set_options(c, oo)
         combo.combo_autotune(c, combo.COMBO_MIXED)   # cached: same schedules as the batch
         ctxs.append(c)

@@ -249,7 +249,9 @@ int combo_batch_create(combo_batch** out, int device, void* hip_stream);
 int combo_batch_destroy(combo_batch* b);
 /* Message of the last failed call on b (member failures name the member). */
 const char* combo_batch_last_error(const combo_batch* b);
-/* Options of every member (validated as combo_set_options; graph_chunk is ignored). */
+/* Options of every member (validated as combo_set_options).  graph_chunk > 0:
+ * the CG iterations of the members in CG run in chunks of that many, captured
+ * once as a HIP graph and replayed while the same members stay in CG. */
 int combo_batch_set_options(combo_batch* b, const combo_options* opt);
 /* Append one RVE: grid and box as combo_set_grid, materials as
  * combo_set_materials, microstructure as combo_set_microstructure (pointers of

@@ -948,6 +948,14 @@ struct LaunchPlan {
     std::vector<char> host;
     std::vector<std::function<hipError_t(char*)>> ops;
     DevBuf dev;
+    char* pinned = nullptr;   // staging for asynchronous uploads
+    size_t pinned_cap = 0;
+    LaunchPlan() = default;
+    LaunchPlan(const LaunchPlan&) = delete;
+    LaunchPlan& operator=(const LaunchPlan&) = delete;
+    ~LaunchPlan() {
+        if (pinned) (void)hipHostFree(pinned);
+    }
     size_t put(const void* src, size_t bytes) {
         const size_t off = (host.size() + 255) & ~(size_t)255;
         host.resize(off + bytes);
@@ -958,12 +966,22 @@ struct LaunchPlan {
         host.clear();
         ops.clear();
     }
-    // nothing may be in flight on the stream that reads `dev`
-    hipError_t upload() {
+    // Copies the tables to the device, in stream order.  Nothing may be in flight on
+    // the stream that reads `dev` or `pinned` (the batch synchronises every tick).
+    hipError_t upload(hipStream_t s) {
         if (host.empty()) return hipSuccess;
         hipError_t e = dev.ensure(host.size());
         if (e != hipSuccess) return e;
-        return hipMemcpy(dev.p, host.data(), host.size(), hipMemcpyHostToDevice);
+        if (pinned_cap < host.size()) {
+            if (pinned) (void)hipHostFree(pinned);
+            pinned = nullptr;
+            pinned_cap = 0;
+            e = hipHostMalloc((void**)&pinned, host.size() * 2, hipHostMallocDefault);
+            if (e != hipSuccess) return e;
+            pinned_cap = host.size() * 2;
+        }
+        memcpy(pinned, host.data(), host.size());
+        return hipMemcpyAsync(dev.p, pinned, host.size(), hipMemcpyHostToDevice, s);
     }
     hipError_t run() const {
         for (const auto& op : ops) {
@@ -1438,6 +1456,17 @@ void plan_cg(combo_batch* B, std::vector<Member>& ms, const std::vector<int>& li
     plan_finalize(lp, FIN_BETA, fbe, s);
 }
 
+// COMBO_BATCH_STATS=1 in the environment prints one line per batch solve: ticks,
+// host planning time, time waiting for the GPU, and members still active over time.
+bool batch_stats() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("COMBO_BATCH_STATS");
+        v = (e && e[0] && e[0] != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
+
 template <typename T>
 int batch_solve_impl(combo_batch* B, std::vector<Member>& ms) {
     const size_t stride = combo_batch::kScalStride;
@@ -1445,27 +1474,73 @@ int batch_solve_impl(combo_batch* B, std::vector<Member>& ms) {
     LaunchPlan tick, cgp;
     std::vector<int> cg_list, cg_prev;
     bool cg_valid = false;
-    const int chunk = 8;
+    // graph_chunk > 0: CG chunks of that many iterations, captured as a hipGraph once
+    // the set of members in CG has stayed the same for a tick, and replayed until it changes
+    const bool use_graph = B->opt.graph_chunk > 0;
+    const int chunk = use_graph ? B->opt.graph_chunk : 8;
+    hipGraph_t cg_graph = nullptr;
+    hipGraphExec_t cg_exec = nullptr;
+    int cg_same = 0;
+    long long graph_ticks = 0;
+    auto drop_graph = [&]() {
+        if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
+        if (cg_graph) (void)hipGraphDestroy(cg_graph);
+        cg_exec = nullptr;
+        cg_graph = nullptr;
+    };
+    long long ticks = 0, cg_ticks = 0, cg_rebuilds = 0;
+    double host_ms = 0.0, wait_ms = 0.0, tail_ms = 0.0;
+    const auto t_begin = clk::now();
     for (;;) {
         bool active = false;
         for (Member& m : ms) active = active || (m.phase != PH_DONE && m.phase != PH_FAIL);
         if (!active) break;
+        const auto t_plan = clk::now();
+        ++ticks;
         plan_tick<T>(B, ms, tick);
-        BHIP_OR_FAIL(tick.upload());
+        BHIP_OR_FAIL(tick.upload(B->stream));
         cg_list.clear();
         for (size_t i = 0; i < nm; ++i)
             if (ms[i].phase == PH_CG) cg_list.push_back((int)i);
         if (!cg_list.empty() && (!cg_valid || cg_list != cg_prev)) {
+            drop_graph();
+            cg_same = 0;
             plan_cg<T>(B, ms, cg_list, cgp);
-            BHIP_OR_FAIL(cgp.upload());
+            BHIP_OR_FAIL(cgp.upload(B->stream));
             cg_prev = cg_list;
             cg_valid = true;
+            ++cg_rebuilds;
+        } else if (!cg_list.empty()) {
+            ++cg_same;
         }
         BHIP_OR_FAIL(tick.run());
-        if (!cg_list.empty())
-            for (int k = 0; k < chunk; ++k) BHIP_OR_FAIL(cgp.run());
+        if (!cg_list.empty()) {
+            ++cg_ticks;
+            if (use_graph && cg_same >= 1 && !cg_exec) {
+                BHIP_OR_FAIL(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+                hipError_t ce = hipSuccess;
+                for (int k = 0; k < chunk && ce == hipSuccess; ++k) ce = cgp.run();
+                hipError_t ee = hipStreamEndCapture(B->stream, &cg_graph);
+                BHIP_OR_FAIL(ce);
+                BHIP_OR_FAIL(ee);
+                BHIP_OR_FAIL(hipGraphInstantiate(&cg_exec, cg_graph, nullptr, nullptr, 0));
+            }
+            if (cg_exec) {
+                BHIP_OR_FAIL(hipGraphLaunch(cg_exec, B->stream));
+                ++graph_ticks;
+            } else {
+                for (int k = 0; k < chunk; ++k) BHIP_OR_FAIL(cgp.run());
+            }
+        }
         BHIP_OR_FAIL(hipMemcpyAsync(B->hscal, B->scal.p, stride * nm, hipMemcpyDeviceToHost, B->stream));
+        const auto t_wait = clk::now();
+        host_ms += std::chrono::duration<double, std::milli>(t_wait - t_plan).count();
         BHIP_OR_FAIL(hipStreamSynchronize(B->stream));
+        const double w = ms_since(t_wait);
+        wait_ms += w;
+        size_t live = 0;
+        for (Member& m : ms) live += (m.phase != PH_DONE && m.phase != PH_FAIL) ? 1 : 0;
+        if (live * 4 <= nm) tail_ms += w;   // GPU time while at most a quarter of the members are left
         for (size_t i = 0; i < nm; ++i) {
             Member& m = ms[i];
             if (m.phase == PH_DONE || m.phase == PH_FAIL) continue;
@@ -1478,6 +1553,11 @@ int batch_solve_impl(combo_batch* B, std::vector<Member>& ms) {
             }
         }
     }
+    drop_graph();
+    if (batch_stats())
+        fprintf(stderr, "[combo] batch: %zu members, %lld ticks (%lld with CG, %lld from a graph, %lld CG plan rebuilds), "
+                        "host %.1f ms, GPU wait %.1f ms (%.1f ms with <= 1/4 of the members left), wall %.1f ms\n",
+                nm, ticks, cg_ticks, graph_ticks, cg_rebuilds, host_ms, wait_ms, tail_ms, ms_since(t_begin));
     return COMBO_OK;
 }
 

@@ -128,6 +128,25 @@ def test_batch_equals_single_solves(precision):
         combo.combo_batch_destroy(b)
 
 
+def test_batch_graph_chunks_equal_plain_launches():
+    """Captured CG chunks (graph_chunk > 0) replay the same launches as plain ones."""
+    mem = members()
+    Fb = np.stack([m[2] for m in mem])
+    K = [m[3] for m in mem]
+    out = []
+    for gc in (0, 8):
+        opts = options(precision=combo.COMBO_FP64, tol_newton=1e-10, tol_cg=1e-11, graph_chunk=gc)
+        b = make_batch(mem, opts)
+        try:
+            out.append(combo.combo_batch_solve(b, Fb, n_increments=K))
+        finally:
+            combo.combo_batch_destroy(b)
+    for i in range(len(mem)):
+        assert out[0]["stats"][i]["newton_iters"] == out[1]["stats"][i]["newton_iters"]
+        assert out[0]["stats"][i]["cg_iters_total"] == out[1]["stats"][i]["cg_iters_total"]
+        assert np.array_equal(out[0]["Pbar"][i], out[1]["Pbar"][i]), i
+
+
 def test_batch_member_matches_oracle():
     mem = members()[:3]
     opts = options(tol_newton=1e-10, tol_cg=1e-12)
