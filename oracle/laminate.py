@@ -1,4 +1,5 @@
-"""Composite boxel (ComBo) rank-one laminate law at finite strain (paper Sec. 4).
+"""Composite boxel (ComBo) rank-one laminate law at finite strain (paper Sec. 4),
+and its infinitesimal-strain closed form (appendix cheat sheet, solve_small).
 
 A composite voxel with inclusion fraction c+ = c, matrix fraction c- = 1 - c and
 interface normal N (out of the inclusion) receives the voxel deformation F_box.
@@ -174,6 +175,49 @@ def solve(Fbox, c, N, mat_minus, mat_plus, backprojection=True, maxit=MAX_ITERS,
         out["m_beta"] = mb
         out["beta_c"] = (beta_p, beta_m)
     return out
+
+
+def solve_small(Hbox, c, N, mat_minus, mat_plus):
+    """Small-strain ComBo laminate in closed form (appendix cheat sheet, right column).
+
+    Hbox [m,3,3] displacement gradient of the voxel (eps_box = sym(Hbox)),
+    c [m] = c+, N [m,3], materials (mu, lambda) of isotropic phases.  With
+    C+- the stiffnesses (isotropic_stiffness) and dC = C+ - C-:
+        Delta_ik = N_j (C+/c+ + C-/c-)_ijkl N_l              (Hessian row)
+        a = Delta^{-1} [(C- - C+) : eps_box] N               (update of a)
+        eps+- = eps_box +- sym(a (x) N) / c+-                (deformation row)
+        sigma_box = c+ C+ : eps+ + c- C- : eps-              (stress row)
+        C_box = c+ C+ + c- C- - dC D Delta^{-1} D^T dC       (tangent row)
+    with D the 9x3 map a -> vec(a (x) N) of the finite-strain law.  The law is
+    linear, so no iteration is needed and C_box : eps_box = sigma_box.
+    Returns P (= sigma_box) [m,3,3], A (= C_box) [m,9,9], a [m,3] and the
+    phase strains and stresses (Pp, Pm are sigma+-)."""
+    H = np.asarray(Hbox, float)
+    c = np.asarray(c, float)
+    N = np.asarray(N, float)
+    (mu_m, lam_m), (mu_p, lam_p) = mat_minus, mat_plus
+    cp, cm = c, 1.0 - c
+    Cp = material.isotropic_stiffness(mu_p, lam_p).reshape(3, 3, 3, 3)
+    Cm = material.isotropic_stiffness(mu_m, lam_m).reshape(3, 3, 3, 3)
+    eps = 0.5 * (H + np.swapaxes(H, -1, -2))
+    Delta = (np.einsum("mj,ijkl,ml->mik", N, Cp, N) / cp[:, None, None]
+             + np.einsum("mj,ijkl,ml->mik", N, Cm, N) / cm[:, None, None])
+    rhs = np.einsum("ijkl,mkl,mj->mi", Cm - Cp, eps, N)
+    a = np.linalg.solve(Delta, rhs[..., None])[..., 0]
+    aN = np.einsum("mi,mj->mij", a, N)
+    saN = 0.5 * (aN + np.swapaxes(aN, 1, 2))
+    eps_p = eps + saN / cp[:, None, None]
+    eps_m = eps - saN / cm[:, None, None]
+    sig_p = np.einsum("ijkl,mkl->mij", Cp, eps_p)
+    sig_m = np.einsum("ijkl,mkl->mij", Cm, eps_m)
+    P = cp[:, None, None] * sig_p + cm[:, None, None] * sig_m
+    D = jump_matrix(N)
+    dC = (Cp - Cm).reshape(9, 9)
+    Cbar = (cp[:, None, None] * Cp.reshape(1, 9, 9) + cm[:, None, None] * Cm.reshape(1, 9, 9))
+    A = Cbar - dC @ D @ np.linalg.inv(Delta) @ np.swapaxes(D, 1, 2) @ dC
+    m = H.shape[0]
+    return dict(P=P, A=A, a=a, iters=np.zeros(m, dtype=int), n_backproj=np.zeros(m, dtype=int),
+                status=np.full(m, STATUS_OK, dtype=int), Pp=sig_p, Pm=sig_m, eps_p=eps_p, eps_m=eps_m)
 
 
 def potential(a, Fbox, c, N, mat_minus, mat_plus):

@@ -61,3 +61,13 @@ def isotropic_stiffness(mu, lam):
     C = (lam * np.einsum("iJ,kL->iJkL", eye, eye)
          + mu * (np.einsum("ik,JL->iJkL", eye, eye) + np.einsum("iL,Jk->iJkL", eye, eye)))
     return C.reshape(9, 9)
+
+
+def linear_stress(F, mu, lam):
+    """Small-strain isotropic law sigma = lambda tr(eps) I + 2 mu eps with
+    eps = sym(H), H = F - I the displacement gradient (infinitesimal strain
+    theory of the appendix cheat sheet; the stiffness is isotropic_stiffness)."""
+    H = F - np.eye(3)
+    eps = 0.5 * (H + np.swapaxes(H, -1, -2))
+    tr = np.trace(eps, axis1=-2, axis2=-1)[..., None, None]
+    return lam * tr * np.eye(3) + 2.0 * mu * eps

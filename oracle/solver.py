@@ -4,7 +4,10 @@ with composite boxels (paper Sec. 2, 3 and 4).
 Problem (HOM, Sec. 2): given the macroscopic deformation gradient Fbar, find a
 periodic fluctuation such that Div P = 0, with P = P(F) the pointwise material
 law: compressible Neo-Hooke in pure voxels (Sec. 6.1), the ComBo laminate in
-composite voxels (Sec. 4).  Outputs: Pbar = <P> (eq. Pbar), the phase averages
+composite voxels (Sec. 4); or, with Problem.law = "linear", the infinitesimal
+strain counterparts of the appendix cheat sheet (isotropic linear elasticity and
+the closed-form laminate), where P is the stress of sym(F - I) and one Newton
+step solves the problem up to the CG tolerance.  Outputs: Pbar = <P> (eq. Pbar), the phase averages
 and the algorithmic effective tangent dPbar/dFbar (mentioned in Sec. 2).
 
 Method (Sec. 3): Newton-Raphson on the Lippmann-Schwinger equation
@@ -76,6 +79,7 @@ class Problem:
     c: np.ndarray       # [n3, n2, n1]
     N: np.ndarray       # [3, n3, n2, n1]
     mats: tuple         # ((mu-, lam-), (mu+, lam+))
+    law: str = "neo_hooke"   # or "linear": small strain, P = sigma(sym(F - I))
 
     @property
     def shape(self):
@@ -130,6 +134,8 @@ def evaluate(F, prob):
     ok = True
     stats = dict(lam_iters=0, lam_iters_max=0, lam_backproj=0, lam_fail=0)
     lam_parts = {}
+    if prob.law == "linear":
+        return _evaluate_linear(Fv, prob, phase, Pv, Av, stats)
     for ph in (0, 1):
         idx = np.nonzero(phase == ph)[0]
         if idx.size == 0:
@@ -156,6 +162,25 @@ def evaluate(F, prob):
         Av[idx] = r["A"]
         lam_parts = dict(idx=idx, Pp=r["Pp"], Pm=r["Pm"], a=r["a"])
     return to_field(Pv, prob.shape), Av, ok, stats, lam_parts
+
+
+def _evaluate_linear(Fv, prob, phase, Pv, Av, stats):
+    """Small-strain law: isotropic linear elasticity in pure voxels, the closed-form
+    laminate of the appendix cheat sheet in composite voxels (no admissibility)."""
+    for ph in (0, 1):
+        idx = np.nonzero(phase == ph)[0]
+        mu, lam = prob.mats[ph]
+        Pv[idx] = material.linear_stress(Fv[idx], mu, lam)
+        Av[idx] = material.isotropic_stiffness(mu, lam)
+    lam_parts = {}
+    idx = np.nonzero(phase == 2)[0]
+    if idx.size:
+        r = laminate.solve_small(Fv[idx] - np.eye(3), prob.c.reshape(-1)[idx],
+                                 prob.N.reshape(3, -1)[:, idx].T, prob.mats[0], prob.mats[1])
+        Pv[idx] = r["P"]
+        Av[idx] = r["A"]
+        lam_parts = dict(idx=idx, Pp=r["Pp"], Pm=r["Pm"], a=r["a"])
+    return to_field(Pv, prob.shape), Av, True, stats, lam_parts
 
 
 def apply_tangent(Av, p, shape):
@@ -255,7 +280,7 @@ def solve(prob, Fbar, opts=None, F_init=None):
     opts = opts or Options()
     shape = prob.shape
     Fbar = np.asarray(Fbar, float).reshape(3, 3)
-    if np.linalg.det(Fbar) <= 0:
+    if prob.law != "linear" and np.linalg.det(Fbar) <= 0:
         raise SolveError(E_INADMISSIBLE, "det Fbar <= 0")
     mu0, kappa0 = reference_medium(prob.mats, opts.mu0, opts.kappa0)
     if F_init is None:
