@@ -178,6 +178,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-small-strain", action="store_true")
     ap.add_argument("--increments", type=int, default=0,
                     help="override the workload's load increments (shorter runs for counter collection)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -312,6 +313,28 @@ def main():
         out["pbar_rel_diff_mixed_vs_fp64"] = float(np.abs(Pbar_mixed - r64["Pbar"]).max() /
                                                    np.abs(r64["Pbar"]).max())
         log("fp64: %.2f s, cg %d" % (out["time_to_solution_s"]["fp64"], r64["stats"]["cg_iters_total"]))
+    if not args.no_small_strain:
+        # the same RVE under the small-strain law (closed-form laminate): one linear solve
+        o = options(combo.COMBO_MIXED)
+        o.law = combo.COMBO_LAW_LINEAR
+        o.n_increments = 1
+        combo.combo_set_options(ctx, o)
+        combo.combo_solve(ctx, lc.Fbar)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cg_lin = 0
+        for k in range(args.steps):
+            rl = combo.combo_solve(ctx, lc.Fbar)
+            cg_lin += rl["stats"]["cg_iters_total"]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        out["small_strain"] = {"law": "linear (closed-form laminate)", "precision": "mixed",
+                               "load": "H = 0.2 e1 (x) e1, eta<=1e-6, tol_cg %.0e" % args.tol_cg,
+                               "time_to_solution_s": el / args.steps, "newton_iters": rl["stats"]["newton_iters"],
+                               "cg_iters": cg_lin / args.steps, "voxel_cg_iters_per_s": n * cg_lin / el,
+                               "laminate_ms": rl["stats"]["time_ms_material"]}
+        log("small strain: %.3f s, newton %d, cg %d" % (el / args.steps, rl["stats"]["newton_iters"],
+                                                         rl["stats"]["cg_iters_total"]))
     combo.combo_destroy(ctx)
     out["batch"] = None if args.no_batch else batch_bench(combo, synth, args.steps)
     if not args.no_cpu:

@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define COMBO_ABI_VERSION 4
+#define COMBO_ABI_VERSION 5
 
 typedef struct combo_ctx combo_ctx;
 typedef struct combo_batch combo_batch;
@@ -85,6 +85,19 @@ typedef struct {
     double lambda;
 } combo_material;
 
+/* Constitutive laws (combo_options.law).
+ * COMBO_LAW_NEO_HOOKE: finite strain.  Pure voxels: compressible Neo-Hooke
+ *   (paper Sec. 6.1); composite voxels: the rank-one laminate solved by
+ *   Newton-Raphson with selective back-projection (Sec. 4, Alg. 1 and 2).
+ * COMBO_LAW_LINEAR: infinitesimal strain (appendix cheat sheet, right column).
+ *   F is read as I + grad u and P as the stress of eps = sym(F - I).  Pure voxels:
+ *   sigma = lambda tr(eps) I + 2 mu eps; composite voxels: the laminate jump in
+ *   closed form, a = Delta^{-1} N.(C- - C+) eps_box, with stress and tangent of
+ *   the same table.  The problem is linear: one Newton step solves it up to the
+ *   CG tolerance, and no det F or admissibility condition applies. */
+#define COMBO_LAW_NEO_HOOKE 0
+#define COMBO_LAW_LINEAR 1
+
 typedef struct {
     int precision;            /* COMBO_FP64 or COMBO_MIXED */
     double tol_newton;        /* eta = |G[P]|_2 / (sqrt(n) |Pbar|_F) <= tol_newton */
@@ -102,6 +115,7 @@ typedef struct {
     int autotune;             /* 1: pick the FFT schedule of the grid by timing (combo_autotune) before solving */
     int line_search;          /* 1 (default): a Newton step F + s dF is taken only if the residual decreases,
                                  eta(s) <= (1 - 1e-4 s) eta, halving s otherwise (max_step_halvings) */
+    int law;                  /* COMBO_LAW_NEO_HOOKE (default) or COMBO_LAW_LINEAR */
 } combo_options;
 
 typedef struct {
@@ -131,7 +145,7 @@ const char* combo_strerror(int status);
 /* Fill opt with the defaults: FP64, tol_newton 1e-8, tol_cg 1e-10, max_newton 30,
  * max_cg 5000, max_laminate 50, 1 increment, default C0, warm start on,
  * no tangent, 10 step halvings, 5 cutbacks, graph_chunk 0, no autotuning,
- * line search on. */
+ * line search on, Neo-Hooke law. */
 void combo_default_options(combo_options* opt);
 
 /* Host-only validation of a microstructure (no GPU needed).  Checks phase ids,

@@ -30,6 +30,8 @@ COMBO_FP64 = 0
 COMBO_MIXED = 1
 COMBO_GREEN_GAMMA0 = 0
 COMBO_GREEN_G = 1
+COMBO_LAW_NEO_HOOKE = 0
+COMBO_LAW_LINEAR = 1
 
 
 class combo_material(ctypes.Structure):
@@ -54,6 +56,7 @@ class combo_options(ctypes.Structure):
         ("graph_chunk", ctypes.c_int),
         ("autotune", ctypes.c_int),
         ("line_search", ctypes.c_int),
+        ("law", ctypes.c_int),
     ]
 
 

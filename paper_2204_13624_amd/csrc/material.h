@@ -24,6 +24,7 @@ struct MatArgs {
     double* a_out;          // [3][nc]
     int warm;
     int maxit;
+    int law;                // kLawNeoHooke or kLawLinear
     T* Sinv;                // [9][n] tangent state at state_pos(voxel) (null: not wanted)
     T* sm;                  // [n]
     int n1, xm, xwbits;     // state layout (see state_pos)
@@ -34,6 +35,11 @@ struct MatArgs {
     double* partials;       // [blocks_pure][19]
     double* partials2;      // [blocks_laminate][31]
 };
+
+// Constitutive laws: finite-strain Neo-Hooke with the Newton-Raphson laminate, or
+// small-strain isotropic elasticity with the closed-form laminate.
+constexpr int kLawNeoHooke = 0;
+constexpr int kLawLinear = 1;
 
 // Layout of the reduced sums written by launch_material (50 doubles):
 //   [0, 9)   sum of P over matrix voxels       [9, 18)  over inclusion voxels

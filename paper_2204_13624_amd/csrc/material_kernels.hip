@@ -17,6 +17,11 @@
 //   P_box = c+ P+ + c- P-                                         (eq. Peff:Seff)
 //   A_box = c+ A+ + c- A- - dA D Delta^{-1} D^T dA,  with (D^T dA)_{k,pq} = dB_{k,pq},
 //   B_{k,pq} = sum_J N_J A_kJpq = mu d_kp N_q + lambda g_k Finv_qp + m g_p Finv_qk.
+// Small-strain law (law == kLawLinear, appendix cheat sheet, infinitesimal column):
+//   sigma = lambda tr(eps) I + 2 mu eps, eps = sym(F - I), whose stiffness is the
+//   Neo-Hooke tangent at F = I (state {I, mu}); the laminate jump is the closed form
+//   a = -Delta^{-1} f(0) with f(0) = (sigma+(eps_box) - sigma-(eps_box)) N and g = N in
+//   Delta, after which the stress and tangent formulas above apply unchanged.
 // Stopping rule: |f| <= 1e-12 max(|P+ N|, |P- N|, 1e-3 max mu, 1e-2 max lambda)
 // (the last term keeps the test above the round-off of lambda ln J) or a Newton
 // correction |Delta^{-1} f| <= 1e-13 max(|a|, 1e-3) (round-off stagnation);
@@ -57,6 +62,22 @@ __device__ __forceinline__ void nh_stress(const double* F, double J, double mu, 
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int J2 = 0; J2 < 3; ++J2) P[3 * i + J2] = mu * F[3 * i + J2] - m * Finv[3 * J2 + i];
+}
+
+// small-strain isotropic stress of the displacement gradient F - I; Finv = I and
+// m = mu make the Neo-Hooke tangent formulas give the isotropic stiffness
+__device__ __forceinline__ void lin_stress(const double* F, double mu, double lam, double* Finv, double* P,
+                                           double& m) {
+    const double tr = F[0] + F[4] + F[8] - 3.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) {
+            const double e = 0.5 * (F[3 * i + J] + F[3 * J + i]) - (i == J ? 1.0 : 0.0);
+            P[3 * i + J] = 2.0 * mu * e + (i == J ? lam * tr : 0.0);
+            Finv[3 * i + J] = (i == J) ? 1.0 : 0.0;
+        }
+    m = mu;
 }
 
 // full tangent entry A_(iJ)(kL) of Neo-Hooke
@@ -109,15 +130,19 @@ __device__ __forceinline__ void k_material_pure_body(const MatArgs<T>& a, int ti
         if (slot >= 0) continue;
         const int ph = (slot == -1) ? 0 : 1;
         const double mu = a.mu[ph], lam = a.lam[ph];
-        const double J = det3(F);
         double Finv[9], P[9], m;
-        if (!(J > 0.0)) {
-            sums[18] += 1.0;
+        if (a.law == kLawLinear) {
+            lin_stress(F, mu, lam, Finv, P, m);
+        } else {
+            const double J = det3(F);
+            if (!(J > 0.0)) {
+                sums[18] += 1.0;
 #pragma unroll
-            for (int c = 0; c < 9; ++c) a.P[c * a.n + vox] = 0.0;
-            continue;
+                for (int c = 0; c < 9; ++c) a.P[c * a.n + vox] = 0.0;
+                continue;
+            }
+            nh_stress(F, J, mu, lam, Finv, P, m);
         }
-        nh_stress(F, J, mu, lam, Finv, P, m);
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
             a.P[c * a.n + vox] = P[c];
@@ -182,7 +207,41 @@ __device__ __forceinline__ void k_material_laminate_body(const MatArgs<T>& a, in
         double Pp[9], Pm[9], Fip[9], Fim[9], mp = 0.0, mm = 0.0;
         const double Jb = det3(Fb);
         double v[3] = {0, 0, 0}, mb[3] = {0, 0, 0}, bp = 0.0, bm = 0.0;
-        if (!(Jb > 0.0)) {
+        if (a.law == kLawLinear) {
+            // closed form: one exact Newton step from a = 0 (the traction jump is linear in a)
+            lin_stress(Fb, mup, lamp, Fip, Pp, mp);
+            lin_stress(Fb, mum, lamm, Fim, Pm, mm);
+            double f[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                f[i] = (Pp[3 * i] - Pm[3 * i]) * N[0] + (Pp[3 * i + 1] - Pm[3 * i + 1]) * N[1] +
+                       (Pp[3 * i + 2] - Pm[3 * i + 2]) * N[2];
+            const double kp = (lamp + mup) / cp, km = (lamm + mum) / cm, d0 = mup / cp + mum / cm;
+            double D[6];
+            D[0] = d0 + (kp + km) * N[0] * N[0];
+            D[1] = (kp + km) * N[0] * N[1];
+            D[2] = (kp + km) * N[0] * N[2];
+            D[3] = d0 + (kp + km) * N[1] * N[1];
+            D[4] = (kp + km) * N[1] * N[2];
+            D[5] = d0 + (kp + km) * N[2] * N[2];
+            double Di[6], da[3];
+            sym3_inv(D, Di);
+            sym3_mul(Di, f, da);
+            double Fp[9], Fm[9];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                a3[i] = -da[i];
+#pragma unroll
+                for (int J = 0; J < 3; ++J) {
+                    const double aN = -da[i] * N[J];
+                    Fp[3 * i + J] = Fb[3 * i + J] + aN / cp;
+                    Fm[3 * i + J] = Fb[3 * i + J] - aN / cm;
+                }
+            }
+            lin_stress(Fp, mup, lamp, Fip, Pp, mp);
+            lin_stress(Fm, mum, lamm, Fim, Pm, mm);
+            status = 0;
+        } else if (!(Jb > 0.0)) {
             status = 2;
         } else {
             double adjb[9];

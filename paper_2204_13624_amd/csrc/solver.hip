@@ -380,6 +380,7 @@ int material(combo_ctx* ctx, const double* F_old, const double* dF, double s, co
     m.a_out = ctx->a_trial.as<double>();
     m.warm = (!cold && ctx->opt.warm_start_laminate) ? 1 : 0;
     m.maxit = ctx->opt.max_laminate;
+    m.law = ctx->opt.law;
     m.Sinv = ctx->Sinv.as<T>();
     m.sm = ctx->sm.as<T>();
     m.n1 = ctx->g.n1;
@@ -1261,6 +1262,7 @@ MatArgs<T> member_matargs(const Member& m) {
     a.a_out = ctx->a_trial.as<double>();
     a.warm = ctx->opt.warm_start_laminate ? 1 : 0;
     a.maxit = ctx->opt.max_laminate;
+    a.law = ctx->opt.law;
     a.Sinv = ctx->Sinv.as<T>();
     a.sm = ctx->sm.as<T>();
     a.n1 = ctx->g.n1;
@@ -1566,7 +1568,7 @@ const char* options_error(const combo_options* o) {
     if (!(o->tol_newton > 0) || !(o->tol_cg > 0) || o->max_newton < 0 || o->max_cg < 1 || o->max_laminate < 0 ||
         o->max_laminate > 64 || o->n_increments < 1 || o->max_step_halvings < 0 || o->max_cutbacks < 0 ||
         o->graph_chunk < 0 || o->graph_chunk > 256 || o->autotune < 0 || o->autotune > 1 ||
-        o->line_search < 0 || o->line_search > 1)
+        o->line_search < 0 || o->line_search > 1 || (o->law != COMBO_LAW_NEO_HOOKE && o->law != COMBO_LAW_LINEAR))
         return "option out of range";
     return nullptr;
 }
@@ -1646,6 +1648,7 @@ void combo_default_options(combo_options* o) {
     o->graph_chunk = 0;
     o->autotune = 0;
     o->line_search = 1;
+    o->law = COMBO_LAW_NEO_HOOKE;
 }
 
 int combo_check_size(int n) { return size_ok(n) ? COMBO_OK : COMBO_E_SIZE; }
@@ -1887,7 +1890,7 @@ int combo_solve(combo_ctx* ctx, const double Fbar[9], const double* F_init, doub
         if (stats) stats->status = COMBO_E_NUMERIC;
         return set_err(ctx, COMBO_E_NUMERIC, "Fbar is not finite");
     }
-    if (!(det9(Fbar) > 0.0)) {
+    if (ctx->opt.law != COMBO_LAW_LINEAR && !(det9(Fbar) > 0.0)) {
         if (stats) stats->status = COMBO_E_INADMISSIBLE;
         return set_err(ctx, COMBO_E_INADMISSIBLE, "det Fbar <= 0");
     }
@@ -2245,7 +2248,7 @@ int combo_batch_solve(combo_batch* B, const double* Fbar, const int* n_increment
     for (size_t i = 0; i < nm; ++i) {
         const std::string who = "member " + std::to_string(i) + ": ";
         if (!finite9(Fbar + 9 * i)) return bset_err(B, COMBO_E_NUMERIC, who + "Fbar is not finite");
-        if (!(det9(Fbar + 9 * i) > 0.0)) return bset_err(B, COMBO_E_INADMISSIBLE, who + "det Fbar <= 0");
+        if (B->opt.law != COMBO_LAW_LINEAR && !(det9(Fbar + 9 * i) > 0.0)) return bset_err(B, COMBO_E_INADMISSIBLE, who + "det Fbar <= 0");
         if (n_increments && n_increments[i] < 1) return bset_err(B, COMBO_E_INVAL, who + "n_increments < 1");
     }
     BHIP_OR_FAIL(hipSetDevice(B->device));
