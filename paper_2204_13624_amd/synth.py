@@ -250,11 +250,13 @@ def single_sphere(n=(16, 16, 16), l=(1.0, 1.0, 1.0), radius=0.3, center=(0.0, 0.
     return coarsen(chi, n, l, S, info=dict(kind="sphere", radius=radius))
 
 
-def random_spheres(n, n_spheres, c_target, seed, l=(1.0, 1.0, 1.0), radius_range=None, S=4):
+def random_spheres(n, n_spheres, c_target, seed, l=(1.0, 1.0, 1.0), radius_range=None, S=4, return_image=False):
     """Non-overlapping random spheres (RSA with a gap of one voxel).
 
     Equal radii when radius_range is None, else radii ~ U[radius_range]*L rescaled
     by one common factor so that the analytic sphere volume fraction is c_target.
+    With return_image, the fine indicator image [n3 S, n2 S, n1 S] (bool) is
+    returned instead of the coarsened microstructure.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     L = float(min(l))
@@ -272,6 +274,8 @@ def random_spheres(n, n_spheres, c_target, seed, l=(1.0, 1.0, 1.0), radius_range
     centers, rs = rsa_spheres(rng, radii, l, gap)
     chi = np.zeros((n[2] * S, n[1] * S, n[0] * S), dtype=bool)
     paint_spheres(chi, n, l, S, centers, rs)
+    if return_image:
+        return chi
     return coarsen(chi, n, l, S, info=dict(kind="spheres", n_spheres=n_spheres, radius_scale=scale,
                                            c_analytic=float((4.0 / 3.0) * math.pi * np.sum(rs ** 3) / vol),
                                            seed=seed))
@@ -406,6 +410,26 @@ def workload_spheres_256(n=256):
     """256^3, 200 spheres r ~ U[0.03, 0.06] L rescaled to c = 0.30, contrast 100, 20 % stretch / 10 incr."""
     ms = random_spheres((n, n, n), 200, 0.30, seed=3, radius_range=(0.03, 0.06))
     return ms, LoadCase(mats=contrast_mats(100.0), Fbar=stretch(0.2), n_increments=10)
+
+
+def workload_spheres_256_image(n=256, S=4):
+    """The fine (S n)^3 indicator image the 256^3 sphere workload is coarsened from."""
+    return random_spheres((n, n, n), 200, 0.30, seed=3, radius_range=(0.03, 0.06), S=S, return_image=True)
+
+
+def sphere_image(N, radius, center=(0.0, 0.0, 0.0), l=(1.0, 1.0, 1.0)):
+    """Fine image [N3, N2, N1] (uint8) of one periodic sphere, voxel centres strictly inside."""
+    chi = np.zeros((N[2], N[1], N[0]), dtype=bool)
+    paint_spheres(chi, N, l, 1, [np.asarray(center, float)], [radius])
+    return chi.astype(np.uint8)
+
+
+def plane_image(N, l, normal, offset, point=(0.0, 0.0, 0.0)):
+    """Fine image [N3, N2, N1] (uint8): 1 where (x - point).normal < offset, x the voxel
+    centres of the box [-l/2, l/2)^3 (not periodic: a half space cut to the box)."""
+    xs = [(np.arange(N[d]) + 0.5) * l[d] / N[d] - 0.5 * l[d] - point[d] for d in range(3)]
+    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    return ((X * normal[0] + Y * normal[1] + Z * normal[2]) < offset).astype(np.uint8)
 
 
 def workload_fibres_256(n=256, S=4):
