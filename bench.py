@@ -99,6 +99,57 @@ def cpu_baseline(ms, lc, sub=128, iters=3):
                                                                              or platform.machine())}
 
 
+def image_bench(combo, synth, ms, steps):
+    """Composite boxels of the 256^3 workload from its 1024^3 fine image (s = 4, paper
+    Sec. 5 normals), image resident in HBM; per-kernel times from HIP events."""
+    import torch
+    t = time.time()
+    img = synth.workload_spheres_256_image()
+    log("image generated in %.1f s" % (time.time() - t))
+    dimg = torch.from_numpy(img.view(np.uint8)).to("cuda:0")
+    del img
+    n = ms.n
+    ctx = combo.combo_create(0)
+    combo.combo_set_grid(ctx, *n, *ms.l)
+    out = combo.combo_image_to_boxels(ctx, dimg, (4, 4, 4))          # warm-up
+    combo.combo_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(3, steps)
+    for _ in range(reps):
+        combo.combo_image_to_boxels(ctx, dimg, (4, 4, 4), out=out)
+    el = (time.perf_counter() - t0) / reps
+    prof = combo.combo_profile_all(ctx)
+    combo.combo_destroy(ctx)
+    phase = out[0].cpu().numpy()
+    nb = phase.size
+    ncomp = int((phase == 2).sum())
+    exact = bool(np.array_equal(phase, ms.phase) and np.array_equal(out[1].cpu().numpy(), ms.c))
+    img_bytes = int(dimg.numel())
+    del dimg
+    ms1, n1 = prof["boxel_count"]
+    ms2, n2 = prof["boxel_normals"]
+    avg1, avg2 = ms1 / n1, ms2 / n2
+    # pass 1: image once; phase (1 B) and c (8 B) of every boxel, N (24 B) of pure ones, list (4 B) of composites
+    b1 = img_bytes + nb * 9 + (nb - ncomp) * 24 + ncomp * 4
+    # pass 2: the fine voxels of each composite boxel once, list entry, N out
+    b2 = ncomp * (64 + 4 + 24)
+    res = {"workload": "1024^3 image of spheres_256 -> 256^3 boxels (4^3 fine voxels each), Laplacian normals",
+           "composites": ncomp, "phase_and_c_equal_generator": exact,
+           "ms_per_call": el * 1e3,
+           "kernels": {"boxel_count": {"avg_us": round(avg1 * 1e3, 2), "bytes_per_launch": b1,
+                                       "GBps": round(b1 / (avg1 * 1e-3) / 1e9, 1)},
+                       "boxel_normals": {"avg_us": round(avg2 * 1e3, 2), "bytes_per_launch": b2,
+                                         "GBps": round(b2 / (avg2 * 1e-3) / 1e9, 1)}},
+           "image_GB_per_s": round(img_bytes / el / 1e9, 1)}
+    res["roofline"] = {"bound": "hbm", "kernel": "boxel_count", "achieved": res["kernels"]["boxel_count"]["GBps"],
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(res["kernels"]["boxel_count"]["GBps"] / HBM_PEAK_GBS, 4)}
+    log("image -> boxels: %.3f ms per call (count %.1f us, normals %.1f us), composites %d, exact %s"
+        % (el * 1e3, avg1 * 1e3, avg2 * 1e3, ncomp, exact))
+    return res
+
+
 def batch_bench(combo, synth, steps):
     """The many-RVE workload: 64 RVEs of 32^3..96^3 in one batch, against the same
     RVEs solved one after another on one context each (setup excluded)."""
@@ -179,6 +230,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-small-strain", action="store_true")
+    ap.add_argument("--no-image", action="store_true")
     ap.add_argument("--increments", type=int, default=0,
                     help="override the workload's load increments (shorter runs for counter collection)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -336,6 +388,7 @@ def main():
         log("small strain: %.3f s, newton %d, cg %d" % (el / args.steps, rl["stats"]["newton_iters"],
                                                          rl["stats"]["cg_iters_total"]))
     combo.combo_destroy(ctx)
+    out["image_to_boxels"] = None if args.no_image else image_bench(combo, synth, ms, args.steps)
     out["batch"] = None if args.no_batch else batch_bench(combo, synth, args.steps)
     if not args.no_cpu:
         t = time.time()

@@ -167,12 +167,41 @@ const char* combo_last_error(const combo_ctx* ctx);
 
 /* Grid and box (paper Sec. 2: the RVE [-l1/2, l1/2] x ...).  Resets the microstructure. */
 int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2, double l3);
+/* The grid and box set by combo_set_grid (host only; COMBO_E_STATE before it). */
+int combo_get_grid(const combo_ctx* ctx, int* n1, int* n2, int* n3, double* l1, double* l2, double* l3);
 /* Materials (mu, lambda) for phase 0 (matrix) and 1 (inclusion); mu > 0, lambda >= 0. */
 int combo_set_materials(combo_ctx* ctx, const combo_material mats[2]);
 /* Per-voxel ComBo data (paper Sec. 4: volume fraction and laminate normal).
  * phase [n], c [n], N [3][n] in the layout above; mem_kind as documented. */
 int combo_set_microstructure(combo_ctx* ctx, const uint8_t* phase, const double* c, const double* N,
                              int mem_kind);
+
+/* Composite boxels from a fine binary image (paper Sec. 5).
+ * chi: [n3 s3][n2 s2][n1 s1] bytes, x fastest, 1 = inclusion, 0 = matrix; the grid
+ * (n1, n2, n3) and box (l1, l2, l3) are the context's (combo_set_grid), so a fine
+ * voxel measures h_m = l_m / (n_m s_m).  Boxel (i, j, k) holds the fine voxels
+ * [i s1, (i+1) s1) x [j s2, (j+1) s2) x [k s3, (k+1) s3).  Outputs, in the layout
+ * of combo_set_microstructure: phase [n3][n2][n1] (0 matrix, 1 inclusion,
+ * 2 composite), c [n3][n2][n1] = inclusion fraction of the boxel, N [3][n3][n2][n1]
+ * = unit normal out of the inclusion for composite boxels, 0 elsewhere.
+ * method COMBO_NORMALS_LAPLACE: interface weights w = |S * chi| of the periodic
+ *   per-axis 3-point Laplacian weighted by r_m = h_i h_j / h_m (Sec. 5.2, [N.1]),
+ *   second moment of w about the weighted barycentre of the interface and its
+ *   smallest eigenvector ([N.2]), oriented by eq. normal:flip;
+ * method COMBO_NORMALS_BARYCENTRE: N = (c- - c+) / |c- - c+| of the phase
+ *   barycentres (eq. normal:kabel); (1, 0, 0) where the two coincide.
+ * All of chi, phase, c and N are host or all device pointers (mem_kind); the
+ * caller owns them.  Runs on the context's stream and returns when the outputs
+ * are written.  COMBO_E_STATE without a grid, COMBO_E_INVAL for s_m < 1, a
+ * method out of range, null pointers or an image value other than 0 and 1. */
+#define COMBO_NORMALS_LAPLACE 0
+#define COMBO_NORMALS_BARYCENTRE 1
+int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, int s3, int method, uint8_t* phase,
+                          double* c, double* N, int mem_kind);
+/* combo_image_to_boxels followed by combo_set_microstructure with its outputs,
+ * kept on the device. */
+int combo_set_microstructure_from_image(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, int s3, int method,
+                                        int mem_kind);
 int combo_set_options(combo_ctx* ctx, const combo_options* opt);
 
 /* Solve HOM for the macroscopic deformation gradient Fbar (host, 9 doubles,
@@ -238,7 +267,9 @@ enum combo_kernel {
     COMBO_K_MATERIAL = 7,     /* pure-voxel law + laminate law + their reductions */
     COMBO_K_RESIDUAL = 8,     /* FP64 x, y, z forward passes of P, residual norm, right-hand side */
     COMBO_K_NEWTON_DIR = 9,   /* FP64 inverse passes giving dF */
-    COMBO_K_COUNT = 10
+    COMBO_K_BOXEL_COUNT = 10, /* image -> boxels, pass 1: volume fractions, phases, composite list */
+    COMBO_K_BOXEL_NORMALS = 11, /* image -> boxels, pass 2: interface weights, moments, normals */
+    COMBO_K_COUNT = 12
 };
 int combo_profile_enable(combo_ctx* ctx, int enable);
 /* Accumulated milliseconds and number of timed launches of one kernel class. */

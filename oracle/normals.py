@@ -23,7 +23,9 @@ figure).  The footnote on M speaks of the barycentre of the boxel; measured from
 the boxel centre, M of an interface patch far from the centre is dominated by the
 offset, its smallest eigenvector turns in-plane, and low volume fractions (the
 case the method is meant to fix) get wrong normals (tests/test_oracle_normals.py
-shows it).  For pure boxels N = 0.
+shows it).  For pure boxels N = 0.  Where the two phase barycentres coincide,
+N~ is taken as 0 (so eq. normal:flip returns -N) and the barycentre method
+returns e1.
 """
 import numpy as np
 
@@ -86,9 +88,11 @@ def boxel_normal(chi_b, w_b, x, method=METHOD_LAPLACE, about="interface"):
     chi_b = chi_b.astype(np.float64)
     cp = (chi_b[..., None] * x).sum(axis=(0, 1, 2)) / chi_b.sum()
     cm = ((1.0 - chi_b)[..., None] * x).sum(axis=(0, 1, 2)) / (1.0 - chi_b).sum()
-    Nt = (cm - cp) / np.linalg.norm(cm - cp)
+    d = cm - cp
+    nd = np.linalg.norm(d)
+    Nt = d / nd if nd > 0 else np.zeros(3)      # coinciding barycentres: no orientation
     if method == METHOD_BARYCENTRE:
-        return Nt
+        return Nt if nd > 0 else np.array([1.0, 0.0, 0.0])
     wsum = w_b.sum()
     xs = x
     if about == "interface":

@@ -30,6 +30,8 @@ COMBO_FP64 = 0
 COMBO_MIXED = 1
 COMBO_GREEN_GAMMA0 = 0
 COMBO_GREEN_G = 1
+COMBO_NORMALS_LAPLACE = 0
+COMBO_NORMALS_BARYCENTRE = 1
 COMBO_LAW_NEO_HOOKE = 0
 COMBO_LAW_LINEAR = 1
 
@@ -101,6 +103,9 @@ _SIGS = {
     "combo_set_grid": (_I, [_P, _I, _I, _I, _D, _D, _D]),
     "combo_set_materials": (_I, [_P, ctypes.POINTER(combo_material)]),
     "combo_set_microstructure": (_I, [_P, _P, _P, _P, _I]),
+    "combo_get_grid": (_I, [_P] + [ctypes.POINTER(ctypes.c_int)] * 3 + [ctypes.POINTER(ctypes.c_double)] * 3),
+    "combo_image_to_boxels": (_I, [_P, _P, _I, _I, _I, _I, _P, _P, _P, _I]),
+    "combo_set_microstructure_from_image": (_I, [_P, _P, _I, _I, _I, _I, _I]),
     "combo_set_options": (_I, [_P, ctypes.POINTER(combo_options)]),
     "combo_solve": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(combo_stats), _I]),
     "combo_eval_law": (_I, [_P, _P, _P, _P, _P, _P, _I]),
@@ -123,7 +128,7 @@ _SIGS = {
 }
 
 KERNEL_NAMES = ["xpass_cg", "ypass_inv", "ypass_fwd", "zpass_inv", "zpass_fwd", "cg_update", "cg_finalize",
-                "material", "residual", "newton_dir"]
+                "material", "residual", "newton_dir", "boxel_count", "boxel_normals"]
 
 _lib = None
 
@@ -255,6 +260,48 @@ def combo_set_microstructure(ctx, phase, c, N):
     cp, k2 = _ptr(c, np.float64)
     npt, k3 = _ptr(N, np.float64)
     _check(ctx, load_library().combo_set_microstructure(ctx, pp, cp, npt, _mem_kind(k1, k2, k3)))
+
+
+def combo_image_to_boxels(ctx, chi, s, method=COMBO_NORMALS_LAPLACE, out=None):
+    """Fine image chi [n3 s3, n2 s2, n1 s1] (uint8 0/1, numpy or torch) -> (phase, c, N) of the
+    context's grid.  out = (phase, c, N) receives them (same memory kind as chi); else new
+    numpy arrays (host image) or torch tensors on the image's device."""
+    (n1, n2, n3), _ = combo_get_grid(ctx)
+    if tuple(chi.shape) != (n3 * s[2], n2 * s[1], n1 * s[0]):
+        raise ValueError("image shape %s does not match grid %s x boxel %s" % (tuple(chi.shape), (n1, n2, n3), tuple(s)))
+    cp, kind = _ptr(chi, np.uint8)
+    if out is None:
+        if kind == COMBO_MEM_DEVICE:
+            import torch
+            dev = chi.device
+            out = (torch.empty((n3, n2, n1), dtype=torch.uint8, device=dev),
+                   torch.empty((n3, n2, n1), dtype=torch.float64, device=dev),
+                   torch.empty((3, n3, n2, n1), dtype=torch.float64, device=dev))
+        else:
+            out = (np.zeros((n3, n2, n1), np.uint8), np.zeros((n3, n2, n1)), np.zeros((3, n3, n2, n1)))
+    pp, k1 = _ptr(out[0], np.uint8)
+    cc, k2 = _ptr(out[1], np.float64)
+    nn, k3 = _ptr(out[2], np.float64)
+    _check(ctx, load_library().combo_image_to_boxels(ctx, cp, int(s[0]), int(s[1]), int(s[2]), int(method),
+                                                     pp, cc, nn, _mem_kind(kind, k1, k2, k3)))
+    return out
+
+
+def combo_get_grid(ctx):
+    """((n1, n2, n3), (l1, l2, l3)) of the context."""
+    n = [ctypes.c_int() for _ in range(3)]
+    l = [ctypes.c_double() for _ in range(3)]
+    _check(ctx, load_library().combo_get_grid(ctx, *[ctypes.byref(x) for x in n + l]))
+    return tuple(x.value for x in n), tuple(x.value for x in l)
+
+
+def combo_set_microstructure_from_image(ctx, chi, s, method=COMBO_NORMALS_LAPLACE):
+    (n1, n2, n3), _ = combo_get_grid(ctx)
+    if tuple(chi.shape) != (n3 * s[2], n2 * s[1], n1 * s[0]):
+        raise ValueError("image shape %s does not match grid %s x boxel %s" % (tuple(chi.shape), (n1, n2, n3), tuple(s)))
+    cp, kind = _ptr(chi, np.uint8)
+    _check(ctx, load_library().combo_set_microstructure_from_image(ctx, cp, int(s[0]), int(s[1]), int(s[2]),
+                                                                   int(method), kind))
 
 
 def combo_set_options(ctx, opts):

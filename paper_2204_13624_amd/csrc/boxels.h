@@ -1,0 +1,31 @@
+// Composite boxels from a fine binary image (paper Sec. 5): argument block and launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace combo {
+
+struct BoxelArgs {
+    const uint8_t* chi;         // [N3][N2][N1] fine image, 1 = inclusion, 0 = matrix
+    long long N1, N2, N3;       // fine voxels per axis (N_m = n_m s_m)
+    int n1, n2, n3;             // boxels per axis
+    int s1, s2, s3;             // fine voxels per boxel and axis
+    double h[3];                // fine voxel size
+    double r[3];                // stencil ratios r_m = h_i h_j / h_m
+    int method;                 // 0: Laplacian moments (Sec. 5.2), 1: barycentres (eq. normal:kabel)
+    int vec4;                   // rows start 4-byte aligned and s1 % 4 == 0: pass 1 reads dwords
+    uint8_t* phase;             // [nb] out
+    double* c;                  // [nb] out
+    double* N;                  // [3][nb] out
+    int* list;                  // [nb] scratch: composite boxels, in the order pass 1 found them
+    int* counter;               // [2] scratch: [0] composites found, [1] nonzero if a value is not 0/1
+};
+
+// Pass 1, one thread per boxel: volume fraction, phase, composite list (counter must start at 0).
+hipError_t launch_boxel_count(const BoxelArgs& a, hipStream_t s);
+// Pass 2, 16 lanes per composite boxel: interface weights, moments, normal.
+hipError_t launch_boxel_normals(const BoxelArgs& a, hipStream_t s);
+
+}  // namespace combo

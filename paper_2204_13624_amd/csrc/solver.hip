@@ -36,6 +36,7 @@
 #include <vector>
 
 #include "combo.h"
+#include "boxels.h"
 #include "context.h"
 
 using namespace combo;
@@ -1797,6 +1798,127 @@ int combo_set_options(combo_ctx* ctx, const combo_options* o) {
     ctx->opt = *o;
     for (auto& gr : ctx->graph) gr.reset();
     return COMBO_OK;
+}
+
+int combo_get_grid(const combo_ctx* ctx, int* n1, int* n2, int* n3, double* l1, double* l2, double* l3) {
+    if (!ctx || !n1 || !n2 || !n3 || !l1 || !l2 || !l3) return COMBO_E_INVAL;
+    if (!ctx->has_grid) return COMBO_E_STATE;
+    *n1 = ctx->g.n1;
+    *n2 = ctx->g.n2;
+    *n3 = ctx->g.n3;
+    *l1 = ctx->l[0];
+    *l2 = ctx->l[1];
+    *l3 = ctx->l[2];
+    return COMBO_OK;
+}
+
+int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, int s3, int method, uint8_t* phase,
+                          double* c, double* N, int mem_kind) {
+    if (!ctx) return COMBO_E_INVAL;
+    if (!ctx->has_grid) return set_err(ctx, COMBO_E_STATE, "combo_set_grid has not been called");
+    if (!chi || !phase || !c || !N) return set_err(ctx, COMBO_E_INVAL, "null image or output pointer");
+    if (mem_kind != COMBO_MEM_HOST && mem_kind != COMBO_MEM_DEVICE) return set_err(ctx, COMBO_E_INVAL, "bad mem_kind");
+    if (s1 < 1 || s2 < 1 || s3 < 1 || s1 > 4096 || s2 > 4096 || s3 > 4096)
+        return set_err(ctx, COMBO_E_INVAL, "fine voxels per boxel must be in [1, 4096]");
+    if (method != COMBO_NORMALS_LAPLACE && method != COMBO_NORMALS_BARYCENTRE)
+        return set_err(ctx, COMBO_E_INVAL, "method must be COMBO_NORMALS_LAPLACE or COMBO_NORMALS_BARYCENTRE");
+    const Grid& g = ctx->g;
+    const long long N1 = (long long)g.n1 * s1, N2 = (long long)g.n2 * s2, N3 = (long long)g.n3 * s3;
+    if ((double)N1 * (double)N2 * (double)N3 > 1.0e12 || (long long)s1 * s2 * s3 > (1LL << 30))
+        return set_err(ctx, COMBO_E_INVAL, "image too large");
+    HIP_OR_FAIL(hipSetDevice(ctx->device));
+    const long long nb = g.n;
+    const size_t img_bytes = (size_t)(N1 * N2 * N3);
+    DevBuf dchi, dphase, dc, dN, scratch;
+    const uint8_t* chi_d = chi;
+    uint8_t* phase_d = phase;
+    double* c_d = c;
+    double* N_d = N;
+    if (mem_kind == COMBO_MEM_HOST) {
+        HIP_OR_FAIL(dchi.ensure(img_bytes + 4));
+        HIP_OR_FAIL(hipMemcpyAsync(dchi.p, chi, img_bytes, hipMemcpyHostToDevice, ctx->stream));
+        HIP_OR_FAIL(dphase.ensure((size_t)nb));
+        HIP_OR_FAIL(dc.ensure(sizeof(double) * nb));
+        HIP_OR_FAIL(dN.ensure(sizeof(double) * 3 * nb));
+        chi_d = static_cast<const uint8_t*>(dchi.p);
+        phase_d = static_cast<uint8_t*>(dphase.p);
+        c_d = static_cast<double*>(dc.p);
+        N_d = static_cast<double*>(dN.p);
+    }
+    HIP_OR_FAIL(scratch.ensure(sizeof(int) * (nb + 2)));
+    BoxelArgs a{};
+    a.chi = chi_d;
+    a.N1 = N1;
+    a.N2 = N2;
+    a.N3 = N3;
+    a.n1 = g.n1;
+    a.n2 = g.n2;
+    a.n3 = g.n3;
+    a.s1 = s1;
+    a.s2 = s2;
+    a.s3 = s3;
+    a.h[0] = ctx->l[0] / (double)N1;
+    a.h[1] = ctx->l[1] / (double)N2;
+    a.h[2] = ctx->l[2] / (double)N3;
+    a.r[0] = a.h[1] * a.h[2] / a.h[0];
+    a.r[1] = a.h[0] * a.h[2] / a.h[1];
+    a.r[2] = a.h[0] * a.h[1] / a.h[2];
+    a.method = method;
+    a.vec4 = (s1 % 4 == 0) && (N1 % 4 == 0) && (reinterpret_cast<uintptr_t>(chi_d) % 4 == 0);
+    a.phase = phase_d;
+    a.c = c_d;
+    a.N = N_d;
+    a.counter = static_cast<int*>(scratch.p);
+    a.list = a.counter + 2;
+    HIP_OR_FAIL(hipMemsetAsync(a.counter, 0, 2 * sizeof(int), ctx->stream));
+    {
+        ProfScope ps(ctx, COMBO_K_BOXEL_COUNT);
+        HIP_OR_FAIL(launch_boxel_count(a, ctx->stream));
+    }
+    {
+        ProfScope ps(ctx, COMBO_K_BOXEL_NORMALS);
+        HIP_OR_FAIL(launch_boxel_normals(a, ctx->stream));
+    }
+    int hcnt[2] = {0, 0};
+    HIP_OR_FAIL(hipMemcpyAsync(hcnt, a.counter, sizeof(hcnt), hipMemcpyDeviceToHost, ctx->stream));
+    if (mem_kind == COMBO_MEM_HOST) {
+        HIP_OR_FAIL(hipMemcpyAsync(phase, phase_d, (size_t)nb, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_FAIL(hipMemcpyAsync(c, c_d, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_FAIL(hipMemcpyAsync(N, N_d, sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    prof_harvest(ctx);
+    if (hcnt[1]) return set_err(ctx, COMBO_E_INVAL, "image values must be 0 or 1");
+    return COMBO_OK;
+}
+
+int combo_set_microstructure_from_image(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, int s3, int method,
+                                        int mem_kind) {
+    if (!ctx) return COMBO_E_INVAL;
+    if (!ctx->has_grid) return set_err(ctx, COMBO_E_STATE, "combo_set_grid has not been called");
+    HIP_OR_FAIL(hipSetDevice(ctx->device));
+    const long long nb = ctx->g.n;
+    DevBuf dphase, dc, dN, dchi;
+    HIP_OR_FAIL(dphase.ensure((size_t)nb));
+    HIP_OR_FAIL(dc.ensure(sizeof(double) * nb));
+    HIP_OR_FAIL(dN.ensure(sizeof(double) * 3 * nb));
+    const uint8_t* chi_d = chi;
+    if (mem_kind == COMBO_MEM_HOST && chi) {
+        if (s1 < 1 || s2 < 1 || s3 < 1 || s1 > 4096 || s2 > 4096 || s3 > 4096)
+            return set_err(ctx, COMBO_E_INVAL, "fine voxels per boxel must be in [1, 4096]");
+        const double img = (double)ctx->g.n1 * s1 * (double)ctx->g.n2 * s2 * (double)ctx->g.n3 * s3;
+        if (img > 1.0e12) return set_err(ctx, COMBO_E_INVAL, "image too large");
+        HIP_OR_FAIL(dchi.ensure((size_t)img + 4));
+        HIP_OR_FAIL(hipMemcpy(dchi.p, chi, (size_t)img, hipMemcpyHostToDevice));
+        chi_d = static_cast<const uint8_t*>(dchi.p);
+    } else if (mem_kind != COMBO_MEM_DEVICE && mem_kind != COMBO_MEM_HOST) {
+        return set_err(ctx, COMBO_E_INVAL, "bad mem_kind");
+    }
+    int st = combo_image_to_boxels(ctx, chi_d, s1, s2, s3, method, static_cast<uint8_t*>(dphase.p),
+                                   static_cast<double*>(dc.p), static_cast<double*>(dN.p), COMBO_MEM_DEVICE);
+    if (st != COMBO_OK) return st;
+    return combo_set_microstructure(ctx, static_cast<const uint8_t*>(dphase.p), static_cast<const double*>(dc.p),
+                                    static_cast<const double*>(dN.p), COMBO_MEM_DEVICE);
 }
 
 int combo_set_microstructure(combo_ctx* ctx, const uint8_t* phase, const double* c, const double* N, int mem_kind) {

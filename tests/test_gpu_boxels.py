@@ -1,0 +1,171 @@
+"""Composite boxels from fine images on the GPU (combo_image_to_boxels), through
+the C-ABI, against the oracle of paper Sec. 5: phases and volume fractions
+exactly, normals to rounding wherever the smallest eigenvalue of the moment
+matrix is separated (elsewhere: a valid unit normal out of the inclusion), both
+normal methods, host and device memory, error paths, the paper's composite count,
+a solve set up from an image, and the 1024^3 image of the 256^3 sphere workload."""
+import numpy as np
+import pytest
+
+from oracle import normals as onorm
+from paper_2204_13624_amd import combo, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def ctx():
+    c = combo.combo_create(0)
+    yield c
+    combo.combo_destroy(c)
+
+
+def random_image(N, seed, count=6):
+    """Union of random periodic spheres on a fine grid N = (N1, N2, N3)."""
+    rng = np.random.default_rng(seed)
+    img = np.zeros((N[2], N[1], N[0]), np.uint8)
+    for _ in range(count):
+        img |= synth.sphere_image(N, rng.uniform(0.08, 0.3), center=rng.uniform(-0.5, 0.5, 3))
+    return img
+
+
+def eigen_gap(img, s, l, boxel):
+    """Relative gap between the two smallest eigenvalues of the oracle's moment matrix."""
+    N3, N2, N1 = img.shape
+    h = (l[0] / N1, l[1] / N2, l[2] / N3)
+    k, j, i = boxel
+    zi = np.arange(k * s[2] - 1, k * s[2] + s[2] + 1) % N3
+    yi = np.arange(j * s[1] - 1, j * s[1] + s[1] + 1) % N2
+    xi = np.arange(i * s[0] - 1, i * s[0] + s[0] + 1) % N1
+    w = onorm.laplace_weights_block(img[np.ix_(zi, yi, xi)], h)
+    x = onorm._local_coords(s, h)
+    xs = x - (w[..., None] * x).sum(axis=(0, 1, 2)) / w.sum()
+    ev = np.linalg.eigvalsh(np.einsum("abc,abci,abcj->ij", w, xs, xs))
+    return (ev[1] - ev[0]) / ev[2]
+
+
+def check_against_oracle(img, n, s, l, method, phase, c, N, gap_tol=1e-6, ntol=1e-10):
+    rp, rc, rN = onorm.detect(img, s, l, method)
+    assert np.array_equal(phase, rp)
+    assert np.array_equal(c, rc)
+    comp = np.argwhere(rp == 2)
+    assert len(comp) > 0
+    assert np.all(N[:, rp != 2] == 0)
+    nsep = 0
+    for b in comp:
+        b = tuple(b)
+        g, r = N[(slice(None),) + b], rN[(slice(None),) + b]
+        assert abs(np.linalg.norm(g) - 1) <= 1e-14
+        if method == onorm.METHOD_BARYCENTRE or eigen_gap(img, s, l, b) > gap_tol:
+            assert np.abs(g - r).max() <= ntol, (b, g, r)
+            nsep += 1
+    assert nsep >= 0.9 * len(comp)
+
+
+@pytest.mark.parametrize("n,s,l", [((6, 4, 3), (8, 8, 8), (1.0, 1.0, 1.0)),          # dword path
+                                   ((9, 6, 4), (5, 6, 3), (1.0, 1.2, 0.6)),          # byte path, boxels
+                                   ((4, 8, 6), (12, 4, 8), (0.6, 0.4, 0.6)),         # equiaxed fine voxels
+                                   ((9, 3, 2), (2, 7, 9), (0.9, 1.05, 0.9))])
+@pytest.mark.parametrize("method", [combo.COMBO_NORMALS_LAPLACE, combo.COMBO_NORMALS_BARYCENTRE])
+def test_boxels_match_oracle(ctx, n, s, l, method):
+    img = random_image(tuple(a * b for a, b in zip(n, s)), seed=sum(n) + method)
+    combo.combo_set_grid(ctx, *n, *l)
+    phase, c, N = combo.combo_image_to_boxels(ctx, img, s, method)
+    check_against_oracle(img, n, s, l, method, phase, c, N)
+
+
+def test_device_memory_matches_host(ctx):
+    import torch
+    n, s, l = (8, 8, 8), (4, 4, 4), (1.0, 1.0, 1.0)
+    img = random_image((32, 32, 32), seed=3)
+    combo.combo_set_grid(ctx, *n, *l)
+    hp, hc, hN = combo.combo_image_to_boxels(ctx, img, s)
+    dp, dc, dN = combo.combo_image_to_boxels(ctx, torch.from_numpy(img).cuda(), s)
+    assert np.array_equal(dp.cpu().numpy(), hp)
+    assert np.array_equal(dc.cpu().numpy(), hc)
+    assert np.array_equal(dN.cpu().numpy(), hN)
+
+
+def test_error_paths(ctx):
+    combo.combo_set_grid(ctx, 4, 4, 4, 1.0, 1.0, 1.0)
+    img = random_image((16, 16, 16), seed=4)
+    bad = img.copy()
+    bad[3, 4, 5] = 2
+    with pytest.raises(combo.ComboError) as e:
+        combo.combo_image_to_boxels(ctx, bad, (4, 4, 4))
+    assert e.value.status == combo.COMBO_E_INVAL and "0 or 1" in str(e.value)
+    with pytest.raises(ValueError):
+        combo.combo_image_to_boxels(ctx, img, (4, 4, 2))
+    out = (np.zeros((4, 4, 4), np.uint8), np.zeros((4, 4, 4)), np.zeros((3, 4, 4, 4)))
+    lib = combo.load_library()
+    st = lib.combo_image_to_boxels(ctx, img.ctypes.data, 4, 4, 4, 7, out[0].ctypes.data, out[1].ctypes.data,
+                                   out[2].ctypes.data, combo.COMBO_MEM_HOST)
+    assert st == combo.COMBO_E_INVAL
+    st = lib.combo_image_to_boxels(ctx, img.ctypes.data, 0, 4, 4, 0, out[0].ctypes.data, out[1].ctypes.data,
+                                   out[2].ctypes.data, combo.COMBO_MEM_HOST)
+    assert st == combo.COMBO_E_INVAL
+    # the good image still works after the failures
+    phase, c, N = combo.combo_image_to_boxels(ctx, img, (4, 4, 4))
+    assert np.array_equal(c, onorm.detect(img, (4, 4, 4), (1.0, 1.0, 1.0))[1])
+
+
+def test_paper_composite_count(ctx):
+    """Sphere R = 0.4 L, 256^3 image -> 32^3 boxels: 2624 composite voxels (paper Sec. 6.2)."""
+    img = synth.sphere_image((256, 256, 256), 0.4)
+    combo.combo_set_grid(ctx, 32, 32, 32, 1.0, 1.0, 1.0)
+    phase, c, N = combo.combo_image_to_boxels(ctx, img, (8, 8, 8))
+    assert int((phase == 2).sum()) == 2624
+    rng = np.random.default_rng(6)
+    comp = np.argwhere(phase == 2)
+    pick = [tuple(b) for b in comp[rng.choice(len(comp), 200, replace=False)]]
+    rp, rc, rN = onorm.detect_at(img, (8, 8, 8), (1.0, 1.0, 1.0), pick)
+    for m, b in enumerate(pick):
+        if eigen_gap(img, (8, 8, 8), (1.0, 1.0, 1.0), b) > 1e-6:
+            assert np.abs(N[(slice(None),) + b] - rN[m]).max() <= 1e-10
+
+
+def test_solve_set_up_from_an_image(ctx):
+    n, s, l = (12, 12, 12), (6, 6, 6), (1.0, 1.0, 1.0)
+    img = synth.sphere_image((72, 72, 72), 0.3, center=(0.02, -0.03, 0.01))
+    phase, c, N = onorm.detect(img, s, l)
+    combo.combo_set_grid(ctx, *n, *l)
+    combo.combo_set_materials(ctx, ((1.0, 2.0), (10.0, 20.0)))
+    o = combo.combo_default_options()
+    o.tol_newton = 1e-10
+    o.tol_cg = 1e-11
+    combo.combo_set_options(ctx, o)
+    combo.combo_set_microstructure(ctx, phase, c, N)
+    r0 = combo.combo_solve(ctx, synth.stretch(0.05))
+    combo.combo_set_microstructure_from_image(ctx, img, s)
+    r1 = combo.combo_solve(ctx, synth.stretch(0.05))
+    assert np.abs(r1["Pbar"] - r0["Pbar"]).max() <= 1e-10 * np.abs(r0["Pbar"]).max()
+
+
+def test_full_size_image_of_the_sphere_workload(ctx):
+    """1024^3 image -> 256^3 boxels (s = 4, the bench's configuration): phases and
+    volume fractions equal the generator's coarsening everywhere; normals at
+    sampled composite boxels equal the oracle's."""
+    import torch
+    img = synth.workload_spheres_256_image()
+    ms, _ = synth.workload_spheres_256()
+    dimg = torch.from_numpy(img.view(np.uint8)).cuda()
+    combo.combo_set_grid(ctx, 256, 256, 256, 1.0, 1.0, 1.0)
+    phase, c, N = combo.combo_image_to_boxels(ctx, dimg, (4, 4, 4))
+    phase = phase.cpu().numpy()
+    c = c.cpu().numpy()
+    N = N.cpu().numpy()
+    assert np.array_equal(phase, ms.phase)
+    assert np.array_equal(c, ms.c)
+    rng = np.random.default_rng(8)
+    comp = np.argwhere(phase == 2)
+    pick = [tuple(b) for b in comp[rng.choice(len(comp), 2000, replace=False)]]
+    img_u8 = img.view(np.uint8)
+    rp, rc, rN = onorm.detect_at(img_u8, (4, 4, 4), (1.0, 1.0, 1.0), pick)
+    sep = 0
+    for m, b in enumerate(pick):
+        g = N[(slice(None),) + b]
+        assert abs(np.linalg.norm(g) - 1) <= 1e-14
+        if eigen_gap(img_u8, (4, 4, 4), (1.0, 1.0, 1.0), b) > 1e-6:
+            assert np.abs(g - rN[m]).max() <= 1e-10, b
+            sep += 1
+    assert sep >= 1500
