@@ -130,10 +130,10 @@ def image_bench(combo, synth, ms, steps):
     ms1, n1 = prof["boxel_count"]
     ms2, n2 = prof["boxel_normals"]
     avg1, avg2 = ms1 / n1, ms2 / n2
-    # pass 1: image once; phase (1 B) and c (8 B) of every boxel, N (24 B) of pure ones, list (4 B) of composites
-    b1 = img_bytes + nb * 9 + (nb - ncomp) * 24 + ncomp * 4
-    # pass 2: the fine voxels of each composite boxel once, list entry, N out
-    b2 = ncomp * (64 + 4 + 24)
+    # pass 1: the image once, phase (1 B) and c (8 B) of every boxel
+    b1 = img_bytes + nb * 9
+    # pass 2: phase (1 B) in and N (24 B) out for every boxel, the 4^3 fine voxels of each composite once
+    b2 = nb * 25 + ncomp * 64
     res = {"workload": "1024^3 image of spheres_256 -> 256^3 boxels (4^3 fine voxels each), Laplacian normals",
            "composites": ncomp, "phase_and_c_equal_generator": exact,
            "ms_per_call": el * 1e3,

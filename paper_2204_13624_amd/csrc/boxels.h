@@ -16,16 +16,17 @@ struct BoxelArgs {
     double r[3];                // stencil ratios r_m = h_i h_j / h_m
     int method;                 // 0: Laplacian moments (Sec. 5.2), 1: barycentres (eq. normal:kabel)
     int vec4;                   // rows start 4-byte aligned and s1 % 4 == 0: pass 1 reads dwords
+    int vec16;                  // s1 == 4, n1 % 4 == 0, rows 16-byte aligned, phase and c 16-byte
+                                // aligned: pass 1 takes four boxels per thread with 16-byte loads
     uint8_t* phase;             // [nb] out
     double* c;                  // [nb] out
     double* N;                  // [3][nb] out
-    int* list;                  // [nb] scratch: composite boxels, in the order pass 1 found them
-    int* counter;               // [2] scratch: [0] composites found, [1] nonzero if a value is not 0/1
+    int* counter;               // [2] scratch, zero before pass 1: [1] becomes nonzero if a value is not 0/1
 };
 
-// Pass 1, one thread per boxel: volume fraction, phase, composite list (counter must start at 0).
+// Pass 1, one thread per boxel: volume fraction and phase.
 hipError_t launch_boxel_count(const BoxelArgs& a, hipStream_t s);
-// Pass 2, 16 lanes per composite boxel: interface weights, moments, normal.
+// Pass 2, one wave per 64 boxels, 16 lanes per composite boxel: interface weights, moments, normal.
 hipError_t launch_boxel_normals(const BoxelArgs& a, hipStream_t s);
 
 }  // namespace combo

@@ -1845,7 +1845,7 @@ int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, in
         c_d = static_cast<double*>(dc.p);
         N_d = static_cast<double*>(dN.p);
     }
-    HIP_OR_FAIL(scratch.ensure(sizeof(int) * (nb + 2)));
+    HIP_OR_FAIL(scratch.ensure(sizeof(int) * 2));
     BoxelArgs a{};
     a.chi = chi_d;
     a.N1 = N1;
@@ -1865,11 +1865,12 @@ int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, in
     a.r[2] = a.h[0] * a.h[1] / a.h[2];
     a.method = method;
     a.vec4 = (s1 % 4 == 0) && (N1 % 4 == 0) && (reinterpret_cast<uintptr_t>(chi_d) % 4 == 0);
+    a.vec16 = (s1 == 4) && (g.n1 % 4 == 0) && (N1 % 16 == 0) && (reinterpret_cast<uintptr_t>(chi_d) % 16 == 0) &&
+              (reinterpret_cast<uintptr_t>(phase_d) % 4 == 0) && (reinterpret_cast<uintptr_t>(c_d) % 16 == 0);
     a.phase = phase_d;
     a.c = c_d;
     a.N = N_d;
     a.counter = static_cast<int*>(scratch.p);
-    a.list = a.counter + 2;
     HIP_OR_FAIL(hipMemsetAsync(a.counter, 0, 2 * sizeof(int), ctx->stream));
     {
         ProfScope ps(ctx, COMBO_K_BOXEL_COUNT);
