@@ -80,6 +80,7 @@ class Problem:
     N: np.ndarray       # [3, n3, n2, n1]
     mats: tuple         # ((mu-, lam-), (mu+, lam+))
     law: str = "neo_hooke"   # or "linear": small strain, P = sigma(sym(F - I))
+    disc: str = "ms"         # or "willot": rotated-scheme gradient (spectral.willot_frequencies)
 
     @property
     def shape(self):
@@ -198,7 +199,7 @@ def inner_c0(x, y, mu0, kappa0):
 
 def residual(P, prob):
     """eta = |G[P]|_2 / (sqrt(n) |Pbar|_F)."""
-    R = spectral.apply_g(P, prob.n, prob.l)
+    R = spectral.apply_g(P, prob.n, prob.l, prob.disc)
     Pbar = P.mean(axis=(2, 3, 4))
     den = np.sqrt(prob.nvox) * max(np.linalg.norm(Pbar), 1e-300)
     return float(np.linalg.norm(R) / den)
@@ -218,7 +219,7 @@ def cg(Av, b, prob, mu0, kappa0, tol, maxit):
     while True:
         if it >= maxit:
             raise SolveError(E_NOCONV, "CG did not converge in %d iterations" % maxit)
-        q = spectral.apply_gamma0(apply_tangent(Av, p, shape), prob.n, prob.l, mu0, kappa0)
+        q = spectral.apply_gamma0(apply_tangent(Av, p, shape), prob.n, prob.l, mu0, kappa0, prob.disc)
         gam = inner_c0(p, q, mu0, kappa0)
         if gam != gam:
             raise SolveError(E_NUMERIC, "CG breakdown: <p, q> = %r" % gam)
@@ -244,7 +245,7 @@ def effective_tangent(F, prob, opts, mu0, kappa0):
         E = np.zeros((3, 3) + tuple(shape))
         E[kL // 3, kL % 3] = 1.0
         tau = apply_tangent(Av, E, shape)
-        b = -spectral.apply_gamma0(tau, prob.n, prob.l, mu0, kappa0)
+        b = -spectral.apply_gamma0(tau, prob.n, prob.l, mu0, kappa0, prob.disc)
         try:
             dF, it = cg(Av, b, prob, mu0, kappa0, opts.tol_cg, opts.max_cg)
         except NegativeCurvature as e:
@@ -317,7 +318,7 @@ def solve(prob, Fbar, opts=None, F_init=None):
                         break
                     if _ == opts.max_newton:
                         break
-                    b = -spectral.apply_gamma0(P, prob.n, prob.l, mu0, kappa0)
+                    b = -spectral.apply_gamma0(P, prob.n, prob.l, mu0, kappa0, prob.disc)
                     try:
                         dF, it = cg(Av, b, prob, mu0, kappa0, opts.tol_cg, opts.max_cg)
                     except NegativeCurvature as e:

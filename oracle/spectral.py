@@ -1,4 +1,5 @@
-"""Spectral (Moulinec-Suquet) discretization of the Green operators (paper Sec. 3).
+"""Spectral discretizations of the Green operators (paper Sec. 3): Moulinec-Suquet
+(Fourier polynomials) and Willot's rotated scheme (willot_frequencies).
 
 Fields are real arrays [3, 3, n3, n2, n1] (tensor indices i, J first, then z, y, x
 with x fastest).  The discrete Fourier transform is numpy's FFT over the three
@@ -75,6 +76,63 @@ def frequencies(n, l):
     return xi, zero | nyq
 
 
+def willot_frequencies(n, l):
+    """Modified wave vectors of the rotated (HEX8R) scheme of Willot (2015), the
+    discretization the paper's reference solutions use (Sec. 3, 6).
+
+    The displacement lives at the voxel corners and the gradient at the voxel
+    centre is the average of the four forward differences along each axis.  For a
+    corner field u = exp(i theta . x / h) this gives, with theta_d = 2 pi k_d / n_d,
+        grad_J u = k_J u,  k_J = (e^{i theta_J} - 1) / h_J  prod_{m != J} (1 + e^{i theta_m}) / 2,
+    which is Willot's (i / 4h) tan(theta_J / 2) prod_m (1 + e^{i theta_m}) written
+    without the tangent.  Returns complex k [3, n3, n2, n1] and the mask of modes
+    with k = 0 (the mean, and modes on two or more Nyquist planes)."""
+    n1, n2, n3 = n
+    h = (l[0] / n1, l[1] / n2, l[2] / n3)
+    th = [2.0 * np.pi * np.arange(m) / m for m in (n1, n2, n3)]
+    shape = [(1, 1, n1), (1, n2, 1), (n3, 1, 1)]
+    dif = [((np.exp(1j * t) - 1.0) / hh).reshape(sh) for t, hh, sh in zip(th, h, shape)]
+    avg = [(0.5 * (1.0 + np.exp(1j * t))).reshape(sh) for t, sh in zip(th, shape)]
+    k = np.zeros((3, n3, n2, n1), dtype=complex)
+    k[0] = dif[0] * avg[1] * avg[2]
+    k[1] = avg[0] * dif[1] * avg[2]
+    k[2] = avg[0] * avg[1] * dif[2]
+    nyq = [np.zeros(m, bool) if m % 2 else (np.arange(m) == m // 2) for m in (n1, n2, n3)]
+    cnt = (nyq[0][None, None, :].astype(int) + nyq[1][None, :, None] + nyq[2][:, None, None])
+    zero = np.zeros((n3, n2, n1), bool)
+    zero[0, 0, 0] = True
+    mask = zero | (cnt >= 2)
+    k[:, mask] = 0.0
+    return k, mask
+
+
+def gamma0_hat_k(tau_hat, k, mask, mu0, kappa0):
+    """Green operator for a complex gradient multiplier k (grad_J -> k_J):
+    (Gamma^0_hat tau_hat)_iJ = k_J [K^{-1} (tau_hat conj(k))]_i with the acoustic
+    tensor K_ik = C^0_iJkL conj(k_J) k_L = mu0 |k|^2 d_ik + kappa0 conj(k_i) k_k."""
+    kc = np.conj(k)
+    v = np.einsum("iJ...,J...->i...", tau_hat, kc)
+    K = mu0 * np.einsum("...,ik->ik...", (kc * k).sum(axis=0).real, np.eye(3)) \
+        + kappa0 * np.einsum("i...,k...->ik...", kc, k)
+    K = np.where(mask[None, None], np.eye(3)[:, :, None, None, None], K)
+    Km = np.moveaxis(K, (0, 1), (-2, -1))
+    vm = np.moveaxis(v, 0, -1)[..., None]
+    w = np.moveaxis(np.linalg.solve(Km, vm)[..., 0], -1, 0)
+    out = np.einsum("i...,J...->iJ...", w, k)
+    out[:, :, mask] = 0.0
+    return out
+
+
+def g_hat_k(tau_hat, k, mask):
+    """(G_hat tau_hat)_iJ = k_J (tau_hat conj(k))_i / |k|^2."""
+    v = np.einsum("iJ...,J...->i...", tau_hat, np.conj(k))
+    k2 = (np.conj(k) * k).sum(axis=0).real
+    k2 = np.where(mask, 1.0, k2)
+    out = np.einsum("i...,J...->iJ...", v / k2, k)
+    out[:, :, mask] = 0.0
+    return out
+
+
 def gamma0_hat(tau_hat, xi, mask, mu0, kappa0):
     """(Gamma^0_hat tau_hat)_iJ = xi_J [K^{-1} (tau_hat xi)]_i, zero on masked modes."""
     v = np.einsum("iJ...,J...->i...", tau_hat, xi)               # tau_hat xi
@@ -99,13 +157,20 @@ def g_hat(tau_hat, xi, mask):
     return out
 
 
-def apply_gamma0(tau, n, l, mu0, kappa0):
-    """Gamma^0[tau] for a real field tau [3,3,n3,n2,n1]."""
+def apply_gamma0(tau, n, l, mu0, kappa0, disc="ms"):
+    """Gamma^0[tau] for a real field tau [3,3,n3,n2,n1]; disc "ms" (Fourier
+    polynomials, Sec. 3) or "willot" (rotated scheme)."""
+    if disc == "willot":
+        k, mask = willot_frequencies(n, l)
+        return ifftn(gamma0_hat_k(fftn(tau), k, mask, mu0, kappa0)).real
     xi, mask = frequencies(n, l)
     return ifftn(gamma0_hat(fftn(tau), xi, mask, mu0, kappa0)).real
 
 
-def apply_g(tau, n, l):
+def apply_g(tau, n, l, disc="ms"):
     """G[tau] for a real field tau [3,3,n3,n2,n1]."""
+    if disc == "willot":
+        k, mask = willot_frequencies(n, l)
+        return ifftn(g_hat_k(fftn(tau), k, mask)).real
     xi, mask = frequencies(n, l)
     return ifftn(g_hat(fftn(tau), xi, mask)).real
