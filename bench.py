@@ -231,6 +231,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-small-strain", action="store_true")
     ap.add_argument("--no-image", action="store_true")
+    ap.add_argument("--no-willot", action="store_true")
     ap.add_argument("--increments", type=int, default=0,
                     help="override the workload's load increments (shorter runs for counter collection)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -365,6 +366,33 @@ def main():
         out["pbar_rel_diff_mixed_vs_fp64"] = float(np.abs(Pbar_mixed - r64["Pbar"]).max() /
                                                    np.abs(r64["Pbar"]).max())
         log("fp64: %.2f s, cg %d" % (out["time_to_solution_s"]["fp64"], r64["stats"]["cg_iters_total"]))
+    if not args.no_willot:
+        # the same workload under Willot's rotated scheme (generic FFT passes)
+        combo.combo_set_discretization(ctx, combo.COMBO_DISC_WILLOT)
+        combo.combo_set_materials(ctx, lc.mats)
+        combo.combo_set_microstructure(ctx, torch.from_numpy(ms.phase).to(dev), torch.from_numpy(ms.c).to(dev),
+                                       torch.from_numpy(np.ascontiguousarray(ms.N)).to(dev))
+        combo.combo_set_options(ctx, options(combo.COMBO_MIXED))
+        combo.combo_profile_enable(ctx, True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rw = combo.combo_solve(ctx, lc.Fbar)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        pw = combo.combo_profile_all(ctx)
+        combo.combo_profile_enable(ctx, False)
+        out["willot"] = {"discretization": "rotated (HEX8R) scheme, generic FFT passes, mixed",
+                         "time_to_solution_s": el, "newton_iters": rw["stats"]["newton_iters"],
+                         "cg_iters": rw["stats"]["cg_iters_total"],
+                         "voxel_cg_iters_per_s": n * rw["stats"]["cg_iters_total"] / el,
+                         "pbar_rel_diff_vs_ms": float(np.abs(rw["Pbar"] - Pbar_mixed).max() /
+                                                      np.abs(Pbar_mixed).max()),
+                         "kernels_avg_us": {k: round(v[0] / v[1] * 1e3, 1) for k, v in pw.items() if v[1]}}
+        log("willot: %.2f s, newton %d, cg %d" % (el, rw["stats"]["newton_iters"], rw["stats"]["cg_iters_total"]))
+        combo.combo_set_discretization(ctx, combo.COMBO_DISC_MS)
+        combo.combo_set_materials(ctx, lc.mats)
+        combo.combo_set_microstructure(ctx, torch.from_numpy(ms.phase).to(dev), torch.from_numpy(ms.c).to(dev),
+                                       torch.from_numpy(np.ascontiguousarray(ms.N)).to(dev))
     if not args.no_small_strain:
         # the same RVE under the small-strain law (closed-form laminate): one linear solve
         o = options(combo.COMBO_MIXED)

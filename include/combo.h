@@ -167,6 +167,23 @@ const char* combo_last_error(const combo_ctx* ctx);
 
 /* Grid and box (paper Sec. 2: the RVE [-l1/2, l1/2] x ...).  Resets the microstructure. */
 int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2, double l3);
+/* Discretization of the gradient (paper Sec. 3 compares several; the default is
+ * the Fourier-polynomial scheme of Moulinec and Suquet).
+ * COMBO_DISC_MS: grad_J -> i xi_J, xi_d = 2 pi k_d / l_d; the mean and every
+ *   Nyquist plane of an even axis are projected out.
+ * COMBO_DISC_WILLOT: Willot's rotated (HEX8R) scheme, the discretization of the
+ *   paper's reference solutions: the displacement lives at voxel corners and the
+ *   gradient at a voxel centre is the mean of the four edge differences per axis,
+ *   grad_J -> k_J = (e^{i th_J} - 1)/h_J prod_{m != J} (1 + e^{i th_m})/2,
+ *   th_d = 2 pi k_d / n_d.  Only the mean and modes on two or more Nyquist planes
+ *   are projected out; an even n1 keeps its x-Nyquist plane.  Runs the generic
+ *   FFT passes (no schedule variants, combo_autotune keeps 0 0 0); not available
+ *   in batches.
+ * Rebuilds the grid's frequency data like combo_set_grid and therefore resets the
+ * microstructure: call after combo_set_grid, before combo_set_microstructure. */
+#define COMBO_DISC_MS 0
+#define COMBO_DISC_WILLOT 1
+int combo_set_discretization(combo_ctx* ctx, int disc);
 /* The grid and box set by combo_set_grid (host only; COMBO_E_STATE before it). */
 int combo_get_grid(const combo_ctx* ctx, int* n1, int* n2, int* n3, double* l1, double* l2, double* l3);
 /* Materials (mu, lambda) for phase 0 (matrix) and 1 (inclusion); mu > 0, lambda >= 0. */

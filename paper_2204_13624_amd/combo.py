@@ -30,6 +30,8 @@ COMBO_FP64 = 0
 COMBO_MIXED = 1
 COMBO_GREEN_GAMMA0 = 0
 COMBO_GREEN_G = 1
+COMBO_DISC_MS = 0
+COMBO_DISC_WILLOT = 1
 COMBO_NORMALS_LAPLACE = 0
 COMBO_NORMALS_BARYCENTRE = 1
 COMBO_LAW_NEO_HOOKE = 0
@@ -103,6 +105,7 @@ _SIGS = {
     "combo_set_grid": (_I, [_P, _I, _I, _I, _D, _D, _D]),
     "combo_set_materials": (_I, [_P, ctypes.POINTER(combo_material)]),
     "combo_set_microstructure": (_I, [_P, _P, _P, _P, _I]),
+    "combo_set_discretization": (_I, [_P, _I]),
     "combo_get_grid": (_I, [_P] + [ctypes.POINTER(ctypes.c_int)] * 3 + [ctypes.POINTER(ctypes.c_double)] * 3),
     "combo_image_to_boxels": (_I, [_P, _P, _I, _I, _I, _I, _P, _P, _P, _I]),
     "combo_set_microstructure_from_image": (_I, [_P, _P, _I, _I, _I, _I, _I]),
@@ -285,6 +288,10 @@ def combo_image_to_boxels(ctx, chi, s, method=COMBO_NORMALS_LAPLACE, out=None):
     _check(ctx, load_library().combo_image_to_boxels(ctx, cp, int(s[0]), int(s[1]), int(s[2]), int(method),
                                                      pp, cc, nn, _mem_kind(kind, k1, k2, k3)))
     return out
+
+
+def combo_set_discretization(ctx, disc):
+    _check(ctx, load_library().combo_set_discretization(ctx, int(disc)))
 
 
 def combo_get_grid(ctx):

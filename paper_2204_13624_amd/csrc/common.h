@@ -51,6 +51,8 @@ struct Grid {
     double xs1, xs2, xs3; // 2 pi / l_d: xi_d(k) = xs_d * k
     int xm, xwbits;       // wavefront x pass: m values per lane, log2 of lanes per row (-1: none)
     int xv, yv, zv;       // schedule: variant of the x, y and z FFT passes (0 = default)
+    int disc;             // 0: Moulinec-Suquet frequencies, 1: Willot's rotated scheme (generic kernels only)
+    const double* ftab;   // disc 1: device table D1[nh] A1[nh] D2[n2] A2[n2] D3[n3] A3[n3]
 };
 
 // Position of voxel `vox` in the tangent-state arrays.  With the wavefront x
@@ -84,6 +86,19 @@ struct BatchLaunch {
 };
 
 __host__ __device__ inline int freq_of(int j, int n) { return (j < (n + 1) / 2) ? j : j - n; }
+
+// Gradient factors per axis at a stored index: the gradient of a CG coefficient
+// field w_hat is F_hat_iJ = k'_J w_hat_i with k' = (D1 A2 A3, A1 D2 A3, A1 A2 D3).
+// Moulinec-Suquet: D_d = xi_d, A_d = 1.  Willot's rotated scheme: D = (2/h) sin(theta/2),
+// A = cos(theta/2) (the common phase of the corner-to-centre stencil is carried by w_hat).
+__device__ inline double fac_d1(const Grid& g, int k) { return g.disc ? g.ftab[k] : g.xs1 * k; }
+__device__ inline double fac_a1(const Grid& g, int k) { return g.disc ? g.ftab[g.nh + k] : 1.0; }
+__device__ inline double fac_d2(const Grid& g, int j) { return g.disc ? g.ftab[2 * g.nh + j] : g.xs2 * freq_of(j, g.n2); }
+__device__ inline double fac_a2(const Grid& g, int j) { return g.disc ? g.ftab[2 * g.nh + g.n2 + j] : 1.0; }
+__device__ inline double fac_d3(const Grid& g, int j) {
+    return g.disc ? g.ftab[2 * g.nh + 2 * g.n2 + j] : g.xs3 * freq_of(j, g.n3);
+}
+__device__ inline double fac_a3(const Grid& g, int j) { return g.disc ? g.ftab[2 * g.nh + 2 * g.n2 + g.n3 + j] : 1.0; }
 // true if index j is the Nyquist index of an even axis of length n
 __host__ __device__ inline bool is_nyquist(int j, int n) { return (n % 2 == 0) && (j == n / 2) && n > 1; }
 

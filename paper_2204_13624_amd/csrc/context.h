@@ -84,6 +84,7 @@ struct combo_ctx {
     double l[3] = {1, 1, 1};
     combo::AxisPlan plan[3]{};
     combo::DevBuf tw32[3], tw64[3];
+    combo::DevBuf ftab;                   // gradient factor table of the rotated scheme
 
     // materials and options
     bool has_mats = false;

@@ -150,18 +150,24 @@ __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int n
                 const int ca = 2 * s, cb = 2 * s + 1;
                 ha = a.in[ca * a.g.nspec + off];
                 if (s < 4) hb = a.in[cb * a.g.nspec + off];
-                const T x1 = xs1 * T(k);
-                if (xi1_comp(ca)) ha = cscale(ha, x1);
-                if (s < 4 && xi1_comp(cb)) hb = cscale(hb, x1);
+                if (a.g.disc) {
+                    const T d1 = T(fac_d1(a.g, k)), a1 = T(fac_a1(a.g, k));
+                    ha = cscale(ha, xi1_comp(ca) ? d1 : a1);
+                    if (s < 4) hb = cscale(hb, xi1_comp(cb) ? d1 : a1);
+                } else {
+                    const T x1 = xs1 * T(k);
+                    if (xi1_comp(ca)) ha = cscale(ha, x1);
+                    if (s < 4 && xi1_comp(cb)) hb = cscale(hb, x1);
+                }
             }
             C* col = buf + (s * R + rr) * L;
-            if (k == 0) {
-                col[0] = mk<T>(ha.x, hb.x);
+            if (k == 0 || 2 * k == L) {   // self-conjugate bins (x Nyquist only where it is stored)
+                col[k] = mk<T>(ha.x, hb.x);
             } else {
                 col[k] = mk<T>(ha.x - hb.y, ha.y + hb.x);
                 col[L - k] = mk<T>(ha.x + hb.y, hb.x - ha.y);
             }
-            if ((L % 2 == 0) && k == nh - 1 && L > 1) col[L / 2] = mk<T>(0, 0);
+            if (2 * nh == L && k == nh - 1 && L > 1) col[L / 2] = mk<T>(0, 0);
         }
         __syncthreads();
         fft_lds<+1, true, T>(buf, a.plan, 5 * R, tw);
@@ -250,9 +256,15 @@ __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int n
         C hb = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
         const long long off = row * nh + k;
         const int ca = 2 * s, cb = 2 * s + 1;
-        const T x1 = xs1 * T(k);
-        if (xi1_comp(ca)) ha = cscale(ha, x1);
-        if (xi1_comp(cb)) hb = cscale(hb, x1);
+        if (a.g.disc) {
+            const T d1 = T(fac_d1(a.g, k)), a1 = T(fac_a1(a.g, k));
+            ha = cscale(ha, xi1_comp(ca) ? d1 : a1);
+            hb = cscale(hb, xi1_comp(cb) ? d1 : a1);
+        } else {
+            const T x1 = xs1 * T(k);
+            if (xi1_comp(ca)) ha = cscale(ha, x1);
+            if (xi1_comp(cb)) hb = cscale(hb, x1);
+        }
         a.out[ca * a.g.nspec + off] = ha;
         if (s < 4) a.out[cb * a.g.nspec + off] = hb;
     }
@@ -730,8 +742,9 @@ __device__ __forceinline__ void k_ypass_fwd_body(const YArgs<T>& a, int tile_, i
             const int e = threadIdx.x + q * kBlock;
             if (e < items) {
                 const int y = e / TX, t = e - y * TX;
-                const T x2 = xs2 * T(freq_of(y, L));
-                const C v = cadd(acc[q], cscale(buf[e], x2));
+                const T x2 = a.g.disc ? T(fac_d2(a.g, y)) : xs2 * T(freq_of(y, L));
+                const C a0 = a.g.disc ? cscale(acc[q], T(fac_a2(a.g, y))) : acc[q];
+                const C v = cadd(a0, cscale(buf[e], x2));
                 const int kx = kx0 + t;
                 if (kx < a.g.nh) a.out[i * a.g.nspec + ((long long)z * L + y) * a.g.nh + kx] = v;
             }
@@ -740,6 +753,10 @@ __device__ __forceinline__ void k_ypass_fwd_body(const YArgs<T>& a, int tile_, i
         y_load(a, buf, 3 * i + 2, z, kx0, TX);
         __syncthreads();
         fft_lds<-1, false, T>(buf, a.plan, TX, tw);
+        if (a.g.disc) {
+            for (int e = threadIdx.x; e < items; e += kBlock) buf[e] = cscale(buf[e], T(fac_a2(a.g, e / TX)));
+            __syncthreads();
+        }
         y_store(a, buf, 3 + i, z, kx0, TX);
         __syncthreads();
     }
@@ -780,7 +797,7 @@ __device__ __forceinline__ void k_ypass_inv_body(const YArgs<T>& a, int tile_, i
                 const int y = e / TX, t = e - y * TX;
                 const int kx = kx0 + t;
                 av[q] = (kx < a.g.nh) ? a.in[i * a.g.nspec + ((long long)z * L + y) * a.g.nh + kx] : mk<T>(0, 0);
-                buf[e] = av[q];
+                buf[e] = a.g.disc ? cscale(av[q], T(fac_a2(a.g, y))) : av[q];
             }
         }
         __syncthreads();
@@ -792,7 +809,7 @@ __device__ __forceinline__ void k_ypass_inv_body(const YArgs<T>& a, int tile_, i
             const int e = threadIdx.x + q * kBlock;
             if (e < items) {
                 const int y = e / TX;
-                buf[e] = cscale(av[q], xs2 * T(freq_of(y, L)));
+                buf[e] = cscale(av[q], a.g.disc ? T(fac_d2(a.g, y)) : xs2 * T(freq_of(y, L)));
             }
         }
         __syncthreads();
@@ -801,6 +818,10 @@ __device__ __forceinline__ void k_ypass_inv_body(const YArgs<T>& a, int tile_, i
         __syncthreads();
         y_load(a, buf, 3 + i, z, kx0, TX);
         __syncthreads();
+        if (a.g.disc) {
+            for (int e = threadIdx.x; e < items; e += kBlock) buf[e] = cscale(buf[e], T(fac_a2(a.g, e / TX)));
+            __syncthreads();
+        }
         fft_lds<+1, false, T>(buf, a.plan, TX, tw);
         y_store(a, buf, 3 * i + 2, z, kx0, TX);
         __syncthreads();
@@ -830,7 +851,8 @@ struct Freq {
 // frequency data of one (y, x) column m = ky nh + kx of the half spectrum
 // (m < 2^31 for every supported grid: 32-bit index arithmetic)
 struct ColFreq {
-    double x1, x2, s12;     // xi_1, xi_2, xi_1^2 + xi_2^2
+    double x1, x2, s12;     // xi_1, xi_2, xi_1^2 + xi_2^2 (rotated scheme: D1 A2, A1 D2, unused)
+    double c3;              // rotated scheme: A1 A2
     double w;               // Parseval weight (1 on the kx = 0 plane, else 2)
     int kx, ky;
     bool zero12;            // kx = 0 and ky = 0
@@ -841,6 +863,18 @@ __device__ __forceinline__ ColFreq col_freq_k(const Grid& g, int ky, int kx) {
     ColFreq c;
     c.ky = ky;
     c.kx = kx;
+    if (g.disc) {
+        const double d1 = fac_d1(g, kx), a1 = fac_a1(g, kx), d2 = fac_d2(g, ky), a2 = fac_a2(g, ky);
+        c.x1 = d1 * a2;
+        c.x2 = a1 * d2;
+        c.c3 = a1 * a2;
+        c.s12 = 0.0;
+        c.w = (kx == 0 || 2 * kx == g.n1) ? 1.0 : 2.0;
+        c.zero12 = false;
+        c.nyq2 = false;
+        return c;
+    }
+    c.c3 = 1.0;
     const int fy = freq_of(c.ky, g.n2);
     c.x1 = g.xs1 * c.kx;
     c.x2 = g.xs2 * fy;
@@ -858,6 +892,16 @@ __device__ __forceinline__ ColFreq col_freq(const Grid& g, int m) {
 
 __device__ __forceinline__ Freq freq_z(const Grid& g, const ColFreq& c, int z) {
     Freq f;
+    if (g.disc) {
+        const double a3 = fac_a3(g, z);
+        f.x1 = c.x1 * a3;
+        f.x2 = c.x2 * a3;
+        f.x3 = c.c3 * fac_d3(g, z);
+        f.s = f.x1 * f.x1 + f.x2 * f.x2 + f.x3 * f.x3;
+        f.zero = !(f.s > 0.0);   // the mean and modes on two or more Nyquist planes
+        f.w = c.w;
+        return f;
+    }
     const int fz = freq_of(z, g.n3);
     f.x1 = c.x1;
     f.x2 = c.x2;
@@ -1016,7 +1060,7 @@ __device__ __forceinline__ void k_zpass_fwd_body(const ZArgs<T, TU>& a, int tile
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int e = threadIdx.x + q * kBlock;
-            if (e < items) v[i][q] = buf[e];
+            if (e < items) v[i][q] = a.g.disc ? cscale(buf[e], T(fac_a3(a.g, e / TX))) : buf[e];
         }
         __syncthreads();
         z_load<T>(a.in, a.g, buf, 3 + i, m0, TX);
@@ -1027,7 +1071,7 @@ __device__ __forceinline__ void k_zpass_fwd_body(const ZArgs<T, TU>& a, int tile
             const int e = threadIdx.x + q * kBlock;
             if (e < items) {
                 const int z = e / TX;
-                v[i][q] = cadd(v[i][q], cscale(buf[e], xs3 * T(freq_of(z, L))));
+                v[i][q] = cadd(v[i][q], cscale(buf[e], a.g.disc ? T(fac_d3(a.g, z)) : xs3 * T(freq_of(z, L))));
             }
         }
         __syncthreads();
@@ -1115,7 +1159,7 @@ __device__ __forceinline__ void k_zpass_inv_body(const ZArgs<T, TU>& a, int tile
                         u[q] = mk<T>(T(xi.x), T(xi.y));
                     }
                 }
-                buf[e] = u[q];
+                buf[e] = a.g.disc ? cscale(u[q], T(fac_a3(a.g, e / TX))) : u[q];
             }
         }
         __syncthreads();
@@ -1127,7 +1171,7 @@ __device__ __forceinline__ void k_zpass_inv_body(const ZArgs<T, TU>& a, int tile
             const int e = threadIdx.x + q * kBlock;
             if (e < items) {
                 const int z = e / TX;
-                buf[e] = cscale(u[q], xs3 * T(freq_of(z, L)));
+                buf[e] = cscale(u[q], a.g.disc ? T(fac_d3(a.g, z)) : xs3 * T(freq_of(z, L)));
             }
         }
         __syncthreads();
@@ -1175,6 +1219,31 @@ __device__ __forceinline__ void antiherm_pair(CU& a, CU& b) {
     a.y = TU(ay);
     b.x = TU(-ax);
     b.y = TU(ay);
+}
+
+// Self-conjugate planes of the stored half spectrum: kx = 0, and kx = n1/2 where the
+// rotated scheme stores it.  There a coefficient of a real field satisfies
+// w(-k) = sigma conj(w(k)): sigma = -1 (anti-Hermitian) where k' changes sign with k,
+// sigma = +1 (Hermitian) where it does not, i.e. (rotated scheme only) on the kx = n1/2
+// plane and, on the kx = 0 plane, at modes with exactly one Nyquist index among ky, kz.
+__device__ __forceinline__ bool selfconj_plane(const Grid& g, int kx) { return kx == 0 || (g.disc && 2 * kx == g.n1); }
+
+__device__ __forceinline__ bool herm_mode(const Grid& g, int kx, int ky, int z) {
+    if (!g.disc) return false;
+    if (kx != 0) return true;
+    return is_nyquist(ky, g.n2) != is_nyquist(z, g.n3);
+}
+
+template <typename CU>
+__device__ __forceinline__ void herm_pair(CU& a, CU& b) {
+    // a <- (a + conj b)/2, b <- conj(a_new)
+    using TU = decltype(a.x);
+    const double ax = 0.5 * (double(a.x) + double(b.x));
+    const double ay = 0.5 * (double(a.y) - double(b.y));
+    a.x = TU(ax);
+    a.y = TU(ay);
+    b.x = TU(ax);
+    b.y = TU(-ay);
 }
 
 template <typename TU>
@@ -1232,29 +1301,34 @@ __device__ __forceinline__ void k_cg_update_body(const UArgs<TU>& a, int tile_, 
         split_index(a.g, idx, z, ky, kx);
         const ColFreq cf = col_freq_k(a.g, ky, kx);
         CU r1[3];
-        if (kx != 0) {
+        if (!selfconj_plane(a.g, kx)) {
             cg_update_one(a, idx, alpha, r1);
 #pragma unroll
             for (int i = 0; i < 3; ++i) a.r[i * a.g.nspec + idx] = r1[i];
             s += rkr(a, r1, freq_z(a.g, cf, z));
             continue;
         }
-        const long long idx2 = kx0_partner(a.g, M, z, ky);
+        const long long idx2 = kx0_partner(a.g, M, z, ky) + kx;
         if (idx2 < idx) continue;   // the partner's thread owns this pair
+        const bool herm = herm_mode(a.g, kx, ky, z);
         cg_update_one(a, idx, alpha, r1);
         if (idx2 == idx) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) r1[i].x = TU(0);   // self-conjugate: purely imaginary
+            for (int i = 0; i < 3; ++i) {   // self-conjugate: purely imaginary (anti-Hermitian) or real
+                if (herm) r1[i].y = TU(0);
+                else r1[i].x = TU(0);
+            }
         } else {
             CU r2[3];
             cg_update_one(a, idx2, alpha, r2);
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                antiherm_pair(r1[i], r2[i]);
+                if (herm) herm_pair(r1[i], r2[i]);
+                else antiherm_pair(r1[i], r2[i]);
                 a.r[i * a.g.nspec + idx2] = r2[i];
             }
             const int z2 = (a.g.n3 - z) % a.g.n3, ky2 = (a.g.n2 - ky) % a.g.n2;
-            s += rkr(a, r2, freq_z(a.g, col_freq_k(a.g, ky2, 0), z2));
+            s += rkr(a, r2, freq_z(a.g, col_freq_k(a.g, ky2, kx), z2));
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) a.r[i * a.g.nspec + idx] = r1[i];
@@ -1282,19 +1356,27 @@ __device__ __forceinline__ void k_antiherm_body(const UArgs<TU>& a, int tile_, i
     cpx<TU>* u = a.r;
     const long long M = (long long)g.n2 * g.nh;
     const long long npl = (long long)g.n2 * g.n3;
-    for (long long t = (long long)tile_ * blockDim.x + threadIdx.x; t < npl; t += (long long)ntiles_ * blockDim.x) {
-        const int z = (int)(t / g.n2), ky = (int)(t - (long long)z * g.n2);
-        const long long idx = (long long)z * M + (long long)ky * g.nh;
-        const long long idx2 = kx0_partner(g, M, z, ky);
+    const int nplanes = (g.disc && g.n1 > 1 && 2 * (g.nh - 1) == g.n1) ? 2 : 1;
+    for (long long t = (long long)tile_ * blockDim.x + threadIdx.x; t < npl * nplanes;
+         t += (long long)ntiles_ * blockDim.x) {
+        const int plane = (int)(t / npl);
+        const long long tp = t - plane * npl;
+        const int kx = plane ? g.nh - 1 : 0;
+        const int z = (int)(tp / g.n2), ky = (int)(tp - (long long)z * g.n2);
+        const long long idx = (long long)z * M + (long long)ky * g.nh + kx;
+        const long long idx2 = kx0_partner(g, M, z, ky) + kx;
         if (idx2 < idx) continue;
+        const bool herm = herm_mode(g, kx, ky, z);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             cpx<TU> v = u[i * g.nspec + idx];
             if (idx2 == idx) {
-                v.x = TU(0);
+                if (herm) v.y = TU(0);
+                else v.x = TU(0);
             } else {
                 cpx<TU> w = u[i * g.nspec + idx2];
-                antiherm_pair(v, w);
+                if (herm) herm_pair(v, w);
+                else antiherm_pair(v, w);
                 u[i * g.nspec + idx2] = w;
             }
             u[i * g.nspec + idx] = v;
@@ -1753,14 +1835,14 @@ int fft2_tx(int L, int v) {
 
 template <typename T>
 int y_tile(const Grid& g) {
-    const int tx = fft2_tx<T>(g.n2, g.yv);
+    const int tx = g.disc ? 0 : fft2_tx<T>(g.n2, g.yv);
     if (tx) return tx;
     return std::max(1, std::min(g.nh, max_elems<T>() / g.n2));
 }
 
 template <typename T>
 int z_tile(const Grid& g) {
-    const int tx = fft2_tx<T>(g.n3, g.zv);
+    const int tx = g.disc ? 0 : fft2_tx<T>(g.n3, g.zv);
     if (tx) return tx;
     return (int)std::max<long long>(1, std::min<long long>((long long)g.n2 * g.nh, max_elems<T>() / g.n3));
 }
@@ -1813,6 +1895,7 @@ int xpass_lds_rows(int n1, int v, bool is_float) {
 
 int blocks_x(const Grid& g, int R, int mode, bool is_float) {
     const long long nrows = (long long)g.n2 * g.n3;
+    if (g.disc) return (int)((nrows + R - 1) / R);
     if (mode == X_CG || mode == X_AVG) {
         const int rows = xpass_lds_rows(g.n1, g.xv, is_float);
         if (rows > 0) return (int)((nrows + rows - 1) / rows);
@@ -1850,7 +1933,7 @@ template <typename T>
 hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const BatchLaunch* b) {
     using XA = XArgs<T>;
     const long long nrows = (long long)a.g.n2 * a.g.n3;
-    if (mode == X_CG || mode == X_AVG) {
+    if (!a.g.disc && (mode == X_CG || mode == X_AVG)) {
         const int vv = xpass_lds_pick(a.g.n1, a.g.xv, std::is_same<T, float>::value);
 #define COMBO_XL_CASE(LL, PP, QQ, RR, VV)                                                                    \
         if constexpr (VV == 0 || std::is_same<T, float>::value) {                                            \
@@ -1867,7 +1950,7 @@ hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const B
 #undef COMBO_XL_CASE
     }
 #define COMBO_XW_CASE(LL, MM, WW)                                                                             \
-    if (a.g.n1 == LL) {                                                                                     \
+    if (!a.g.disc && a.g.n1 == LL) {                                                                        \
         const int nblk = (int)((nrows + (256 / WW) - 1) / (256 / WW));                                       \
         if (nb) *nb = nblk;                                                                                  \
         switch (mode) {                                                                                      \
@@ -1914,7 +1997,7 @@ hipError_t launch_y(int dir, const YArgs<T>& a0, hipStream_t s, const BatchLaunc
     const int vv = fft2_pick<T>(a.g.n2, a.g.yv);
 #define COMBO_Y_CASE(TT, LL, PP, QQ, TXX, VV)                                                                   \
     if constexpr (std::is_same<T, TT>::value) {                                                               \
-        if (a.g.n2 == LL && vv == VV) {                                                                        \
+        if (!a.g.disc && a.g.n2 == LL && vv == VV) {                                                           \
             constexpr int nt = fft2_threads<PP, QQ, TXX>();                                                    \
             if (dir < 0) COMBO_LAUNCH(k_y2_fwd, (PP, QQ, TXX, T), YA, nblk, nt, 0);                      \
             else COMBO_LAUNCH(k_y2_inv, (PP, QQ, TXX, T), YA, nblk, nt, 0);                              \
@@ -1942,7 +2025,7 @@ hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb, co
     const int vv = fft2_pick<T>(a.g.n3, a.g.zv);
 #define COMBO_Z_CASE(TT, LL, PP, QQ, TXX, VV)                                                                  \
     if constexpr (std::is_same<T, TT>::value) {                                                              \
-        if (a.g.n3 == LL && vv == VV) {                                                                       \
+        if (!a.g.disc && a.g.n3 == LL && vv == VV) {                                                          \
             constexpr int nt = fft2_threads<PP, QQ, TXX>();                                                   \
             switch (mode) {                                                                                   \
                 case Z_CG: COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_CG), ZA, nblk, nt, 0); break;        \
@@ -1980,7 +2063,7 @@ hipError_t launch_update(const UArgs<TU>& a, hipStream_t s, int* nb, const Batch
 }
 
 int blocks_antiherm(const Grid& g) {
-    const long long npl = (long long)g.n2 * g.n3;
+    const long long npl = 2LL * g.n2 * g.n3;
     return (int)std::min<long long>((npl + kBlock - 1) / kBlock, 1024);
 }
 

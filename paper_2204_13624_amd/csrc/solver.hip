@@ -686,6 +686,7 @@ void apply_schedule(combo_ctx* ctx, const Schedule& sc) {
 }
 
 int autotune(combo_ctx* ctx, int precision) {
+    if (ctx->g.disc != COMBO_DISC_MS) return COMBO_OK;   // the rotated scheme has one (generic) schedule
     const std::string key = tune_key(ctx, precision);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1735,6 +1736,8 @@ int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2,
     ctx->g.n2 = n2;
     ctx->g.n3 = n3;
     ctx->g.xv = ctx->g.yv = ctx->g.zv = 0;
+    ctx->g.disc = COMBO_DISC_MS;
+    ctx->g.ftab = nullptr;
     ctx->g.nh = (n1 % 2 == 0) ? n1 / 2 : (n1 + 1) / 2;
     ctx->g.n = (long long)n1 * n2 * n3;
     ctx->g.nspec = (long long)ctx->g.nh * n2 * n3;
@@ -1775,6 +1778,42 @@ int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2,
     for (auto& gr : ctx->graph) gr.reset();
     ctx->has_grid = true;
     ctx->has_ms = false;
+    return COMBO_OK;
+}
+
+int combo_set_discretization(combo_ctx* ctx, int disc) {
+    if (!ctx) return COMBO_E_INVAL;
+    if (!ctx->has_grid) return set_err(ctx, COMBO_E_STATE, "combo_set_grid has not been called");
+    if (disc != COMBO_DISC_MS && disc != COMBO_DISC_WILLOT)
+        return set_err(ctx, COMBO_E_INVAL, "disc must be COMBO_DISC_MS or COMBO_DISC_WILLOT");
+    const int n1 = ctx->g.n1, n2 = ctx->g.n2, n3 = ctx->g.n3;
+    int st = combo_set_grid(ctx, n1, n2, n3, ctx->l[0], ctx->l[1], ctx->l[2]);
+    if (st != COMBO_OK || disc == COMBO_DISC_MS) return st;
+    Grid& g = ctx->g;
+    g.disc = COMBO_DISC_WILLOT;
+    g.nh = n1 / 2 + 1;   // x frequencies 0 .. floor(n1/2): an even n1 keeps its Nyquist bin
+    g.nspec = (long long)g.nh * n2 * n3;
+    g.xwbits = -1;       // natural state order: the rotated scheme runs the generic x pass
+    // D = (2/h) sin(theta/2), A = cos(theta/2); x: theta = 2 pi k / n1 (k >= 0), y and z:
+    // theta = 2 pi freq / n with freq in [-n/2, n/2); A = 0 exactly at |theta| = pi
+    const int ns[3] = {n1, n2, n3};
+    const int len[3] = {g.nh, n2, n3};
+    std::vector<double> tab;
+    for (int d = 0; d < 3; ++d) {
+        const long double h = (long double)ctx->l[d] / ns[d];
+        std::vector<double> D(len[d]), A(len[d]);
+        for (int j = 0; j < len[d]; ++j) {
+            const int f = (d == 0) ? j : freq_of(j, ns[d]);
+            const long double half = 3.14159265358979323846264338327950288L * (long double)f / (long double)ns[d];
+            D[j] = (double)(2.0L / h * sinl(half));
+            A[j] = (2 * f == ns[d] || 2 * f == -ns[d]) ? 0.0 : (double)cosl(half);
+        }
+        tab.insert(tab.end(), D.begin(), D.end());
+        tab.insert(tab.end(), A.begin(), A.end());
+    }
+    HIP_OR_FAIL(ctx->ftab.ensure(sizeof(double) * tab.size()));
+    HIP_OR_FAIL(hipMemcpy(ctx->ftab.p, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice));
+    g.ftab = static_cast<const double*>(ctx->ftab.p);
     return COMBO_OK;
 }
 
