@@ -709,7 +709,7 @@ __device__ __forceinline__ void y_store(const YArgs<T>& a, const cpx<T>* buf, in
 
 // forward: in 9 comps (row-major (i,J), comps (i,1) already times xi_1) -> out 6:
 // out_i = FFT(in_i1) + xi_2 FFT(in_i2), out_{3+i} = FFT(in_i3)   (1-based J in the comments)
-template <typename T>
+template <typename T, int DISC>
 __device__ __forceinline__ void k_ypass_fwd_body(const YArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     if (a.st && a.st->done) return;
@@ -742,8 +742,8 @@ __device__ __forceinline__ void k_ypass_fwd_body(const YArgs<T>& a, int tile_, i
             const int e = threadIdx.x + q * kBlock;
             if (e < items) {
                 const int y = e / TX, t = e - y * TX;
-                const T x2 = a.g.disc ? T(fac_d2(a.g, y)) : xs2 * T(freq_of(y, L));
-                const C a0 = a.g.disc ? cscale(acc[q], T(fac_a2(a.g, y))) : acc[q];
+                const T x2 = DISC ? T(fac_d2(a.g, y)) : xs2 * T(freq_of(y, L));
+                const C a0 = DISC ? cscale(acc[q], T(fac_a2(a.g, y))) : acc[q];
                 const C v = cadd(a0, cscale(buf[e], x2));
                 const int kx = kx0 + t;
                 if (kx < a.g.nh) a.out[i * a.g.nspec + ((long long)z * L + y) * a.g.nh + kx] = v;
@@ -753,7 +753,7 @@ __device__ __forceinline__ void k_ypass_fwd_body(const YArgs<T>& a, int tile_, i
         y_load(a, buf, 3 * i + 2, z, kx0, TX);
         __syncthreads();
         fft_lds<-1, false, T>(buf, a.plan, TX, tw);
-        if (a.g.disc) {
+        if (DISC) {
             for (int e = threadIdx.x; e < items; e += kBlock) buf[e] = cscale(buf[e], T(fac_a2(a.g, e / TX)));
             __syncthreads();
         }
@@ -762,19 +762,19 @@ __device__ __forceinline__ void k_ypass_fwd_body(const YArgs<T>& a, int tile_, i
     }
 }
 
-template <typename T>
+template <typename T, int DISC>
 __global__ void __launch_bounds__(kBlock) k_ypass_fwd(YArgs<T> a) {
-    k_ypass_fwd_body<T>(a, blockIdx.x, gridDim.x);
+    k_ypass_fwd_body<T, DISC>(a, blockIdx.x, gridDim.x);
 }
 
-template <typename T>
+template <typename T, int DISC>
 __global__ void __launch_bounds__(kBlock) k_ypass_fwd_b(const YArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
     const TileMap e = map[blockIdx.x];
-    k_ypass_fwd_body<T>(as[e.rve], e.tile, e.ntiles);
+    k_ypass_fwd_body<T, DISC>(as[e.rve], e.tile, e.ntiles);
 }
 
 // inverse: in 6 comps [A_i, B_i] -> out 9: (i,1) = IFFT(A_i), (i,2) = IFFT(xi_2 A_i), (i,3) = IFFT(B_i)
-template <typename T>
+template <typename T, int DISC>
 __device__ __forceinline__ void k_ypass_inv_body(const YArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     if (a.st && a.st->done) return;
@@ -797,7 +797,7 @@ __device__ __forceinline__ void k_ypass_inv_body(const YArgs<T>& a, int tile_, i
                 const int y = e / TX, t = e - y * TX;
                 const int kx = kx0 + t;
                 av[q] = (kx < a.g.nh) ? a.in[i * a.g.nspec + ((long long)z * L + y) * a.g.nh + kx] : mk<T>(0, 0);
-                buf[e] = a.g.disc ? cscale(av[q], T(fac_a2(a.g, y))) : av[q];
+                buf[e] = DISC ? cscale(av[q], T(fac_a2(a.g, y))) : av[q];
             }
         }
         __syncthreads();
@@ -809,7 +809,7 @@ __device__ __forceinline__ void k_ypass_inv_body(const YArgs<T>& a, int tile_, i
             const int e = threadIdx.x + q * kBlock;
             if (e < items) {
                 const int y = e / TX;
-                buf[e] = cscale(av[q], a.g.disc ? T(fac_d2(a.g, y)) : xs2 * T(freq_of(y, L)));
+                buf[e] = cscale(av[q], DISC ? T(fac_d2(a.g, y)) : xs2 * T(freq_of(y, L)));
             }
         }
         __syncthreads();
@@ -818,7 +818,7 @@ __device__ __forceinline__ void k_ypass_inv_body(const YArgs<T>& a, int tile_, i
         __syncthreads();
         y_load(a, buf, 3 + i, z, kx0, TX);
         __syncthreads();
-        if (a.g.disc) {
+        if (DISC) {
             for (int e = threadIdx.x; e < items; e += kBlock) buf[e] = cscale(buf[e], T(fac_a2(a.g, e / TX)));
             __syncthreads();
         }
@@ -828,15 +828,15 @@ __device__ __forceinline__ void k_ypass_inv_body(const YArgs<T>& a, int tile_, i
     }
 }
 
-template <typename T>
+template <typename T, int DISC>
 __global__ void __launch_bounds__(kBlock) k_ypass_inv(YArgs<T> a) {
-    k_ypass_inv_body<T>(a, blockIdx.x, gridDim.x);
+    k_ypass_inv_body<T, DISC>(a, blockIdx.x, gridDim.x);
 }
 
-template <typename T>
+template <typename T, int DISC>
 __global__ void __launch_bounds__(kBlock) k_ypass_inv_b(const YArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
     const TileMap e = map[blockIdx.x];
-    k_ypass_inv_body<T>(as[e.rve], e.tile, e.ntiles);
+    k_ypass_inv_body<T, DISC>(as[e.rve], e.tile, e.ntiles);
 }
 
 // ------------------------------------------------------------------------------
@@ -1036,7 +1036,7 @@ __device__ __forceinline__ void z_store(cpx<T>* out, const Grid& g, const cpx<T>
 //   Z_CG:   q = K^{-1} v / n, partial sum of <p, q>_K = sum w Re(p^H v)/n
 //   Z_RHS:  r = b = -K^{-1} v, x = 0, partials of <b, b>_K and of |G P|^2 = |v|^2/|xi|^2
 //   Z_PROJ: x = K^{-1} v
-template <typename T, typename TU, int MODE>
+template <typename T, typename TU, int MODE, int DISC>
 __device__ __forceinline__ void k_zpass_fwd_body(const ZArgs<T, TU>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using CU = cpx<TU>;
@@ -1060,7 +1060,7 @@ __device__ __forceinline__ void k_zpass_fwd_body(const ZArgs<T, TU>& a, int tile
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int e = threadIdx.x + q * kBlock;
-            if (e < items) v[i][q] = a.g.disc ? cscale(buf[e], T(fac_a3(a.g, e / TX))) : buf[e];
+            if (e < items) v[i][q] = DISC ? cscale(buf[e], T(fac_a3(a.g, e / TX))) : buf[e];
         }
         __syncthreads();
         z_load<T>(a.in, a.g, buf, 3 + i, m0, TX);
@@ -1071,7 +1071,7 @@ __device__ __forceinline__ void k_zpass_fwd_body(const ZArgs<T, TU>& a, int tile
             const int e = threadIdx.x + q * kBlock;
             if (e < items) {
                 const int z = e / TX;
-                v[i][q] = cadd(v[i][q], cscale(buf[e], a.g.disc ? T(fac_d3(a.g, z)) : xs3 * T(freq_of(z, L))));
+                v[i][q] = cadd(v[i][q], cscale(buf[e], DISC ? T(fac_d3(a.g, z)) : xs3 * T(freq_of(z, L))));
             }
         }
         __syncthreads();
@@ -1097,20 +1097,20 @@ __device__ __forceinline__ void k_zpass_fwd_body(const ZArgs<T, TU>& a, int tile
     }
 }
 
-template <typename T, typename TU, int MODE>
+template <typename T, typename TU, int MODE, int DISC>
 __global__ void __launch_bounds__(kBlock) k_zpass_fwd(ZArgs<T, TU> a) {
-    k_zpass_fwd_body<T, TU, MODE>(a, blockIdx.x, gridDim.x);
+    k_zpass_fwd_body<T, TU, MODE, DISC>(a, blockIdx.x, gridDim.x);
 }
 
-template <typename T, typename TU, int MODE>
+template <typename T, typename TU, int MODE, int DISC>
 __global__ void __launch_bounds__(kBlock) k_zpass_fwd_b(const ZArgs<T, TU>* __restrict__ as, const TileMap* __restrict__ map) {
     const TileMap e = map[blockIdx.x];
-    k_zpass_fwd_body<T, TU, MODE>(as[e.rve], e.tile, e.ntiles);
+    k_zpass_fwd_body<T, TU, MODE, DISC>(as[e.rve], e.tile, e.ntiles);
 }
 
 // inverse z pass: source vector u (Z_INV_CG: p = r + beta p first, p = r on the
 // first iteration; Z_INV_PLAIN: u = x), out_i = IFFT(u_i), out_{3+i} = IFFT(xi_3 u_i)
-template <typename T, typename TU, int MODE>
+template <typename T, typename TU, int MODE, int DISC>
 __device__ __forceinline__ void k_zpass_inv_body(const ZArgs<T, TU>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using CU = cpx<TU>;
@@ -1159,7 +1159,7 @@ __device__ __forceinline__ void k_zpass_inv_body(const ZArgs<T, TU>& a, int tile
                         u[q] = mk<T>(T(xi.x), T(xi.y));
                     }
                 }
-                buf[e] = a.g.disc ? cscale(u[q], T(fac_a3(a.g, e / TX))) : u[q];
+                buf[e] = DISC ? cscale(u[q], T(fac_a3(a.g, e / TX))) : u[q];
             }
         }
         __syncthreads();
@@ -1171,7 +1171,7 @@ __device__ __forceinline__ void k_zpass_inv_body(const ZArgs<T, TU>& a, int tile
             const int e = threadIdx.x + q * kBlock;
             if (e < items) {
                 const int z = e / TX;
-                buf[e] = cscale(u[q], a.g.disc ? T(fac_d3(a.g, z)) : xs3 * T(freq_of(z, L)));
+                buf[e] = cscale(u[q], DISC ? T(fac_d3(a.g, z)) : xs3 * T(freq_of(z, L)));
             }
         }
         __syncthreads();
@@ -1181,15 +1181,15 @@ __device__ __forceinline__ void k_zpass_inv_body(const ZArgs<T, TU>& a, int tile
     }
 }
 
-template <typename T, typename TU, int MODE>
+template <typename T, typename TU, int MODE, int DISC>
 __global__ void __launch_bounds__(kBlock) k_zpass_inv(ZArgs<T, TU> a) {
-    k_zpass_inv_body<T, TU, MODE>(a, blockIdx.x, gridDim.x);
+    k_zpass_inv_body<T, TU, MODE, DISC>(a, blockIdx.x, gridDim.x);
 }
 
-template <typename T, typename TU, int MODE>
+template <typename T, typename TU, int MODE, int DISC>
 __global__ void __launch_bounds__(kBlock) k_zpass_inv_b(const ZArgs<T, TU>* __restrict__ as, const TileMap* __restrict__ map) {
     const TileMap e = map[blockIdx.x];
-    k_zpass_inv_body<T, TU, MODE>(as[e.rve], e.tile, e.ntiles);
+    k_zpass_inv_body<T, TU, MODE, DISC>(as[e.rve], e.tile, e.ntiles);
 }
 
 // ------------------------------------------------------------------------------
@@ -1475,7 +1475,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_columns(const double* partial
 template <int P, int Q, int TX>
 constexpr int fft2_threads() { return TX * (P > Q ? P : Q); }
 
-template <int P, int Q, int TX, typename T>
+template <int P, int Q, int TX, typename T, int DISC>
 __device__ __forceinline__ void k_y2_fwd_body(const YArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using F = Fft2<P, Q, TX>;
@@ -1519,7 +1519,8 @@ __device__ __forceinline__ void k_y2_fwd_body(const YArgs<T>& a, int tile_, int 
                 fft2_stageB<P, Q, TX, -1, T>(y, tB, k1, ex);
                 if (sub == 0) {
 #pragma unroll
-                    for (int k2 = 0; k2 < P; ++k2) acc[k2] = y[k2];
+                    for (int k2 = 0; k2 < P; ++k2)
+                        acc[k2] = DISC ? cscale(y[k2], T(fac_a2(a.g, k1 + Q * k2))) : y[k2];
                 } else if (colB) {
                     const int oc = (sub == 1) ? i : 3 + i;
                     C* dst = a.out + oc * a.g.nspec + zoff + kx0;   // uniform
@@ -1527,7 +1528,8 @@ __device__ __forceinline__ void k_y2_fwd_body(const YArgs<T>& a, int tile_, int 
                     for (int k2 = 0; k2 < P; ++k2) {
                         const int ky = k1 + Q * k2;
                         C v = y[k2];
-                        if (sub == 1) v = cadd(acc[k2], cscale(v, xs2 * T(freq_of(ky, L))));
+                        if (sub == 1) v = cadd(acc[k2], cscale(v, DISC ? T(fac_d2(a.g, ky)) : xs2 * T(freq_of(ky, L))));
+                        else if (DISC) v = cscale(v, T(fac_a2(a.g, ky)));
                         dst[tB + ky * nh] = v;
                     }
                 }
@@ -1537,18 +1539,18 @@ __device__ __forceinline__ void k_y2_fwd_body(const YArgs<T>& a, int tile_, int 
     }
 }
 
-template <int P, int Q, int TX, typename T>
+template <int P, int Q, int TX, typename T, int DISC>
 __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_fwd(YArgs<T> a) {
-    k_y2_fwd_body<P, Q, TX, T>(a, blockIdx.x, gridDim.x);
+    k_y2_fwd_body<P, Q, TX, T, DISC>(a, blockIdx.x, gridDim.x);
 }
 
-template <int P, int Q, int TX, typename T>
+template <int P, int Q, int TX, typename T, int DISC>
 __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_fwd_b(const YArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
     const TileMap e = map[blockIdx.x];
-    k_y2_fwd_body<P, Q, TX, T>(as[e.rve], e.tile, e.ntiles);
+    k_y2_fwd_body<P, Q, TX, T, DISC>(as[e.rve], e.tile, e.ntiles);
 }
 
-template <int P, int Q, int TX, typename T>
+template <int P, int Q, int TX, typename T, int DISC>
 __device__ __forceinline__ void k_y2_inv_body(const YArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using F = Fft2<P, Q, TX>;
@@ -1584,7 +1586,8 @@ __device__ __forceinline__ void k_y2_inv_body(const YArgs<T>& a, int tile_, int 
 #pragma unroll
             for (int j2 = 0; j2 < Q; ++j2) {
                 const int y = j1 + P * j2;
-                x[j2] = (sub == 1) ? cscale(nx[j2], xs2 * T(freq_of(y, L))) : nx[j2];
+                if (DISC) x[j2] = cscale(nx[j2], T(sub == 1 ? fac_d2(a.g, y) : fac_a2(a.g, y)));
+                else x[j2] = (sub == 1) ? cscale(nx[j2], xs2 * T(freq_of(y, L))) : nx[j2];
             }
             if (3 * i + sub + 1 < 9) load(3 * i + sub + 1);
             if (hasA) fft2_stageA<P, Q, TX, +1, T>(x, tA, j1, ex, tw);
@@ -1601,18 +1604,18 @@ __device__ __forceinline__ void k_y2_inv_body(const YArgs<T>& a, int tile_, int 
     }
 }
 
-template <int P, int Q, int TX, typename T>
+template <int P, int Q, int TX, typename T, int DISC>
 __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_inv(YArgs<T> a) {
-    k_y2_inv_body<P, Q, TX, T>(a, blockIdx.x, gridDim.x);
+    k_y2_inv_body<P, Q, TX, T, DISC>(a, blockIdx.x, gridDim.x);
 }
 
-template <int P, int Q, int TX, typename T>
+template <int P, int Q, int TX, typename T, int DISC>
 __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_y2_inv_b(const YArgs<T>* __restrict__ as, const TileMap* __restrict__ map) {
     const TileMap e = map[blockIdx.x];
-    k_y2_inv_body<P, Q, TX, T>(as[e.rve], e.tile, e.ntiles);
+    k_y2_inv_body<P, Q, TX, T, DISC>(as[e.rve], e.tile, e.ntiles);
 }
 
-template <int P, int Q, int TX, typename T, typename TU, int MODE>
+template <int P, int Q, int TX, typename T, typename TU, int MODE, int DISC>
 __device__ __forceinline__ void k_z2_fwd_body(const ZArgs<T, TU>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using F = Fft2<P, Q, TX>;
@@ -1656,8 +1659,14 @@ __device__ __forceinline__ void k_z2_fwd_body(const ZArgs<T, TU>& a, int tile_, 
                 fft2_stageB<P, Q, TX, -1, T>(y, tB, k1, ex);
 #pragma unroll
                 for (int k2 = 0; k2 < P; ++k2) {
-                    if (sub == 0) v[i][k2] = y[k2];
-                    else v[i][k2] = cadd(v[i][k2], cscale(y[k2], xs3 * T(freq_of(k1 + Q * k2, L))));
+                    const int zz = k1 + Q * k2;
+                    if constexpr (DISC) {
+                        if (sub == 0) v[i][k2] = cscale(y[k2], T(fac_a3(a.g, zz)));
+                        else v[i][k2] = cadd(v[i][k2], cscale(y[k2], T(fac_d3(a.g, zz))));
+                    } else {
+                        if (sub == 0) v[i][k2] = y[k2];
+                        else v[i][k2] = cadd(v[i][k2], cscale(y[k2], xs3 * T(freq_of(zz, L))));
+                    }
                 }
             }
             __syncthreads();
@@ -1682,18 +1691,18 @@ __device__ __forceinline__ void k_z2_fwd_body(const ZArgs<T, TU>& a, int tile_, 
     }
 }
 
-template <int P, int Q, int TX, typename T, typename TU, int MODE>
+template <int P, int Q, int TX, typename T, typename TU, int MODE, int DISC>
 __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_fwd(ZArgs<T, TU> a) {
-    k_z2_fwd_body<P, Q, TX, T, TU, MODE>(a, blockIdx.x, gridDim.x);
+    k_z2_fwd_body<P, Q, TX, T, TU, MODE, DISC>(a, blockIdx.x, gridDim.x);
 }
 
-template <int P, int Q, int TX, typename T, typename TU, int MODE>
+template <int P, int Q, int TX, typename T, typename TU, int MODE, int DISC>
 __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_fwd_b(const ZArgs<T, TU>* __restrict__ as, const TileMap* __restrict__ map) {
     const TileMap e = map[blockIdx.x];
-    k_z2_fwd_body<P, Q, TX, T, TU, MODE>(as[e.rve], e.tile, e.ntiles);
+    k_z2_fwd_body<P, Q, TX, T, TU, MODE, DISC>(as[e.rve], e.tile, e.ntiles);
 }
 
-template <int P, int Q, int TX, typename T, typename TU, int MODE>
+template <int P, int Q, int TX, typename T, typename TU, int MODE, int DISC>
 __device__ __forceinline__ void k_z2_inv_body(const ZArgs<T, TU>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using CU = cpx<TU>;
@@ -1755,7 +1764,11 @@ __device__ __forceinline__ void k_z2_inv_body(const ZArgs<T, TU>& a, int tile_, 
             if (hasA) {
                 C x[Q];
 #pragma unroll
-                for (int j2 = 0; j2 < Q; ++j2) x[j2] = sub ? cscale(u[j2], xs3 * T(freq_of(j1 + P * j2, L))) : u[j2];
+                for (int j2 = 0; j2 < Q; ++j2) {
+                    const int zz = j1 + P * j2;
+                    if (DISC) x[j2] = cscale(u[j2], T(sub ? fac_d3(a.g, zz) : fac_a3(a.g, zz)));
+                    else x[j2] = sub ? cscale(u[j2], xs3 * T(freq_of(zz, L))) : u[j2];
+                }
                 fft2_stageA<P, Q, TX, +1, T>(x, tA, j1, ex, tw);
             }
             __syncthreads();
@@ -1772,15 +1785,15 @@ __device__ __forceinline__ void k_z2_inv_body(const ZArgs<T, TU>& a, int tile_, 
     }
 }
 
-template <int P, int Q, int TX, typename T, typename TU, int MODE>
+template <int P, int Q, int TX, typename T, typename TU, int MODE, int DISC>
 __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_inv(ZArgs<T, TU> a) {
-    k_z2_inv_body<P, Q, TX, T, TU, MODE>(a, blockIdx.x, gridDim.x);
+    k_z2_inv_body<P, Q, TX, T, TU, MODE, DISC>(a, blockIdx.x, gridDim.x);
 }
 
-template <int P, int Q, int TX, typename T, typename TU, int MODE>
+template <int P, int Q, int TX, typename T, typename TU, int MODE, int DISC>
 __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_inv_b(const ZArgs<T, TU>* __restrict__ as, const TileMap* __restrict__ map) {
     const TileMap e = map[blockIdx.x];
-    k_z2_inv_body<P, Q, TX, T, TU, MODE>(as[e.rve], e.tile, e.ntiles);
+    k_z2_inv_body<P, Q, TX, T, TU, MODE, DISC>(as[e.rve], e.tile, e.ntiles);
 }
 
 // Supported fast-path lengths: (P, Q, TX) per precision; TX keeps the exchange
@@ -1835,14 +1848,14 @@ int fft2_tx(int L, int v) {
 
 template <typename T>
 int y_tile(const Grid& g) {
-    const int tx = g.disc ? 0 : fft2_tx<T>(g.n2, g.yv);
+    const int tx = fft2_tx<T>(g.n2, g.yv);
     if (tx) return tx;
     return std::max(1, std::min(g.nh, max_elems<T>() / g.n2));
 }
 
 template <typename T>
 int z_tile(const Grid& g) {
-    const int tx = g.disc ? 0 : fft2_tx<T>(g.n3, g.zv);
+    const int tx = fft2_tx<T>(g.n3, g.zv);
     if (tx) return tx;
     return (int)std::max<long long>(1, std::min<long long>((long long)g.n2 * g.nh, max_elems<T>() / g.n3));
 }
@@ -1997,18 +2010,22 @@ hipError_t launch_y(int dir, const YArgs<T>& a0, hipStream_t s, const BatchLaunc
     const int vv = fft2_pick<T>(a.g.n2, a.g.yv);
 #define COMBO_Y_CASE(TT, LL, PP, QQ, TXX, VV)                                                                   \
     if constexpr (std::is_same<T, TT>::value) {                                                               \
-        if (!a.g.disc && a.g.n2 == LL && vv == VV) {                                                           \
+        if (a.g.n2 == LL && vv == VV) {                                                                        \
             constexpr int nt = fft2_threads<PP, QQ, TXX>();                                                    \
-            if (dir < 0) COMBO_LAUNCH(k_y2_fwd, (PP, QQ, TXX, T), YA, nblk, nt, 0);                      \
-            else COMBO_LAUNCH(k_y2_inv, (PP, QQ, TXX, T), YA, nblk, nt, 0);                              \
+            if (dir < 0 && a.g.disc) COMBO_LAUNCH(k_y2_fwd, (PP, QQ, TXX, T, 1), YA, nblk, nt, 0);       \
+            else if (dir < 0) COMBO_LAUNCH(k_y2_fwd, (PP, QQ, TXX, T, 0), YA, nblk, nt, 0);              \
+            else if (a.g.disc) COMBO_LAUNCH(k_y2_inv, (PP, QQ, TXX, T, 1), YA, nblk, nt, 0);             \
+            else COMBO_LAUNCH(k_y2_inv, (PP, QQ, TXX, T, 0), YA, nblk, nt, 0);                           \
             return hipGetLastError();                                                                          \
         }                                                                                                      \
     }
     COMBO_FFT2_CONFIGS(COMBO_Y_CASE)
 #undef COMBO_Y_CASE
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n2 + (size_t)a.g.n2 * a.TX);
-    if (dir < 0) COMBO_LAUNCH(k_ypass_fwd, (T), YA, nblk, kBlock, lds);
-    else COMBO_LAUNCH(k_ypass_inv, (T), YA, nblk, kBlock, lds);
+    if (dir < 0 && a.g.disc) COMBO_LAUNCH(k_ypass_fwd, (T, 1), YA, nblk, kBlock, lds);
+    else if (dir < 0) COMBO_LAUNCH(k_ypass_fwd, (T, 0), YA, nblk, kBlock, lds);
+    else if (a.g.disc) COMBO_LAUNCH(k_ypass_inv, (T, 1), YA, nblk, kBlock, lds);
+    else COMBO_LAUNCH(k_ypass_inv, (T, 0), YA, nblk, kBlock, lds);
     return hipGetLastError();
 }
 
@@ -2025,14 +2042,29 @@ hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb, co
     const int vv = fft2_pick<T>(a.g.n3, a.g.zv);
 #define COMBO_Z_CASE(TT, LL, PP, QQ, TXX, VV)                                                                  \
     if constexpr (std::is_same<T, TT>::value) {                                                              \
-        if (!a.g.disc && a.g.n3 == LL && vv == VV) {                                                          \
+        if (a.g.n3 == LL && vv == VV) {                                                                       \
             constexpr int nt = fft2_threads<PP, QQ, TXX>();                                                   \
             switch (mode) {                                                                                   \
-                case Z_CG: COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_CG), ZA, nblk, nt, 0); break;        \
-                case Z_RHS: COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_RHS), ZA, nblk, nt, 0); break;      \
-                case Z_PROJ: COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_PROJ), ZA, nblk, nt, 0); break;    \
-                case Z_INV_CG: COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_CG), ZA, nblk, nt, 0); break; \
-                default: COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_PLAIN), ZA, nblk, nt, 0); break;  \
+                case Z_CG:                                                                                    \
+                    if (a.g.disc) COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_CG, 1), ZA, nblk, nt, 0);     \
+                    else COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_CG, 0), ZA, nblk, nt, 0);              \
+                    break;                                                                                    \
+                case Z_RHS:                                                                                   \
+                    if (a.g.disc) COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_RHS, 1), ZA, nblk, nt, 0);    \
+                    else COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_RHS, 0), ZA, nblk, nt, 0);             \
+                    break;                                                                                    \
+                case Z_PROJ:                                                                                  \
+                    if (a.g.disc) COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_PROJ, 1), ZA, nblk, nt, 0);   \
+                    else COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_PROJ, 0), ZA, nblk, nt, 0);            \
+                    break;                                                                                    \
+                case Z_INV_CG:                                                                                \
+                    if (a.g.disc) COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_CG, 1), ZA, nblk, nt, 0); \
+                    else COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_CG, 0), ZA, nblk, nt, 0);          \
+                    break;                                                                                    \
+                default:                                                                                      \
+                    if (a.g.disc) COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_PLAIN, 1), ZA, nblk, nt, 0); \
+                    else COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_PLAIN, 0), ZA, nblk, nt, 0);       \
+                    break;                                                                                    \
             }                                                                                                 \
             return hipGetLastError();                                                                         \
         }                                                                                                     \
@@ -2040,12 +2072,22 @@ hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb, co
     COMBO_FFT2_CONFIGS(COMBO_Z_CASE)
 #undef COMBO_Z_CASE
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n3 + (size_t)a.g.n3 * a.TX);
+    if (a.g.disc) {
+        switch (mode) {
+            case Z_CG: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_CG, 1), ZA, nblk, kBlock, lds); break;
+            case Z_RHS: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_RHS, 1), ZA, nblk, kBlock, lds); break;
+            case Z_PROJ: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_PROJ, 1), ZA, nblk, kBlock, lds); break;
+            case Z_INV_CG: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_CG, 1), ZA, nblk, kBlock, lds); break;
+            default: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_PLAIN, 1), ZA, nblk, kBlock, lds); break;
+        }
+        return hipGetLastError();
+    }
     switch (mode) {
-        case Z_CG: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_CG), ZA, nblk, kBlock, lds); break;
-        case Z_RHS: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_RHS), ZA, nblk, kBlock, lds); break;
-        case Z_PROJ: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_PROJ), ZA, nblk, kBlock, lds); break;
-        case Z_INV_CG: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_CG), ZA, nblk, kBlock, lds); break;
-        default: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_PLAIN), ZA, nblk, kBlock, lds); break;
+        case Z_CG: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_CG, 0), ZA, nblk, kBlock, lds); break;
+        case Z_RHS: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_RHS, 0), ZA, nblk, kBlock, lds); break;
+        case Z_PROJ: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_PROJ, 0), ZA, nblk, kBlock, lds); break;
+        case Z_INV_CG: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_CG, 0), ZA, nblk, kBlock, lds); break;
+        default: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_PLAIN, 0), ZA, nblk, kBlock, lds); break;
     }
     return hipGetLastError();
 }
