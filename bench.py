@@ -132,8 +132,9 @@ def image_bench(combo, synth, ms, steps):
     avg1, avg2 = ms1 / n1, ms2 / n2
     # pass 1: the image once, phase (1 B) and c (8 B) of every boxel
     b1 = img_bytes + nb * 9
-    # pass 2: phase (1 B) in and N (24 B) out for every boxel, the 4^3 fine voxels of each composite once
-    b2 = nb * 25 + ncomp * 64
+    # pass 2: phase (1 B) in and N (24 B) out for every boxel; per composite its 4^3 fine voxels once,
+    # the list entry (written, read twice) and its 13 FP64 moments (written and read)
+    b2 = nb * 25 + ncomp * (64 + 12 + 2 * 104)
     res = {"workload": "1024^3 image of spheres_256 -> 256^3 boxels (4^3 fine voxels each), Laplacian normals",
            "composites": ncomp, "phase_and_c_equal_generator": exact,
            "ms_per_call": el * 1e3,
@@ -142,9 +143,10 @@ def image_bench(combo, synth, ms, steps):
                        "boxel_normals": {"avg_us": round(avg2 * 1e3, 2), "bytes_per_launch": b2,
                                          "GBps": round(b2 / (avg2 * 1e-3) / 1e9, 1)}},
            "image_GB_per_s": round(img_bytes / el / 1e9, 1)}
-    res["roofline"] = {"bound": "hbm", "kernel": "boxel_count", "achieved": res["kernels"]["boxel_count"]["GBps"],
+    dom = max(("boxel_count", "boxel_normals"), key=lambda k: res["kernels"][k]["avg_us"])
+    res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": res["kernels"][dom]["GBps"],
                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(res["kernels"]["boxel_count"]["GBps"] / HBM_PEAK_GBS, 4)}
+                       "frac": round(res["kernels"][dom]["GBps"] / HBM_PEAK_GBS, 4)}
     log("image -> boxels: %.3f ms per call (count %.1f us, normals %.1f us), composites %d, exact %s"
         % (el * 1e3, avg1 * 1e3, avg2 * 1e3, ncomp, exact))
     return res

@@ -21,12 +21,17 @@ struct BoxelArgs {
     uint8_t* phase;             // [nb] out
     double* c;                  // [nb] out
     double* N;                  // [3][nb] out
-    int* counter;               // [2] scratch, zero before pass 1: [1] becomes nonzero if a value is not 0/1
+    int* counter;               // [2] scratch, zero before pass 1: [0] composites (pass 2a), [1] nonzero if a
+                                // value is not 0/1
 };
 
 // Pass 1, one thread per boxel: volume fraction and phase.
 hipError_t launch_boxel_count(const BoxelArgs& a, hipStream_t s);
-// Pass 2, one wave per 64 boxels, 16 lanes per composite boxel: interface weights, moments, normal.
-hipError_t launch_boxel_normals(const BoxelArgs& a, hipStream_t s);
+// Pass 2a: N = 0 for pure boxels, the ordered list of composite boxels (blockcnt: boxel_blocks(nb)
+// ints, list: nb ints; the count goes to counter[0]).
+int boxel_blocks(long long nb);
+hipError_t launch_boxel_list(const BoxelArgs& a, int* blockcnt, int* list, hipStream_t s);
+// Pass 2b: moments (16 lanes per list entry, mom: 13 doubles per entry) and normals of the ncomp entries.
+hipError_t launch_boxel_normals(const BoxelArgs& a, const int* list, double* mom, int ncomp, hipStream_t s);
 
 }  // namespace combo

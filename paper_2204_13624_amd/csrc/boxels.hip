@@ -13,10 +13,12 @@
 //     interface, i.e. the centred moment sum w xi xi^T - (sum w xi)(sum w xi)^T / sum w
 //     scaled by h_d h_e / 4; N = eigenvector of its smallest eigenvalue (cyclic
 //     Jacobi in FP64), flipped unless N~ . N > 0 (eq. normal:flip).
-// Pass 1 (one thread per boxel) streams the image once with dword loads and
-// popcounts and writes c and phase; pass 2 (one wave per 64 boxels) writes N = 0
-// for pure boxels and revisits the composite ones, four at a time with 16 lanes
-// each, with their one-voxel periodic halo.
+// Pass 1 (one or four boxels per thread) streams the image once with dword or
+// 16-byte loads and popcounts and writes c and phase.  Pass 2 compacts the
+// composite boxels into an ordered list (block counts, one-workgroup scan, ordered
+// write; N = 0 for the pure ones), then reduces the moments of each list entry
+// with 16 lanes over its fine voxels and one-voxel periodic halo, and solves each
+// entry's eigenproblem in a thread of its own.
 #include <hip/hip_runtime.h>
 
 #include "boxels.h"
@@ -26,6 +28,7 @@ namespace combo {
 namespace {
 
 constexpr int kTeam = 16;
+constexpr int kPer = 4;    // fine voxels per lane and load round in pass 2
 
 __global__ void __launch_bounds__(256) k_boxel_count(BoxelArgs a) {
     const long long nb = (long long)a.n1 * a.n2 * a.n3;
@@ -114,7 +117,8 @@ __device__ void smallest_eigvec(double A[3][3], double v[3]) {
         const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
         const double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
         if (!(off > 1e-32 * dia)) break;
-        for (int pq = 0; pq < 3; ++pq) {
+#pragma unroll
+        for (int pq = 0; pq < 3; ++pq) {   // unrolled: p and q are constants, A and Q stay in registers
             const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
             const double apq = A[p][q];
             if (!(fabs(apq) > 1e-17 * (fabs(A[p][p]) + fabs(A[q][q])))) continue;
@@ -122,16 +126,19 @@ __device__ void smallest_eigvec(double A[3][3], double v[3]) {
             const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
             // A <- J^T A J with J the rotation in the (p, q) plane
+#pragma unroll
             for (int m = 0; m < 3; ++m) {
                 const double amp = A[m][p], amq = A[m][q];
                 A[m][p] = c * amp - s * amq;
                 A[m][q] = s * amp + c * amq;
             }
+#pragma unroll
             for (int m = 0; m < 3; ++m) {
                 const double apm = A[p][m], aqm = A[q][m];
                 A[p][m] = c * apm - s * aqm;
                 A[q][m] = s * apm + c * aqm;
             }
+#pragma unroll
             for (int m = 0; m < 3; ++m) {
                 const double qmp = Q[m][p], qmq = Q[m][q];
                 Q[m][p] = c * qmp - s * qmq;
@@ -139,11 +146,14 @@ __device__ void smallest_eigvec(double A[3][3], double v[3]) {
             }
         }
     }
-    int imin = 0;
-    if (A[1][1] < A[imin][imin]) imin = 1;
-    if (A[2][2] < A[imin][imin]) imin = 2;
-    const double nv = sqrt(Q[0][imin] * Q[0][imin] + Q[1][imin] * Q[1][imin] + Q[2][imin] * Q[2][imin]);
-    for (int m = 0; m < 3; ++m) v[m] = Q[m][imin] / nv;
+    const bool m1 = A[1][1] < A[0][0];
+    const double dmin01 = m1 ? A[1][1] : A[0][0];
+    const bool m2 = A[2][2] < dmin01;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) v[m] = m2 ? Q[m][2] : (m1 ? Q[m][1] : Q[m][0]);
+    const double nv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) v[m] /= nv;
 }
 
 template <typename X>
@@ -153,88 +163,170 @@ __device__ __forceinline__ X team_sum(X v) {
     return v;
 }
 
-// one wave per 64 consecutive boxels: pure boxels get N = 0; 16-lane teams reduce
-// the moments of the composite ones, four at a time, into the wave's LDS slots,
-// then every composite lane solves its own 3x3 eigenproblem
-constexpr int kMom = 13;   // sw, sw xi (3), sw xi xi^T (6), sum_{chi=1} xi (3)
+// Pass 2 works on a dense list of the composite boxels so that no lane idles:
+//   k_boxel_blockcount: per block of kCompact boxels, the number of composites (and N = 0 for pure boxels);
+//   k_boxel_scan:       one workgroup, exclusive prefix of the block counts and the total;
+//   k_boxel_compact:    the composites of each block, in ascending order, into list[];
+//   k_boxel_moments:    16-lane teams per list entry: interface weights and moments -> mom[];
+//   k_boxel_eigen:      one thread per list entry: the normal from its moments.
+constexpr int kCompact = 1024;   // boxels per compaction block (256 threads x 4)
+constexpr int kMom = 13;         // sw, sw xi (3), sw xi xi^T (6), sum_{chi=1} xi (3)
 
-__global__ void __launch_bounds__(256) k_boxel_normals(BoxelArgs a) {
-    __shared__ double mom[256][kMom];
-    const int lane = threadIdx.x & 63;
-    const int wbase = threadIdx.x - lane;
+__global__ void __launch_bounds__(256) k_boxel_blockcount(BoxelArgs a, int* blockcnt) {
+    __shared__ int red[4];
     const long long nb = (long long)a.n1 * a.n2 * a.n3;
-    const long long b0 = (long long)blockIdx.x * blockDim.x + wbase;
-    const long long bl = b0 + lane;
-    const int ph = (bl < nb) ? a.phase[bl] : 0;
-    unsigned long long mask = __ballot(ph == 2);
-    if (bl < nb && ph != 2) {
-        a.N[bl] = 0.0;
-        a.N[nb + bl] = 0.0;
-        a.N[2 * nb + bl] = 0.0;
+    int cnt = 0;
+    for (int q = 0; q < 4; ++q) {
+        const long long b = (long long)blockIdx.x * kCompact + q * 256 + threadIdx.x;
+        if (b >= nb) continue;
+        if (a.phase[b] == 2) {
+            ++cnt;
+        } else {
+            a.N[b] = 0.0;
+            a.N[nb + b] = 0.0;
+            a.N[2 * nb + b] = 0.0;
+        }
     }
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) blockcnt[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// exclusive prefix of nblk counts in place; total to counter[0]
+__global__ void __launch_bounds__(1024) k_boxel_scan(int* blockcnt, int nblk, int* counter) {
+    __shared__ int part[1024];
+    const int per = (nblk + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = min(lo + per, nblk);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += blockcnt[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {   // Hillis-Steele inclusive scan of the 1024 partial sums
+        const int v = (threadIdx.x >= off) ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = part[threadIdx.x] - s;             // exclusive start of this thread's range
+    for (int i = lo; i < hi; ++i) {
+        const int c = blockcnt[i];
+        blockcnt[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == 1023) counter[0] = part[1023];
+}
+
+__global__ void __launch_bounds__(256) k_boxel_compact(BoxelArgs a, const int* blockoff, int* list) {
+    __shared__ int wsum[4][4];
+    const long long nb = (long long)a.n1 * a.n2 * a.n3;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    unsigned long long masks[4];
+    for (int q = 0; q < 4; ++q) {
+        const long long b = (long long)blockIdx.x * kCompact + q * 256 + threadIdx.x;
+        masks[q] = __ballot(b < nb && a.phase[b] == 2);
+        if (lane == 0) wsum[q][w] = __popcll(masks[q]);
+    }
+    __syncthreads();
+    int base = blockoff[blockIdx.x];
+    for (int q = 0; q < 4; ++q) {
+        int before = 0;
+        for (int ww = 0; ww < w; ++ww) before += wsum[q][ww];
+        const long long b = (long long)blockIdx.x * kCompact + q * 256 + threadIdx.x;
+        if ((masks[q] >> lane) & 1ull) list[base + before + __popcll(masks[q] & below)] = (int)b;
+        base += wsum[q][0] + wsum[q][1] + wsum[q][2] + wsum[q][3];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_boxel_moments(BoxelArgs a, const int* list, double* mom, long long nteams) {
+    const int tl = threadIdx.x % kTeam;
+    const long long team = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kTeam;
+    const int ncomp = a.counter[0];
     const int s1 = a.s1, s2 = a.s2, s3 = a.s3;
-    const long long V = (long long)s1 * s2 * s3;
-    const int team = lane / kTeam;
-    const int tl = lane % kTeam;
-    while (mask) {
-        unsigned long long m = mask;
-        for (int q = 0; q < team && m; ++q) m &= m - 1;
-        for (int q = 0; q < 64 / kTeam && mask; ++q) mask &= mask - 1;
-        if (!m) continue;   // uniform over the team
-        const int bit = __builtin_ctzll(m);
-        const long long b = b0 + bit;
+    const int V32 = s1 * s2 * s3;
+    for (long long idx = team; idx < ncomp; idx += nteams) {   // uniform over the team
+        const long long b = list[idx];
         const int i = (int)(b % a.n1);
         const long long tt = b / a.n1;
         const int j = (int)(tt % a.n2), k = (int)(tt / a.n2);
         double acc[kMom];
 #pragma unroll
         for (int q = 0; q < kMom; ++q) acc[q] = 0.0;
-        const int V32 = (int)V;
-        for (int t = tl; t < V32; t += kTeam) {
-            const int u = t / s1;
-            const int x = t - u * s1;
-            const int z = u / s2;
-            const int y = u - z * s2;
-            const long long X = (long long)i * s1 + x, Y = (long long)j * s2 + y, Z = (long long)k * s3 + z;
-            const uint8_t* plane = a.chi + Z * a.N2 * a.N1;
-            const uint8_t* row = plane + Y * a.N1;
-            const int c0 = row[X];
-            const int xm = row[wrap(X - 1, a.N1)], xp = row[wrap(X + 1, a.N1)];
-            const int ym = plane[(long long)wrap(Y - 1, a.N2) * a.N1 + X];
-            const int yp = plane[(long long)wrap(Y + 1, a.N2) * a.N1 + X];
-            const int zm = a.chi[((long long)wrap(Z - 1, a.N3) * a.N2 + Y) * a.N1 + X];
-            const int zp = a.chi[((long long)wrap(Z + 1, a.N3) * a.N2 + Y) * a.N1 + X];
-            const int a1 = abs(xm + xp - 2 * c0), a2 = abs(ym + yp - 2 * c0), a3 = abs(zm + zp - 2 * c0);
-            const int xi0 = 2 * x + 1 - s1, xi1 = 2 * y + 1 - s2, xi2 = 2 * z + 1 - s3;
-            if (c0) {
-                acc[10] += xi0;
-                acc[11] += xi1;
-                acc[12] += xi2;
+        // kPer voxels per lane and round: all 7 kPer byte loads of a round are issued before
+        // any is used, so a round costs one memory latency
+        for (int t0 = tl; t0 < V32; t0 += kTeam * kPer) {
+            int cv[kPer][7];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int t = t0 + u * kTeam;
+                const bool ok = t < V32;
+                const int tt2 = ok ? t : 0;
+                const int uu = tt2 / s1;
+                const int x = tt2 - uu * s1;
+                const int z = uu / s2;
+                const int y = uu - z * s2;
+                const long long X = (long long)i * s1 + x, Y = (long long)j * s2 + y, Z = (long long)k * s3 + z;
+                const uint8_t* plane = a.chi + Z * a.N2 * a.N1;
+                const uint8_t* row = plane + Y * a.N1;
+                cv[u][0] = ok ? row[X] : 0;
+                cv[u][1] = ok ? row[wrap(X - 1, a.N1)] : 0;
+                cv[u][2] = ok ? row[wrap(X + 1, a.N1)] : 0;
+                cv[u][3] = ok ? plane[(long long)wrap(Y - 1, a.N2) * a.N1 + X] : 0;
+                cv[u][4] = ok ? plane[(long long)wrap(Y + 1, a.N2) * a.N1 + X] : 0;
+                cv[u][5] = ok ? a.chi[((long long)wrap(Z - 1, a.N3) * a.N2 + Y) * a.N1 + X] : 0;
+                cv[u][6] = ok ? a.chi[((long long)wrap(Z + 1, a.N3) * a.N2 + Y) * a.N1 + X] : 0;
             }
-            if (a1 | a2 | a3) {
-                const double w = a.r[0] * a1 + a.r[1] * a2 + a.r[2] * a3;
-                const double wx = w * xi0, wy = w * xi1, wz = w * xi2;
-                acc[0] += w;
-                acc[1] += wx;
-                acc[2] += wy;
-                acc[3] += wz;
-                acc[4] += wx * xi0;
-                acc[5] += wx * xi1;
-                acc[6] += wx * xi2;
-                acc[7] += wy * xi1;
-                acc[8] += wy * xi2;
-                acc[9] += wz * xi2;
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int t = t0 + u * kTeam;
+                if (t >= V32) continue;
+                const int uu = t / s1;
+                const int x = t - uu * s1;
+                const int z = uu / s2;
+                const int y = uu - z * s2;
+                const int c0 = cv[u][0];
+                const int a1 = abs(cv[u][1] + cv[u][2] - 2 * c0), a2 = abs(cv[u][3] + cv[u][4] - 2 * c0),
+                          a3 = abs(cv[u][5] + cv[u][6] - 2 * c0);
+                const int xi0 = 2 * x + 1 - s1, xi1 = 2 * y + 1 - s2, xi2 = 2 * z + 1 - s3;
+                if (c0) {
+                    acc[10] += xi0;
+                    acc[11] += xi1;
+                    acc[12] += xi2;
+                }
+                if (a1 | a2 | a3) {
+                    const double w = a.r[0] * a1 + a.r[1] * a2 + a.r[2] * a3;
+                    const double wx = w * xi0, wy = w * xi1, wz = w * xi2;
+                    acc[0] += w;
+                    acc[1] += wx;
+                    acc[2] += wy;
+                    acc[3] += wz;
+                    acc[4] += wx * xi0;
+                    acc[5] += wx * xi1;
+                    acc[6] += wx * xi2;
+                    acc[7] += wy * xi1;
+                    acc[8] += wy * xi2;
+                    acc[9] += wz * xi2;
+                }
             }
         }
 #pragma unroll
         for (int q = 0; q < kMom; ++q) acc[q] = team_sum(acc[q]);
-        if (tl == 0)
+        // lane q of the team stores moment q
 #pragma unroll
-            for (int q = 0; q < kMom; ++q) mom[wbase + bit][q] = acc[q];
+        for (int q = 0; q < kMom; ++q)
+            if (tl == q) mom[idx * kMom + q] = acc[q];
     }
-    __syncthreads();
-    if (ph != 2) return;
-    const double* mm = mom[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256) k_boxel_eigen(BoxelArgs a, const int* list, const double* mom) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.counter[0]) return;
+    const long long nb = (long long)a.n1 * a.n2 * a.n3;
+    const long long b = list[idx];
+    double mm[kMom];
+#pragma unroll
+    for (int q = 0; q < kMom; ++q) mm[q] = mom[idx * kMom + q];
     // sum_{chi=1} xi holds integers (exact in double); N~ ~ -h (.) that sum
     const double nt[3] = {-a.h[0] * mm[10], -a.h[1] * mm[11], -a.h[2] * mm[12]};
     double out[3];
@@ -251,7 +343,9 @@ __global__ void __launch_bounds__(256) k_boxel_normals(BoxelArgs a) {
         const double sx[3] = {mm[1], mm[2], mm[3]};
         const double S[3][3] = {{mm[4], mm[5], mm[6]}, {mm[5], mm[7], mm[8]}, {mm[6], mm[8], mm[9]}};
         double M[3][3];
+#pragma unroll
         for (int d = 0; d < 3; ++d)
+#pragma unroll
             for (int e = 0; e < 3; ++e) M[d][e] = 0.25 * a.h[d] * a.h[e] * (S[d][e] - sx[d] * sx[e] / sw);
         double v[3];
         smallest_eigvec(M, v);
@@ -259,9 +353,9 @@ __global__ void __launch_bounds__(256) k_boxel_normals(BoxelArgs a) {
         const double sg = dot > 0 ? 1.0 : -1.0;
         for (int q = 0; q < 3; ++q) out[q] = sg * v[q];
     }
-    a.N[bl] = out[0];
-    a.N[nb + bl] = out[1];
-    a.N[2 * nb + bl] = out[2];
+    a.N[b] = out[0];
+    a.N[nb + b] = out[1];
+    a.N[2 * nb + b] = out[2];
 }
 
 }  // namespace
@@ -278,10 +372,24 @@ hipError_t launch_boxel_count(const BoxelArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_boxel_normals(const BoxelArgs& a, hipStream_t s) {
+int boxel_blocks(long long nb) { return (int)((nb + kCompact - 1) / kCompact); }
+
+hipError_t launch_boxel_list(const BoxelArgs& a, int* blockcnt, int* list, hipStream_t s) {
     const long long nb = (long long)a.n1 * a.n2 * a.n3;
-    const unsigned blocks = (unsigned)((nb + 255) / 256);
-    hipLaunchKernelGGL(k_boxel_normals, dim3(blocks), dim3(256), 0, s, a);
+    const int nblk = boxel_blocks(nb);
+    hipLaunchKernelGGL(k_boxel_blockcount, dim3(nblk), dim3(256), 0, s, a, blockcnt);
+    hipLaunchKernelGGL(k_boxel_scan, dim3(1), dim3(1024), 0, s, blockcnt, nblk, a.counter);
+    hipLaunchKernelGGL(k_boxel_compact, dim3(nblk), dim3(256), 0, s, a, (const int*)blockcnt, list);
+    return hipGetLastError();
+}
+
+hipError_t launch_boxel_normals(const BoxelArgs& a, const int* list, double* mom, int ncomp, hipStream_t s) {
+    if (ncomp <= 0) return hipSuccess;
+    const long long blocks = std::min<long long>(((long long)ncomp * kTeam + 255) / 256, 65536);
+    const long long nteams = blocks * 256 / kTeam;
+    hipLaunchKernelGGL(k_boxel_moments, dim3((unsigned)blocks), dim3(256), 0, s, a, list, mom, nteams);
+    hipLaunchKernelGGL(k_boxel_eigen, dim3((unsigned)((ncomp + 255) / 256)), dim3(256), 0, s, a, list,
+                       (const double*)mom);
     return hipGetLastError();
 }
 

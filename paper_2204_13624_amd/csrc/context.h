@@ -85,6 +85,7 @@ struct combo_ctx {
     combo::AxisPlan plan[3]{};
     combo::DevBuf tw32[3], tw64[3];
     combo::DevBuf ftab;                   // gradient factor table of the rotated scheme
+    combo::DevBuf bx_scratch, bx_mom;     // image -> boxels: counters, block offsets, list; moments
 
     // materials and options
     bool has_mats = false;

@@ -1868,7 +1868,8 @@ int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, in
     HIP_OR_FAIL(hipSetDevice(ctx->device));
     const long long nb = g.n;
     const size_t img_bytes = (size_t)(N1 * N2 * N3);
-    DevBuf dchi, dphase, dc, dN, scratch;
+    DevBuf dchi, dphase, dc, dN;
+    DevBuf& scratch = ctx->bx_scratch;   // kept by the context: repeated calls allocate nothing new
     const uint8_t* chi_d = chi;
     uint8_t* phase_d = phase;
     double* c_d = c;
@@ -1884,7 +1885,7 @@ int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, in
         c_d = static_cast<double*>(dc.p);
         N_d = static_cast<double*>(dN.p);
     }
-    HIP_OR_FAIL(scratch.ensure(sizeof(int) * 2));
+    HIP_OR_FAIL(scratch.ensure(sizeof(int) * (2 + (size_t)boxel_blocks(nb) + (size_t)nb)));
     BoxelArgs a{};
     a.chi = chi_d;
     a.N1 = N1;
@@ -1915,12 +1916,18 @@ int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, in
         ProfScope ps(ctx, COMBO_K_BOXEL_COUNT);
         HIP_OR_FAIL(launch_boxel_count(a, ctx->stream));
     }
+    int* blockcnt = a.counter + 2;
+    int* list = blockcnt + boxel_blocks(nb);
+    int hcnt[2] = {0, 0};
+    DevBuf& mom = ctx->bx_mom;
     {
         ProfScope ps(ctx, COMBO_K_BOXEL_NORMALS);
-        HIP_OR_FAIL(launch_boxel_normals(a, ctx->stream));
+        HIP_OR_FAIL(launch_boxel_list(a, blockcnt, list, ctx->stream));
+        HIP_OR_FAIL(hipMemcpyAsync(hcnt, a.counter, sizeof(hcnt), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+        HIP_OR_FAIL(mom.ensure(sizeof(double) * 13 * (size_t)std::max(hcnt[0], 1)));
+        HIP_OR_FAIL(launch_boxel_normals(a, list, static_cast<double*>(mom.p), hcnt[0], ctx->stream));
     }
-    int hcnt[2] = {0, 0};
-    HIP_OR_FAIL(hipMemcpyAsync(hcnt, a.counter, sizeof(hcnt), hipMemcpyDeviceToHost, ctx->stream));
     if (mem_kind == COMBO_MEM_HOST) {
         HIP_OR_FAIL(hipMemcpyAsync(phase, phase_d, (size_t)nb, hipMemcpyDeviceToHost, ctx->stream));
         HIP_OR_FAIL(hipMemcpyAsync(c, c_d, sizeof(double) * nb, hipMemcpyDeviceToHost, ctx->stream));
