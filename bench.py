@@ -369,7 +369,7 @@ def main():
                                                    np.abs(r64["Pbar"]).max())
         log("fp64: %.2f s, cg %d" % (out["time_to_solution_s"]["fp64"], r64["stats"]["cg_iters_total"]))
     if not args.no_willot:
-        # the same workload under Willot's rotated scheme (generic FFT passes)
+        # the same workload under Willot's rotated scheme
         combo.combo_set_discretization(ctx, combo.COMBO_DISC_WILLOT)
         combo.combo_set_materials(ctx, lc.mats)
         combo.combo_set_microstructure(ctx, torch.from_numpy(ms.phase).to(dev), torch.from_numpy(ms.c).to(dev),
@@ -383,7 +383,7 @@ def main():
         el = time.perf_counter() - t1
         pw = combo.combo_profile_all(ctx)
         combo.combo_profile_enable(ctx, False)
-        out["willot"] = {"discretization": "rotated (HEX8R) scheme, generic FFT passes, mixed",
+        out["willot"] = {"discretization": "rotated (HEX8R) scheme, two-stage FFT passes, mixed",
                          "time_to_solution_s": el, "newton_iters": rw["stats"]["newton_iters"],
                          "cg_iters": rw["stats"]["cg_iters_total"],
                          "voxel_cg_iters_per_s": n * rw["stats"]["cg_iters_total"] / el,

@@ -460,7 +460,7 @@ struct XLdsShape {
 
 constexpr int cmax3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
 
-template <typename T, int MODE, int P, int Q, int RR>
+template <typename T, int MODE, int P, int Q, int RR, int DISC>
 __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     using S = XLdsShape<P, Q, RR>;
@@ -474,7 +474,8 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
     T* fld = reinterpret_cast<T*>(buf);   // real rows [9][R][L] and a sink row block
     const int tid = threadIdx.x;
     static_assert(L % 2 == 0, "two-stage x pass rows have even length");
-    constexpr int nh = L / 2;   // stored x frequencies (the Nyquist bin is not stored)
+    // stored x frequencies: the Nyquist bin is dropped (Moulinec-Suquet) or kept (rotated scheme)
+    constexpr int nh = DISC ? L / 2 + 1 : L / 2;
     const long long nspec = a.g.nspec;
     const long long nrows = (long long)a.g.n2 * a.g.n3;
     const long long row0 = (long long)tile_ * R;
@@ -504,7 +505,7 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
 #pragma unroll
         for (int j2 = 0; j2 < Q; ++j2) {
             const int k = j + P * j2;
-            const int kk = k >= nh ? L - k : k;
+            const int kk = k > L / 2 ? L - k : (k == L / 2 && !DISC ? 0 : k);
             const int kc = kk < nh ? kk : 0;
             ha[j2] = pa[kc];
             hb[j2] = pb[kc];
@@ -513,15 +514,22 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
 #pragma unroll
         for (int j2 = 0; j2 < Q; ++j2) {
             const int k = j + P * j2;
-            const bool conj = k >= nh;
+            const bool conj = k > L / 2;
             const int kk = conj ? L - k : k;
             const T m = (live && kk < nh) ? T(1) : T(0);
-            const T x1 = xs1 * T(kk);
-            const T ma = sa ? m * x1 : m;
-            const T mb = sb ? mb0 * m * x1 : mb0 * m;
+            T ma, mb;
+            if constexpr (DISC) {
+                const T d1 = T(fac_d1(a.g, kk)), a1 = T(fac_a1(a.g, kk));
+                ma = m * (sa ? d1 : a1);
+                mb = mb0 * m * (sb ? d1 : a1);
+            } else {
+                const T x1 = xs1 * T(kk);
+                ma = sa ? m * x1 : m;
+                mb = sb ? mb0 * m * x1 : mb0 * m;
+            }
             const C A = cscale(ha[j2], ma), B = cscale(hb[j2], mb);
             const C zc = conj ? mk<T>(A.x + B.y, B.x - A.y) : mk<T>(A.x - B.y, A.y + B.x);
-            x[j2] = k == 0 ? mk<T>(A.x, B.x) : zc;
+            x[j2] = (k == 0 || 2 * k == L) ? mk<T>(A.x, B.x) : zc;   // self-conjugate bins (L/2: zero unless stored)
         }
         RegDFT<Q, +1, C>::run(x);
 #pragma unroll
@@ -629,25 +637,31 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
         C ha = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
         C hb = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
         const int c1 = 2 * ss, c2 = 2 * ss + 1;
-        const T x1 = xs1 * T(k);
-        if (xi1_comp(c1)) ha = cscale(ha, x1);
-        if (xi1_comp(c2)) hb = cscale(hb, x1);
+        if constexpr (DISC) {
+            const T d1 = T(fac_d1(a.g, k)), a1 = T(fac_a1(a.g, k));
+            ha = cscale(ha, xi1_comp(c1) ? d1 : a1);
+            hb = cscale(hb, xi1_comp(c2) ? d1 : a1);
+        } else {
+            const T x1 = xs1 * T(k);
+            if (xi1_comp(c1)) ha = cscale(ha, x1);
+            if (xi1_comp(c2)) hb = cscale(hb, x1);
+        }
         const long long off = rw * nh + k;
         a.out[c1 * nspec + off] = ha;
         if (ss < 4) a.out[c2 * nspec + off] = hb;
     }
 }
 
-template <typename T, int MODE, int P, int Q, int RR>
+template <typename T, int MODE, int P, int Q, int RR, int DISC>
 __global__ void __launch_bounds__((XLdsShape<P, Q, RR>::NTH)) k_xlds(XArgs<T> a) {
-    k_xlds_body<T, MODE, P, Q, RR>(a, blockIdx.x, gridDim.x);
+    k_xlds_body<T, MODE, P, Q, RR, DISC>(a, blockIdx.x, gridDim.x);
 }
 
-template <typename T, int MODE, int P, int Q, int RR>
+template <typename T, int MODE, int P, int Q, int RR, int DISC>
 __global__ void __launch_bounds__((XLdsShape<P, Q, RR>::NTH)) k_xlds_b(const XArgs<T>* __restrict__ as,
                                                                          const TileMap* __restrict__ map) {
     const TileMap e = map[blockIdx.x];
-    k_xlds_body<T, MODE, P, Q, RR>(as[e.rve], e.tile, e.ntiles);
+    k_xlds_body<T, MODE, P, Q, RR, DISC>(as[e.rve], e.tile, e.ntiles);
 }
 
 // row lengths with a two-stage x pass (CG operator, averaged tangent):
@@ -1908,11 +1922,11 @@ int xpass_lds_rows(int n1, int v, bool is_float) {
 
 int blocks_x(const Grid& g, int R, int mode, bool is_float) {
     const long long nrows = (long long)g.n2 * g.n3;
-    if (g.disc) return (int)((nrows + R - 1) / R);
     if (mode == X_CG || mode == X_AVG) {
         const int rows = xpass_lds_rows(g.n1, g.xv, is_float);
         if (rows > 0) return (int)((nrows + rows - 1) / rows);
     }
+    if (g.disc) return (int)((nrows + R - 1) / R);   // the rotated scheme has no wavefront x pass
 #define COMBO_XB_CASE(LL, MM, WW) \
     if (g.n1 == LL) return (int)((nrows + (256 / WW) - 1) / (256 / WW));
     COMBO_XWAVE_CONFIGS(COMBO_XB_CASE)
@@ -1946,7 +1960,7 @@ template <typename T>
 hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const BatchLaunch* b) {
     using XA = XArgs<T>;
     const long long nrows = (long long)a.g.n2 * a.g.n3;
-    if (!a.g.disc && (mode == X_CG || mode == X_AVG)) {
+    if (mode == X_CG || mode == X_AVG) {
         const int vv = xpass_lds_pick(a.g.n1, a.g.xv, std::is_same<T, float>::value);
 #define COMBO_XL_CASE(LL, PP, QQ, RR, VV)                                                                    \
         if constexpr (VV == 0 || std::is_same<T, float>::value) {                                            \
@@ -1954,8 +1968,13 @@ hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const B
                 using SH = XLdsShape<PP, QQ, RR>;                                                            \
                 const int nblk = (int)((nrows + SH::R - 1) / SH::R);                                         \
                 if (nb) *nb = nblk;                                                                          \
-                if (mode == X_CG) COMBO_LAUNCH(k_xlds, (T, X_CG, PP, QQ, RR), XA, nblk, SH::NTH, 0);         \
-                else COMBO_LAUNCH(k_xlds, (T, X_AVG, PP, QQ, RR), XA, nblk, SH::NTH, 0);                     \
+                if (a.g.disc) {                                                                              \
+                    if (mode == X_CG) COMBO_LAUNCH(k_xlds, (T, X_CG, PP, QQ, RR, 1), XA, nblk, SH::NTH, 0);  \
+                    else COMBO_LAUNCH(k_xlds, (T, X_AVG, PP, QQ, RR, 1), XA, nblk, SH::NTH, 0);              \
+                } else {                                                                                     \
+                    if (mode == X_CG) COMBO_LAUNCH(k_xlds, (T, X_CG, PP, QQ, RR, 0), XA, nblk, SH::NTH, 0);  \
+                    else COMBO_LAUNCH(k_xlds, (T, X_AVG, PP, QQ, RR, 0), XA, nblk, SH::NTH, 0);              \
+                }                                                                                            \
                 return hipGetLastError();                                                                    \
             }                                                                                                \
         }

@@ -64,7 +64,11 @@ def test_green_operators_match_oracle(ctx, n, l):
             assert rel(out, ref) <= tol, (which, prec)
 
 
-@pytest.mark.parametrize("n,l", SHAPES[:3])
+# x lengths 32, 48 and 64 run the two-stage x pass (with the x-Nyquist bin); the others the LDS x pass
+CG_SHAPES = SHAPES[:3] + [((32, 6, 4), (1.0, 1.0, 1.0)), ((64, 8, 6), (1.0, 0.5, 0.4)), ((48, 9, 4), (1.0, 1.0, 1.0))]
+
+
+@pytest.mark.parametrize("n,l", CG_SHAPES)
 def test_cg_operator_matches_oracle(ctx, n, l):
     ms = synth.random_composite_field(n, 5, frac_composite=0.3, l=l)
     setup(ctx, ms)
@@ -77,14 +81,17 @@ def test_cg_operator_matches_oracle(ctx, n, l):
     p = ospec.apply_g(rng.normal(size=(3, 3, n[2], n[1], n[0])), n, l, "willot")
     ref = ospec.apply_gamma0(osol.apply_tangent(Av, p, prob.shape), n, l, mu0, kappa0, "willot")
     pc = np.ascontiguousarray(p.reshape(9, n[2], n[1], n[0]))
+    (_, _, _), (nxv, _, _) = combo.combo_get_schedule(ctx)
     for prec, tol in ((combo.COMBO_FP64, 1e-11), (combo.COMBO_MIXED, 3e-6)):
         o = combo.combo_default_options()
         o.precision = prec
         combo.combo_set_options(ctx, o)
         assert combo.combo_eval_law(ctx, F, None, None, None, None) == combo.COMBO_OK
-        q = np.zeros_like(pc)
-        combo.combo_apply_operator(ctx, prec, pc, q)
-        assert rel(q, ref.reshape(pc.shape)) <= tol, prec
+        for xv in range(nxv):
+            combo.combo_set_schedule(ctx, xv, 0, 0)
+            q = np.zeros_like(pc)
+            combo.combo_apply_operator(ctx, prec, pc, q)
+            assert rel(q, ref.reshape(pc.shape)) <= tol, (prec, xv)
 
 
 @pytest.mark.parametrize("n", [(16, 16, 16), (9, 12, 8)])
