@@ -21,6 +21,8 @@ struct BoxelArgs {
     uint8_t* phase;             // [nb] out
     double* c;                  // [nb] out
     double* N;                  // [3][nb] out
+    uint64_t* packed;           // [nb] or null: pass 1 (four-boxel path, s1 = 4, s2 s3 <= 16) stores each
+                                // boxel's fine values as bits x + 4 (y + s2 z) for pass 2
     int* counter;               // [2] scratch, zero before pass 1: [0] composites (pass 2a), [1] nonzero if a
                                 // value is not 0/1
 };

@@ -84,6 +84,9 @@ __global__ void __launch_bounds__(256) k_boxel_count4(BoxelArgs a) {
     const uint8_t* base = a.chi + ((long long)k * a.s3 * a.N2 + (long long)j * a.s2) * a.N1 + (long long)i * 4;
     int cnt[4] = {0, 0, 0, 0};
     unsigned bad = 0;
+    uint64_t pk[4] = {0, 0, 0, 0};
+    // the four 0/1 bytes of a row dword as four bits
+    auto nib = [](uint32_t v) -> uint64_t { return (v & 1u) | ((v >> 7) & 2u) | ((v >> 14) & 4u) | ((v >> 21) & 8u); };
 #pragma unroll 8
     for (int r = 0; r < rows; ++r) {
         const int z = r / a.s2, y = r - z * a.s2;
@@ -93,6 +96,21 @@ __global__ void __launch_bounds__(256) k_boxel_count4(BoxelArgs a) {
         cnt[1] += __popc(v.y);
         cnt[2] += __popc(v.z);
         cnt[3] += __popc(v.w);
+        if (r < 16) {
+            pk[0] |= nib(v.x) << (4 * r);
+            pk[1] |= nib(v.y) << (4 * r);
+            pk[2] |= nib(v.z) << (4 * r);
+            pk[3] |= nib(v.w) << (4 * r);
+        }
+    }
+    if (a.packed) {
+        ulonglong2 p01, p23;
+        p01.x = pk[0];
+        p01.y = pk[1];
+        p23.x = pk[2];
+        p23.y = pk[3];
+        *reinterpret_cast<ulonglong2*>(a.packed + b4) = p01;
+        *reinterpret_cast<ulonglong2*>(a.packed + b4 + 2) = p23;
     }
     if (bad) atomicOr(&a.counter[1], 1);
     double2 c01, c23;
@@ -319,6 +337,77 @@ __global__ void __launch_bounds__(256) k_boxel_moments(BoxelArgs a, const int* l
     }
 }
 
+// moments from the packed boxel words (s1 = 4, s2 s3 <= 16): each lane of a team reads the
+// composite's word and those of its six face neighbours (periodic), then takes kPer voxels
+__device__ __forceinline__ int bitv(uint64_t w, int i) { return (int)((w >> i) & 1ull); }
+
+__global__ void __launch_bounds__(256, 3) k_boxel_moments_packed(BoxelArgs a, const int* list, double* mom,
+                                                              long long nteams) {
+    const int tl = threadIdx.x % kTeam;
+    const long long team = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kTeam;
+    const int ncomp = a.counter[0];
+    const int s2 = a.s2, s3 = a.s3;
+    const int V32 = 4 * s2 * s3;
+    const int n1 = a.n1, n2 = a.n2, n3 = a.n3;
+    for (long long idx = team; idx < ncomp; idx += nteams) {   // uniform over the team
+        const long long b = list[idx];
+        const int i = (int)(b % n1);
+        const long long tt = b / n1;
+        const int j = (int)(tt % n2), k = (int)(tt / n2);
+        const long long rowb = (long long)k * n2 + j;
+        const uint64_t w0 = a.packed[b];
+        const uint64_t wxm = a.packed[rowb * n1 + (i == 0 ? n1 - 1 : i - 1)];
+        const uint64_t wxp = a.packed[rowb * n1 + (i == n1 - 1 ? 0 : i + 1)];
+        const uint64_t wym = a.packed[((long long)k * n2 + (j == 0 ? n2 - 1 : j - 1)) * n1 + i];
+        const uint64_t wyp = a.packed[((long long)k * n2 + (j == n2 - 1 ? 0 : j + 1)) * n1 + i];
+        const uint64_t wzm = a.packed[((long long)(k == 0 ? n3 - 1 : k - 1) * n2 + j) * n1 + i];
+        const uint64_t wzp = a.packed[((long long)(k == n3 - 1 ? 0 : k + 1) * n2 + j) * n1 + i];
+        double acc[kMom];
+#pragma unroll
+        for (int q = 0; q < kMom; ++q) acc[q] = 0.0;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int t = tl + u * kTeam;
+            if (t >= V32) continue;
+            const int x = t & 3, r = t >> 2;
+            const int z = r / s2, y = r - z * s2;
+            const int c0 = bitv(w0, t);
+            const int xm = x > 0 ? bitv(w0, t - 1) : bitv(wxm, t + 3);
+            const int xp = x < 3 ? bitv(w0, t + 1) : bitv(wxp, t - 3);
+            const int ym = y > 0 ? bitv(w0, t - 4) : bitv(wym, t + 4 * (s2 - 1));
+            const int yp = y < s2 - 1 ? bitv(w0, t + 4) : bitv(wyp, t - 4 * (s2 - 1));
+            const int zm = z > 0 ? bitv(w0, t - 4 * s2) : bitv(wzm, t + 4 * s2 * (s3 - 1));
+            const int zp = z < s3 - 1 ? bitv(w0, t + 4 * s2) : bitv(wzp, t - 4 * s2 * (s3 - 1));
+            const int a1 = abs(xm + xp - 2 * c0), a2 = abs(ym + yp - 2 * c0), a3 = abs(zm + zp - 2 * c0);
+            const int xi0 = 2 * x - 3, xi1 = 2 * y + 1 - s2, xi2 = 2 * z + 1 - s3;
+            if (c0) {
+                acc[10] += xi0;
+                acc[11] += xi1;
+                acc[12] += xi2;
+            }
+            if (a1 | a2 | a3) {
+                const double w = a.r[0] * a1 + a.r[1] * a2 + a.r[2] * a3;
+                const double wx = w * xi0, wy = w * xi1, wz = w * xi2;
+                acc[0] += w;
+                acc[1] += wx;
+                acc[2] += wy;
+                acc[3] += wz;
+                acc[4] += wx * xi0;
+                acc[5] += wx * xi1;
+                acc[6] += wx * xi2;
+                acc[7] += wy * xi1;
+                acc[8] += wy * xi2;
+                acc[9] += wz * xi2;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kMom; ++q) acc[q] = team_sum(acc[q]);
+#pragma unroll
+        for (int q = 0; q < kMom; ++q)
+            if (tl == q) mom[idx * kMom + q] = acc[q];
+    }
+}
+
 __global__ void __launch_bounds__(256) k_boxel_eigen(BoxelArgs a, const int* list, const double* mom) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.counter[0]) return;
@@ -387,7 +476,10 @@ hipError_t launch_boxel_normals(const BoxelArgs& a, const int* list, double* mom
     if (ncomp <= 0) return hipSuccess;
     const long long blocks = std::min<long long>(((long long)ncomp * kTeam + 255) / 256, 65536);
     const long long nteams = blocks * 256 / kTeam;
-    hipLaunchKernelGGL(k_boxel_moments, dim3((unsigned)blocks), dim3(256), 0, s, a, list, mom, nteams);
+    if (a.packed)
+        hipLaunchKernelGGL(k_boxel_moments_packed, dim3((unsigned)blocks), dim3(256), 0, s, a, list, mom, nteams);
+    else
+        hipLaunchKernelGGL(k_boxel_moments, dim3((unsigned)blocks), dim3(256), 0, s, a, list, mom, nteams);
     hipLaunchKernelGGL(k_boxel_eigen, dim3((unsigned)((ncomp + 255) / 256)), dim3(256), 0, s, a, list,
                        (const double*)mom);
     return hipGetLastError();

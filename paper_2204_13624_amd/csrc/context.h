@@ -86,6 +86,7 @@ struct combo_ctx {
     combo::DevBuf tw32[3], tw64[3];
     combo::DevBuf ftab;                   // gradient factor table of the rotated scheme
     combo::DevBuf bx_scratch, bx_mom;     // image -> boxels: counters, block offsets, list; moments
+    combo::DevBuf bx_packed;              // image -> boxels: one 64-bit word of fine values per boxel
 
     // materials and options
     bool has_mats = false;

@@ -1910,6 +1910,11 @@ int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, in
     a.phase = phase_d;
     a.c = c_d;
     a.N = N_d;
+    a.packed = nullptr;
+    if (a.vec16 && (long long)s2 * s3 <= 16) {
+        HIP_OR_FAIL(ctx->bx_packed.ensure(sizeof(uint64_t) * (size_t)nb));
+        a.packed = static_cast<uint64_t*>(ctx->bx_packed.p);
+    }
     a.counter = static_cast<int*>(scratch.p);
     HIP_OR_FAIL(hipMemsetAsync(a.counter, 0, 2 * sizeof(int), ctx->stream));
     {

@@ -65,7 +65,8 @@ def check_against_oracle(img, n, s, l, method, phase, c, N, gap_tol=1e-6, ntol=1
 @pytest.mark.parametrize("n,s,l", [((6, 4, 3), (8, 8, 8), (1.0, 1.0, 1.0)),          # dword path
                                    ((9, 6, 4), (5, 6, 3), (1.0, 1.2, 0.6)),          # byte path, boxels
                                    ((4, 8, 6), (12, 4, 8), (0.6, 0.4, 0.6)),         # equiaxed fine voxels
-                                   ((9, 3, 2), (2, 7, 9), (0.9, 1.05, 0.9))])
+                                   ((9, 3, 2), (2, 7, 9), (0.9, 1.05, 0.9)),
+                                   ((8, 6, 4), (4, 3, 5), (1.0, 0.9, 1.0))])          # packed-word path
 @pytest.mark.parametrize("method", [combo.COMBO_NORMALS_LAPLACE, combo.COMBO_NORMALS_BARYCENTRE])
 def test_boxels_match_oracle(ctx, n, s, l, method):
     img = random_image(tuple(a * b for a, b in zip(n, s)), seed=sum(n) + method)
@@ -169,3 +170,26 @@ def test_full_size_image_of_the_sphere_workload(ctx):
             assert np.abs(g - rN[m]).max() <= 1e-10, b
             sep += 1
     assert sep >= 1500
+
+
+def test_degenerate_images(ctx):
+    """Empty and full images (no composites: pass 2 has an empty list), s = 1 (every
+    boxel pure), thin boxels with s1 = 1, and one 32^3 boxel (many load rounds per lane)."""
+    combo.combo_set_grid(ctx, 4, 3, 2, 1.0, 1.0, 1.0)
+    for val in (0, 1):
+        img = np.full((2 * 4, 3 * 4, 4 * 4), val, np.uint8)
+        phase, c, N = combo.combo_image_to_boxels(ctx, img, (4, 4, 4))
+        assert (phase == val).all() and (c == val).all() and (N == 0).all()
+    img = random_image((4, 3, 2), seed=12)
+    phase, c, N = combo.combo_image_to_boxels(ctx, img, (1, 1, 1))
+    assert np.array_equal(phase, img) and np.array_equal(c, img.astype(float)) and (N == 0).all()
+    combo.combo_set_grid(ctx, 16, 4, 3, 1.0, 0.5, 0.6)
+    img = random_image((16, 20, 9), seed=13)
+    phase, c, N = combo.combo_image_to_boxels(ctx, img, (1, 5, 3))
+    check_against_oracle(img, (16, 4, 3), (1, 5, 3), (1.0, 0.5, 0.6), onorm.METHOD_LAPLACE, phase, c, N)
+    combo.combo_set_grid(ctx, 1, 1, 1, 1.0, 1.0, 1.0)
+    img = synth.sphere_image((32, 32, 32), 0.3, center=(0.45, 0.45, 0.45))   # wraps through the faces
+    phase, c, N = combo.combo_image_to_boxels(ctx, img, (32, 32, 32))
+    rp, rc, rN = onorm.detect(img, (32, 32, 32), (1.0, 1.0, 1.0))
+    assert phase[0, 0, 0] == rp[0, 0, 0] == 2 and c[0, 0, 0] == rc[0, 0, 0]
+    assert np.abs(N[:, 0, 0, 0] - rN[:, 0, 0, 0]).max() <= 1e-10
