@@ -177,8 +177,8 @@ int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2,
  *   grad_J -> k_J = (e^{i th_J} - 1)/h_J prod_{m != J} (1 + e^{i th_m})/2,
  *   th_d = 2 pi k_d / n_d.  Only the mean and modes on two or more Nyquist planes
  *   are projected out; an even n1 keeps its x-Nyquist plane.  Runs the same FFT
- *   passes with the rotated factors (combo_autotune keeps the default schedule;
- *   combo_set_schedule applies); not available in batches.
+ *   passes with the rotated factors; combo_autotune tunes and caches its schedules
+ *   separately ("mixed-willot" / "fp64-willot").  Not available in batches.
  * Rebuilds the grid's frequency data like combo_set_grid and therefore resets the
  * microstructure: call after combo_set_grid, before combo_set_microstructure. */
 #define COMBO_DISC_MS 0

@@ -569,8 +569,10 @@ std::string tune_key(const combo_ctx* ctx, int precision) {
         for (char& c : arch)
             if (c == ' ') c = '_';
     }
+    // the rotated scheme has schedules of its own (its passes are separate instances)
     return arch + " " + std::to_string(ctx->g.n1) + " " + std::to_string(ctx->g.n2) + " " +
-           std::to_string(ctx->g.n3) + " " + (precision == COMBO_MIXED ? "mixed" : "fp64");
+           std::to_string(ctx->g.n3) + " " + (precision == COMBO_MIXED ? "mixed" : "fp64") +
+           (ctx->g.disc == COMBO_DISC_WILLOT ? "-willot" : "");
 }
 
 // COMBO_TUNE_CACHE names a text file: one line "arch n1 n2 n3 precision xv yv zv" per tuned grid
@@ -686,7 +688,6 @@ void apply_schedule(combo_ctx* ctx, const Schedule& sc) {
 }
 
 int autotune(combo_ctx* ctx, int precision) {
-    if (ctx->g.disc != COMBO_DISC_MS) return COMBO_OK;   // the rotated scheme has one (generic) schedule
     const std::string key = tune_key(ctx, precision);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -135,6 +135,21 @@ def test_layered_rve_is_exact_on_an_even_grid(ctx):
     assert rel(combo.combo_solve(ctx, FBAR)["Pbar"], ref) <= 1e-7
 
 
+def test_autotuned_schedule_matches_default(ctx):
+    ms = synth.single_sphere((64, 48, 32), radius=0.25)
+    setup(ctx, ms, precision=combo.COMBO_MIXED, tol_newton=1e-8, tol_cg=1e-6)
+    r0 = combo.combo_solve(ctx, FBAR)
+    (_, _, _), counts = combo.combo_get_schedule(ctx)
+    sched = combo.combo_autotune(ctx, combo.COMBO_MIXED)
+    assert all(0 <= v < c for v, c in zip(sched, counts))
+    r1 = combo.combo_solve(ctx, FBAR)
+    assert rel(r1["Pbar"], r0["Pbar"]) <= 1e-6
+    for xv in range(counts[0]):
+        for yv in range(counts[1]):
+            combo.combo_set_schedule(ctx, xv, yv, counts[2] - 1)
+            assert rel(combo.combo_solve(ctx, FBAR)["Pbar"], r0["Pbar"]) <= 1e-6, (xv, yv)
+
+
 def test_discretization_switch_and_errors(ctx):
     ms = synth.single_sphere((8, 8, 8), radius=0.3)
     setup(ctx, ms, tol_newton=1e-10, tol_cg=1e-12)
