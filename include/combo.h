@@ -178,7 +178,7 @@ int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2,
  *   th_d = 2 pi k_d / n_d.  Only the mean and modes on two or more Nyquist planes
  *   are projected out; an even n1 keeps its x-Nyquist plane.  Runs the same FFT
  *   passes with the rotated factors; combo_autotune tunes and caches its schedules
- *   separately ("mixed-willot" / "fp64-willot").  Not available in batches.
+ *   separately ("mixed-willot" / "fp64-willot").  Batches: combo_batch_set_discretization.
  * Rebuilds the grid's frequency data like combo_set_grid and therefore resets the
  * microstructure: call after combo_set_grid, before combo_set_microstructure. */
 #define COMBO_DISC_MS 0
@@ -315,6 +315,9 @@ const char* combo_batch_last_error(const combo_batch* b);
  * the CG iterations of the members in CG run in chunks of that many, captured
  * once as a HIP graph and replayed while the same members stay in CG. */
 int combo_batch_set_options(combo_batch* b, const combo_options* opt);
+/* Discretization (COMBO_DISC_MS or COMBO_DISC_WILLOT, see combo_set_discretization)
+ * of the members added after this call; members of either kind can share a batch. */
+int combo_batch_set_discretization(combo_batch* b, int disc);
 /* Append one RVE: grid and box as combo_set_grid, materials as
  * combo_set_materials, microstructure as combo_set_microstructure (pointers of
  * mem_kind, copied).  *index (may be NULL) receives the member's position.

@@ -106,6 +106,7 @@ _SIGS = {
     "combo_set_materials": (_I, [_P, ctypes.POINTER(combo_material)]),
     "combo_set_microstructure": (_I, [_P, _P, _P, _P, _I]),
     "combo_set_discretization": (_I, [_P, _I]),
+    "combo_batch_set_discretization": (_I, [_P, _I]),
     "combo_get_grid": (_I, [_P] + [ctypes.POINTER(ctypes.c_int)] * 3 + [ctypes.POINTER(ctypes.c_double)] * 3),
     "combo_image_to_boxels": (_I, [_P, _P, _I, _I, _I, _I, _P, _P, _P, _I]),
     "combo_set_microstructure_from_image": (_I, [_P, _P, _I, _I, _I, _I, _I]),
@@ -292,6 +293,12 @@ def combo_image_to_boxels(ctx, chi, s, method=COMBO_NORMALS_LAPLACE, out=None):
 
 def combo_set_discretization(ctx, disc):
     _check(ctx, load_library().combo_set_discretization(ctx, int(disc)))
+
+
+def combo_batch_set_discretization(b, disc):
+    st = load_library().combo_batch_set_discretization(b, int(disc))
+    if st != COMBO_OK:
+        raise ComboError(st, load_library().combo_batch_last_error(b).decode())
 
 
 def combo_get_grid(ctx):

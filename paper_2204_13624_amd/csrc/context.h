@@ -127,6 +127,7 @@ struct combo_batch {
     bool own_stream = false;
     std::string err;
     combo_options opt{};
+    int disc = COMBO_DISC_MS;           // discretization of members added from now on
     std::vector<combo_ctx*> members;
     combo::DevBuf scal;                 // [members] x kScalStride bytes: CGState at 0, sums at kScalSums
     char* hscal = nullptr;              // pinned host copy of scal

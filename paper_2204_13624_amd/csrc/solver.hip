@@ -1035,8 +1035,10 @@ void plan_finalize(LaunchPlan& lp, int mode, const std::vector<FinArgs>& f, hipS
     });
 }
 
-// launch-group key: axis length, schedule variant, tile width or rows
+// launch-group key: axis length, schedule variant and discretization, tile width or rows
 long long key2(long long len, long long tile, int variant = 0) { return (len << 40) | ((long long)variant << 32) | tile; }
+// the discretization selects other kernel instances: members that differ in it never share a launch
+int vkey(const Grid& g, int variant) { return variant + 64 * g.disc; }
 
 enum MemberPhase { PH_INC = 0, PH_RES, PH_CG, PH_STEP, PH_LSRES, PH_DONE, PH_FAIL };
 
@@ -1305,17 +1307,17 @@ void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
             ZArgs<double, T> z = zargs<double, T>(ctx, 1.0, 0.0);
             z.out = ctx->specA.as<double2>();
             za.push_back(z);
-            kz.push_back(key2(ctx->g.n3, z.TX, ctx->g.zv));
+            kz.push_back(key2(ctx->g.n3, z.TX, vkey(ctx->g, ctx->g.zv)));
             nz.push_back(blocks_z(ctx->g, z.TX));
             YArgs<double> y = yargs<double>(ctx, ctx->specA.p, ctx->specB.p, false);
             ya.push_back(y);
-            ky.push_back(key2(ctx->g.n2, y.TX, ctx->g.yv));
+            ky.push_back(key2(ctx->g.n2, y.TX, vkey(ctx->g, ctx->g.yv)));
             ny.push_back(blocks_y(ctx->g, y.TX));
             XArgs<double> x = xargs<double>(ctx);
             x.in = ctx->specB.as<double2>();
             x.real_out = ctx->dF.as<double>();
             xa.push_back(x);
-            kx.push_back(key2(ctx->g.n1, x.R, ctx->g.xv));
+            kx.push_back(key2(ctx->g.n1, x.R, vkey(ctx->g, ctx->g.xv)));
             nx.push_back(blocks_x(ctx->g, x.R, X_INV_REAL, false));
         }
         plan_pass(lp, za, kz, nz, [=](const ZArgs<double, T>& a, const BatchLaunch* bl) {
@@ -1375,16 +1377,16 @@ void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
             x.real_in = ctx->P.as<double>();
             x.out = ctx->specA.as<double2>();
             xa.push_back(x);
-            kx.push_back(key2(ctx->g.n1, x.R, ctx->g.xv));
+            kx.push_back(key2(ctx->g.n1, x.R, vkey(ctx->g, ctx->g.xv)));
             nx.push_back(blocks_x(ctx->g, x.R, X_FWD_REAL, false));
             YArgs<double> y = yargs<double>(ctx, ctx->specA.p, ctx->specB.p, false);
             ya.push_back(y);
-            ky.push_back(key2(ctx->g.n2, y.TX, ctx->g.yv));
+            ky.push_back(key2(ctx->g.n2, y.TX, vkey(ctx->g, ctx->g.yv)));
             ny.push_back(blocks_y(ctx->g, y.TX));
             ZArgs<double, T> z = zargs<double, T>(ctx, m.mu0, m.kappa0);
             z.in = ctx->specB.as<double2>();
             za.push_back(z);
-            kz.push_back(key2(ctx->g.n3, z.TX, ctx->g.zv));
+            kz.push_back(key2(ctx->g.n3, z.TX, vkey(ctx->g, ctx->g.zv)));
             const int nbz = blocks_z(ctx->g, z.TX);
             nz.push_back(nbz);
             ua.push_back(uargs<T>(ctx, m.mu0, m.kappa0));
@@ -1427,19 +1429,19 @@ void plan_cg(combo_batch* B, std::vector<Member>& ms, const std::vector<int>& li
         z.in = ctx->specB.as<cpx<T>>();
         z.out = nullptr;
         zf.push_back(z);
-        kz.push_back(key2(ctx->g.n3, z.TX, ctx->g.zv));
+        kz.push_back(key2(ctx->g.n3, z.TX, vkey(ctx->g, ctx->g.zv)));
         const int nbz = blocks_z(ctx->g, z.TX);
         nz.push_back(nbz);
         YArgs<T> yv = yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true);
         yi.push_back(yv);
         yf.push_back(yv);
-        ky.push_back(key2(ctx->g.n2, yv.TX, ctx->g.yv));
+        ky.push_back(key2(ctx->g.n2, yv.TX, vkey(ctx->g, ctx->g.yv)));
         ny.push_back(blocks_y(ctx->g, yv.TX));
         XArgs<T> x = xargs<T>(ctx);
         x.in = ctx->specB.as<cpx<T>>();
         x.out = ctx->specA.as<cpx<T>>();
         xa.push_back(x);
-        kx.push_back(key2(ctx->g.n1, x.R, ctx->g.xv));
+        kx.push_back(key2(ctx->g.n1, x.R, vkey(ctx->g, ctx->g.xv)));
         nx.push_back(blocks_x(ctx->g, x.R, X_CG, sizeof(T) == 4));
         ua.push_back(uargs<T>(ctx, m.mu0, m.kappa0));
         ku.push_back(0);
@@ -2391,6 +2393,14 @@ int combo_batch_set_options(combo_batch* b, const combo_options* o) {
     return COMBO_OK;
 }
 
+int combo_batch_set_discretization(combo_batch* b, int disc) {
+    if (!b) return COMBO_E_INVAL;
+    if (disc != COMBO_DISC_MS && disc != COMBO_DISC_WILLOT)
+        return bset_err(b, COMBO_E_INVAL, "disc must be COMBO_DISC_MS or COMBO_DISC_WILLOT");
+    b->disc = disc;
+    return COMBO_OK;
+}
+
 int combo_batch_add(combo_batch* b, int n1, int n2, int n3, double l1, double l2, double l3,
                     const combo_material mats[2], const uint8_t* phase, const double* c, const double* N, int mem_kind,
                     int* index) {
@@ -2400,6 +2410,7 @@ int combo_batch_add(combo_batch* b, int n1, int n2, int n3, double l1, double l2
     int st = combo_create(&m, b->device, b->stream);
     if (st) return bset_err(b, st, "member context creation failed");
     st = combo_set_grid(m, n1, n2, n3, l1, l2, l3);
+    if (!st && b->disc != COMBO_DISC_MS) st = combo_set_discretization(m, b->disc);
     if (!st) st = combo_set_materials(m, mats);
     if (!st) st = combo_set_options(m, &b->opt);
     if (!st) st = combo_set_microstructure(m, phase, c, N, mem_kind);

@@ -196,3 +196,30 @@ def test_full_size_sphere_workload(ctx):
     combo.combo_set_options(ctx, o)
     r64 = combo.combo_solve(ctx, Fb)
     assert rel(r["Pbar"], r64["Pbar"]) <= 1e-6
+
+
+def test_batch_mixes_discretizations():
+    """Two rotated-scheme members of different grids and one Moulinec-Suquet member in one
+    batch: each equals its single solve and the oracle of its discretization."""
+    cases = [(synth.single_sphere((16, 16, 16), radius=0.3), "willot"),
+             (synth.random_spheres((24, 16, 12), 3, 0.2, seed=21), "willot"),
+             (synth.single_sphere((16, 12, 8), radius=0.3), "ms")]
+    o = combo.combo_default_options()
+    o.tol_newton = 1e-10
+    o.tol_cg = 1e-12
+    b = combo.combo_batch_create(0)
+    try:
+        combo.combo_batch_set_options(b, o)
+        for i, (ms, disc) in enumerate(cases):
+            combo.combo_batch_set_discretization(b, combo.COMBO_DISC_WILLOT if disc == "willot" else combo.COMBO_DISC_MS)
+            assert combo.combo_batch_add(b, ms.n, ms.l, MATS, ms.phase, ms.c, ms.N) == i
+        with pytest.raises(combo.ComboError):
+            combo.combo_batch_set_discretization(b, 5)
+        res = combo.combo_batch_solve(b, np.stack([FBAR] * 3), n_increments=[1, 1, 1])
+    finally:
+        combo.combo_batch_destroy(b)
+    for i, (ms, disc) in enumerate(cases):
+        assert res["stats"][i]["status"] == combo.COMBO_OK
+        ref = osol.solve(osol.Problem(ms.n, ms.l, ms.phase, ms.c, ms.N, MATS, disc=disc), FBAR,
+                         osol.Options(tol_newton=1e-10, tol_cg=1e-12))
+        assert rel(res["Pbar"][i], ref["Pbar"]) <= 1e-8, i
