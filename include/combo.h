@@ -159,7 +159,11 @@ int combo_check_size(int n);
 
 /* Context ------------------------------------------------------------------ */
 /* Create a context on GPU `device` using `hip_stream` (a hipStream_t; NULL =
- * a stream the context creates and owns).  COMBO_E_HIP if no usable GPU. */
+ * a stream the context creates and owns, non-blocking).  COMBO_E_HIP if no
+ * usable GPU.  Device buffers given to any call are read and written on that
+ * stream: work on other streams that produces them must be complete (or
+ * ordered before the call) when the call is made.  Calls return after their
+ * device outputs are written. */
 int combo_create(combo_ctx** out, int device, void* hip_stream);
 int combo_destroy(combo_ctx* ctx);
 /* Message of the last failed call on ctx; owned by ctx, valid until the next call. */

@@ -187,6 +187,11 @@ def _ptr(x, dtype):
         want = {np.float64: "torch.float64", np.uint8: "torch.uint8", np.int32: "torch.int32"}[dtype]
         if str(x.dtype) != want:
             raise TypeError("expected %s, got %s" % (want, x.dtype))
+        if x.is_cuda:
+            # the library works on its own stream: what torch has queued on its
+            # stream for this tensor (the kernels that produced it) must be done
+            import torch
+            torch.cuda.current_stream(x.device).synchronize()
         return ctypes.c_void_p(x.data_ptr()), (COMBO_MEM_DEVICE if x.is_cuda else COMBO_MEM_HOST)
     if not isinstance(x, np.ndarray) or x.dtype != dtype or not x.flags.c_contiguous:
         raise TypeError("expected a C-contiguous numpy array of %s" % np.dtype(dtype))

@@ -75,6 +75,17 @@ def test_law_at_256_sampled_voxels(ctx, spheres256):
     P = torch.empty_like(F)
     a = torch.empty((3, n), device=dev(), dtype=torch.float64)
     st = combo.combo_eval_law(ctx, F, P, None, a, None)
+    if st != combo.COMBO_OK:   # name the failing voxels before failing
+        err = combo.combo_last_error(ctx)
+        it = torch.zeros(n, device=dev(), dtype=torch.int32)
+        combo.combo_eval_law(ctx, F, P, None, a, it)
+        det = torch.linalg.det(F.T.reshape(-1, 3, 3))
+        maxit = combo.combo_default_options().max_laminate
+        worst = torch.nonzero(it >= maxit).flatten()[:8].cpu().numpy()
+        print("law failure:", err, "| laminate iters max", int(it.max()), "| at the limit", int((it >= maxit).sum()),
+              "| min det F", float(det.min()), "| voxels", worst, "| c", ms.c.reshape(-1)[worst],
+              "| N", ms.N.reshape(3, -1)[:, worst].T, "| F", F[:, torch.from_numpy(worst).to(dev())].T.cpu().numpy(),
+              flush=True)
     assert st == combo.COMBO_OK, combo.combo_last_error(ctx)
     idx = sample_voxels(ms, 4096, 1)
     ti = torch.from_numpy(idx).to(dev())
