@@ -45,14 +45,17 @@ struct AxisPlan {
 // Geometry of one RVE as the kernels see it.
 struct Grid {
     int n1, n2, n3;       // voxels per axis
-    int nh;               // stored x frequencies: n1/2 (even n1, Nyquist dropped) or (n1+1)/2
+    int nh;               // row stride of the half spectrum (complex values; >= nkx)
+    int nkx;              // stored x frequencies: n1/2 (even n1, Nyquist dropped) or (n1+1)/2;
+                          // rotated scheme: n1/2 + 1, rows padded to nh with zero modes
     long long n;          // n1*n2*n3
-    long long nspec;      // nh*n2*n3 (complex values per spectral component)
+    long long nspec;      // nh*n2*n3 (complex values per spectral component, padding included)
     double xs1, xs2, xs3; // 2 pi / l_d: xi_d(k) = xs_d * k
     int xm, xwbits;       // wavefront x pass: m values per lane, log2 of lanes per row (-1: none)
     int xv, yv, zv;       // schedule: variant of the x, y and z FFT passes (0 = default)
-    int disc;             // 0: Moulinec-Suquet frequencies, 1: Willot's rotated scheme (generic kernels only)
+    int disc;             // 0: Moulinec-Suquet frequencies, 1: Willot's rotated scheme
     const double* ftab;   // disc 1: device table D1[nh] A1[nh] D2[n2] A2[n2] D3[n3] A3[n3]
+                          // (D1 = A1 = 0 on the padding x >= nkx: every padded mode is a zero mode)
 };
 
 // Position of voxel `vox` in the tangent-state arrays.  With the wavefront x
@@ -99,6 +102,13 @@ __device__ inline double fac_d3(const Grid& g, int j) {
     return g.disc ? g.ftab[2 * g.nh + 2 * g.n2 + j] : g.xs3 * freq_of(j, g.n3);
 }
 __device__ inline double fac_a3(const Grid& g, int j) { return g.disc ? g.ftab[2 * g.nh + 2 * g.n2 + g.n3 + j] : 1.0; }
+// Copies count factors of the table (e.g. one axis's D[len] A[len], contiguous: count =
+// 2 len) into LDS in the precision of the pass, so that the transforms read them from
+// LDS instead of keeping per-element double loads from the table in flight.
+template <typename T>
+__device__ inline void stage_factors(T* dst, const double* src, int count, int tid, int nthreads) {
+    for (int i = tid; i < count; i += nthreads) dst[i] = T(src[i]);
+}
 // true if index j is the Nyquist index of an even axis of length n
 __host__ __device__ inline bool is_nyquist(int j, int n) { return (n % 2 == 0) && (j == n / 2) && n > 1; }
 

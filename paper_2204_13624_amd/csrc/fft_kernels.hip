@@ -123,7 +123,7 @@ __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int n
     using C = cpx<T>;
     if (MODE == X_CG && a.st->done) return;
     extern __shared__ char smem_raw[];
-    const int L = a.g.n1, nh = a.g.nh, R = a.R;
+    const int L = a.g.n1, nh = a.g.nh, nk = a.g.nkx, R = a.R;   // row stride, stored bins
     C* tw = reinterpret_cast<C*>(smem_raw);
     C* buf = tw + L;                   // [5R][L], column-major (each sequence contiguous)
     __shared__ double red[16];
@@ -138,10 +138,10 @@ __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int n
 
     if (HAS_INV) {
         // unpack half spectra into full-length sequences
-        const int items = 5 * R * nh;
+        const int items = 5 * R * nk;
         for (int it = tid; it < items; it += kBlock) {
-            const int k = it % nh;
-            const int sr = it / nh;
+            const int k = it % nk;
+            const int sr = it / nk;
             const int rr = sr % R, s = sr / R;
             const long long row = row0 + rr;
             C ha = mk<T>(0, 0), hb = mk<T>(0, 0);
@@ -167,7 +167,7 @@ __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int n
                 col[k] = mk<T>(ha.x - hb.y, ha.y + hb.x);
                 col[L - k] = mk<T>(ha.x + hb.y, hb.x - ha.y);
             }
-            if (2 * nh == L && k == nh - 1 && L > 1) col[L / 2] = mk<T>(0, 0);
+            if (2 * nk == L && k == nk - 1 && L > 1) col[L / 2] = mk<T>(0, 0);
         }
         __syncthreads();
         fft_lds<+1, true, T>(buf, a.plan, 5 * R, tw);
@@ -256,7 +256,9 @@ __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int n
         C hb = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
         const long long off = row * nh + k;
         const int ca = 2 * s, cb = 2 * s + 1;
-        if (a.g.disc) {
+        if (k >= nk) {   // row padding: zero modes
+            ha = hb = mk<T>(0, 0);
+        } else if (a.g.disc) {
             const T d1 = T(fac_d1(a.g, k)), a1 = T(fac_a1(a.g, k));
             ha = cscale(ha, xi1_comp(ca) ? d1 : a1);
             hb = cscale(hb, xi1_comp(cb) ? d1 : a1);
@@ -469,18 +471,25 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
     constexpr int BUFC = cmax3(S::EXA, S::EXN, FLD);
     if (MODE == X_CG && a.st->done) return;
     __shared__ C buf[BUFC];   // exchange, natural rows and real rows in turn
+    // stored x frequencies: the Nyquist bin is dropped (Moulinec-Suquet) or kept (rotated
+    // scheme, whose rows may be padded: row stride ld >= nh)
+    constexpr int nh = DISC ? L / 2 + 1 : L / 2;
+    const int ld = DISC ? a.g.nh : nh;
     __shared__ C tw[L];
+    __shared__ T fx[DISC ? 2 * nh : 1];   // rotated scheme: D1[nh] A1[nh]
     __shared__ double red[16];
     T* fld = reinterpret_cast<T*>(buf);   // real rows [9][R][L] and a sink row block
     const int tid = threadIdx.x;
     static_assert(L % 2 == 0, "two-stage x pass rows have even length");
-    // stored x frequencies: the Nyquist bin is dropped (Moulinec-Suquet) or kept (rotated scheme)
-    constexpr int nh = DISC ? L / 2 + 1 : L / 2;
     const long long nspec = a.g.nspec;
     const long long nrows = (long long)a.g.n2 * a.g.n3;
     const long long row0 = (long long)tile_ * R;
     const T xs1 = T(a.g.xs1);
     for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
+    if constexpr (DISC) {
+        stage_factors<T>(fx, a.g.ftab, nh, tid, blockDim.x);
+        stage_factors<T>(fx + nh, a.g.ftab + ld, nh, tid, blockDim.x);
+    }
     const int t = tid / S::NT, j = tid % S::NT;   // column and item index of this thread
     const bool col_ok = t < TX;
     const int s = col_ok ? t / R : 0, r = col_ok ? t % R : 0;
@@ -497,8 +506,8 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
     T* fb = fld + ((s < 4 ? cb : 9) * R + r) * L;   // row 9 of fld is a write-only sink
     if (col_ok && j < P) {
         const long long rowc = live ? row : 0;
-        const C* pa = a.in + ca * nspec + rowc * nh;
-        const C* pb = a.in + (s < 4 ? cb : ca) * nspec + rowc * nh;
+        const C* pa = a.in + ca * nspec + rowc * ld;
+        const C* pb = a.in + (s < 4 ? cb : ca) * nspec + rowc * ld;
         const bool sa = xi1_comp(ca), sb = xi1_comp(cb);
         const T mb0 = s < 4 ? T(1) : T(0);
         C ha[Q], hb[Q];
@@ -519,7 +528,7 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
             const T m = (live && kk < nh) ? T(1) : T(0);
             T ma, mb;
             if constexpr (DISC) {
-                const T d1 = T(fac_d1(a.g, kk)), a1 = T(fac_a1(a.g, kk));
+                const T d1 = fx[kk], a1 = fx[nh + kk];
                 ma = m * (sa ? d1 : a1);
                 mb = mb0 * m * (sb ? d1 : a1);
             } else {
@@ -627,8 +636,8 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
         for (int k2 = 0; k2 < P; ++k2) buf[t * LP + j + Q * k2] = y[k2];
     }
     __syncthreads();
-    for (int i = tid; i < TX * nh; i += blockDim.x) {
-        const int tt = i / nh, k = i - tt * nh;
+    for (int i = tid; i < TX * ld; i += blockDim.x) {
+        const int tt = i / ld, k = i - tt * ld;
         const int ss = tt / R, rr = tt - ss * R;
         const long long rw = row0 + rr;
         if (rw >= nrows) continue;
@@ -638,7 +647,8 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
         C hb = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
         const int c1 = 2 * ss, c2 = 2 * ss + 1;
         if constexpr (DISC) {
-            const T d1 = T(fac_d1(a.g, k)), a1 = T(fac_a1(a.g, k));
+            const bool pad = k >= nh;   // row padding: zero modes
+            const T d1 = pad ? T(0) : fx[k], a1 = pad ? T(0) : fx[nh + k];
             ha = cscale(ha, xi1_comp(c1) ? d1 : a1);
             hb = cscale(hb, xi1_comp(c2) ? d1 : a1);
         } else {
@@ -646,7 +656,7 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
             if (xi1_comp(c1)) ha = cscale(ha, x1);
             if (xi1_comp(c2)) hb = cscale(hb, x1);
         }
-        const long long off = rw * nh + k;
+        const long long off = rw * ld + k;
         a.out[c1 * nspec + off] = ha;
         if (ss < 4) a.out[c2 * nspec + off] = hb;
     }
@@ -873,6 +883,22 @@ struct ColFreq {
     bool nyq2;              // Nyquist plane of y
 };
 
+// column data of the rotated scheme (what col_freq_k computes when g.disc is set)
+__device__ __forceinline__ ColFreq col_freq_rot(const Grid& g, int ky, int kx) {
+    ColFreq c;
+    c.ky = ky;
+    c.kx = kx;
+    const double d1 = fac_d1(g, kx), a1 = fac_a1(g, kx), d2 = fac_d2(g, ky), a2 = fac_a2(g, ky);
+    c.x1 = d1 * a2;
+    c.x2 = a1 * d2;
+    c.c3 = a1 * a2;
+    c.s12 = 0.0;
+    c.w = (kx == 0 || 2 * kx == g.n1) ? 1.0 : 2.0;
+    c.zero12 = false;
+    c.nyq2 = false;
+    return c;
+}
+
 __device__ __forceinline__ ColFreq col_freq_k(const Grid& g, int ky, int kx) {
     ColFreq c;
     c.ky = ky;
@@ -902,6 +928,19 @@ __device__ __forceinline__ ColFreq col_freq_k(const Grid& g, int ky, int kx) {
 __device__ __forceinline__ ColFreq col_freq(const Grid& g, int m) {
     const int ky = m / g.nh;
     return col_freq_k(g, ky, m - ky * g.nh);
+}
+
+// rotated scheme: the column's factors times the z factors a3 = A3(z), d3 = D3(z) (what
+// freq_z computes when g.disc is set, with the factors passed in)
+__device__ __forceinline__ Freq freq_z_rot(const ColFreq& c, double a3, double d3) {
+    Freq f;
+    f.x1 = c.x1 * a3;
+    f.x2 = c.x2 * a3;
+    f.x3 = c.c3 * d3;
+    f.s = f.x1 * f.x1 + f.x2 * f.x2 + f.x3 * f.x3;
+    f.zero = !(f.s > 0.0);   // the mean and modes on two or more Nyquist planes
+    f.w = c.w;
+    return f;
 }
 
 __device__ __forceinline__ Freq freq_z(const Grid& g, const ColFreq& c, int z) {
@@ -961,18 +1000,16 @@ __device__ __forceinline__ void kmul(const Freq& f, double mu0, double kappa0, c
     }
 }
 
-// Per-frequency end of the forward z pass: given v = tau_hat xi at (m, z),
+// Per-frequency end of the forward z pass: given v = tau_hat xi at the frequency f
+// stored at idx (z M + m),
 //   Z_CG:   q = K^{-1} v / n, accumulate <p, q>_K = w Re(p^H v)/n
 //   Z_RHS:  r = b = -K^{-1} v, x = 0, accumulate <b, b>_K and |G P|^2 = |v|^2/|xi|^2
 //   Z_PROJ: x = K^{-1} v
 template <typename T, typename TU, int MODE>
-__device__ __forceinline__ void z_epilogue(const ZArgs<T, TU>& a, const ColFreq& cf, long long m, int z, const cpx<T>* vv,
+__device__ __forceinline__ void z_epilogue(const ZArgs<T, TU>& a, const Freq& f, long long idx, const cpx<T>* vv,
                                            double& s1, double& s2) {
     using C = cpx<T>;
     using CU = cpx<TU>;
-    const long long M = (long long)a.g.n2 * a.g.nh;
-    const Freq f = freq_z(a.g, cf, z);
-    const long long idx = (long long)z * M + m;
     C w[3];
     if (f.zero) {
         w[0] = w[1] = w[2] = mk<T>(0, 0);
@@ -1022,6 +1059,15 @@ __device__ __forceinline__ void z_epilogue(const ZArgs<T, TU>& a, const ColFreq&
             a.x[i * a.g.nspec + idx] = o;
         }
     }
+}
+
+// z_epilogue at column m, frequency index z of the Moulinec-Suquet spectrum (frequency
+// from the column data)
+template <typename T, typename TU, int MODE>
+__device__ __forceinline__ void z_epilogue_at(const ZArgs<T, TU>& a, const ColFreq& cf, long long m, int z,
+                                              const cpx<T>* vv, double& s1, double& s2) {
+    const long long M = (long long)a.g.n2 * a.g.nh;
+    z_epilogue<T, TU, MODE>(a, freq_z(a.g, cf, z), (long long)z * M + m, vv, s1, s2);
 }
 
 template <typename T>
@@ -1099,7 +1145,7 @@ __device__ __forceinline__ void k_zpass_fwd_body(const ZArgs<T, TU>& a, int tile
         const long long m = m0 + t;
         if (m >= M) continue;
         C vv[3] = {v[0][q], v[1][q], v[2][q]};
-        z_epilogue<T, TU, MODE>(a, col_freq(a.g, (int)m), m, z, vv, s1, s2);
+        z_epilogue<T, TU, MODE>(a, freq_at(a.g, m, z), (long long)z * M + m, vv, s1, s2);
     }
     if (MODE == Z_CG || MODE == Z_RHS) {
         const double t1 = block_sum(s1, red);
@@ -1370,12 +1416,12 @@ __device__ __forceinline__ void k_antiherm_body(const UArgs<TU>& a, int tile_, i
     cpx<TU>* u = a.r;
     const long long M = (long long)g.n2 * g.nh;
     const long long npl = (long long)g.n2 * g.n3;
-    const int nplanes = (g.disc && g.n1 > 1 && 2 * (g.nh - 1) == g.n1) ? 2 : 1;
+    const int nplanes = (g.disc && g.n1 > 1 && 2 * (g.nkx - 1) == g.n1) ? 2 : 1;
     for (long long t = (long long)tile_ * blockDim.x + threadIdx.x; t < npl * nplanes;
          t += (long long)ntiles_ * blockDim.x) {
         const int plane = (int)(t / npl);
         const long long tp = t - plane * npl;
-        const int kx = plane ? g.nh - 1 : 0;
+        const int kx = plane ? g.nkx - 1 : 0;
         const int z = (int)(tp / g.n2), ky = (int)(tp - (long long)z * g.n2);
         const long long idx = (long long)z * M + (long long)ky * g.nh + kx;
         const long long idx2 = kx0_partner(g, M, z, ky) + kx;
@@ -1497,11 +1543,13 @@ __device__ __forceinline__ void k_y2_fwd_body(const YArgs<T>& a, int tile_, int 
     if (a.st && a.st->done) return;
     __shared__ C ex[F::exch_elems()];
     __shared__ C tw[L];
+    __shared__ T fy[DISC ? 2 * L : 1];   // rotated scheme: D2[L] A2[L]
     const int tid = threadIdx.x;
     const int z = tile_ / a.ntile, kx0 = (tile_ % a.ntile) * TX;
     const int nh = a.g.nh;
     const long long zoff = (long long)z * L * nh;
     for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
+    if constexpr (DISC) stage_factors<T>(fy, a.g.ftab + 2 * a.g.nh, 2 * L, tid, blockDim.x);
     const bool hasA = tid < F::NA, hasB = tid < F::NB;
     const int tA = tid % TX, j1 = tid / TX, tB = tid % TX, k1 = tid / TX;
     const bool colA = kx0 + tA < nh, colB = kx0 + tB < nh;
@@ -1534,7 +1582,7 @@ __device__ __forceinline__ void k_y2_fwd_body(const YArgs<T>& a, int tile_, int 
                 if (sub == 0) {
 #pragma unroll
                     for (int k2 = 0; k2 < P; ++k2)
-                        acc[k2] = DISC ? cscale(y[k2], T(fac_a2(a.g, k1 + Q * k2))) : y[k2];
+                        acc[k2] = DISC ? cscale(y[k2], fy[L + k1 + Q * k2]) : y[k2];
                 } else if (colB) {
                     const int oc = (sub == 1) ? i : 3 + i;
                     C* dst = a.out + oc * a.g.nspec + zoff + kx0;   // uniform
@@ -1542,8 +1590,8 @@ __device__ __forceinline__ void k_y2_fwd_body(const YArgs<T>& a, int tile_, int 
                     for (int k2 = 0; k2 < P; ++k2) {
                         const int ky = k1 + Q * k2;
                         C v = y[k2];
-                        if (sub == 1) v = cadd(acc[k2], cscale(v, DISC ? T(fac_d2(a.g, ky)) : xs2 * T(freq_of(ky, L))));
-                        else if (DISC) v = cscale(v, T(fac_a2(a.g, ky)));
+                        if (sub == 1) v = cadd(acc[k2], cscale(v, DISC ? fy[ky] : xs2 * T(freq_of(ky, L))));
+                        else if (DISC) v = cscale(v, fy[L + ky]);
                         dst[tB + ky * nh] = v;
                     }
                 }
@@ -1572,11 +1620,13 @@ __device__ __forceinline__ void k_y2_inv_body(const YArgs<T>& a, int tile_, int 
     if (a.st && a.st->done) return;
     __shared__ C ex[F::exch_elems()];
     __shared__ C tw[L];
+    __shared__ T fy[DISC ? 2 * L : 1];   // rotated scheme: D2[L] A2[L]
     const int tid = threadIdx.x;
     const int z = tile_ / a.ntile, kx0 = (tile_ % a.ntile) * TX;
     const int nh = a.g.nh;
     const long long zoff = (long long)z * L * nh;
     for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
+    if constexpr (DISC) stage_factors<T>(fy, a.g.ftab + 2 * a.g.nh, 2 * L, tid, blockDim.x);
     const bool hasA = tid < F::NA, hasB = tid < F::NB;
     const int tA = tid % TX, j1 = tid / TX, tB = tid % TX, k1 = tid / TX;
     const bool colA = kx0 + tA < nh, colB = kx0 + tB < nh;
@@ -1600,7 +1650,7 @@ __device__ __forceinline__ void k_y2_inv_body(const YArgs<T>& a, int tile_, int 
 #pragma unroll
             for (int j2 = 0; j2 < Q; ++j2) {
                 const int y = j1 + P * j2;
-                if (DISC) x[j2] = cscale(nx[j2], T(sub == 1 ? fac_d2(a.g, y) : fac_a2(a.g, y)));
+                if (DISC) x[j2] = cscale(nx[j2], fy[sub == 1 ? y : L + y]);
                 else x[j2] = (sub == 1) ? cscale(nx[j2], xs2 * T(freq_of(y, L))) : nx[j2];
             }
             if (3 * i + sub + 1 < 9) load(3 * i + sub + 1);
@@ -1637,11 +1687,13 @@ __device__ __forceinline__ void k_z2_fwd_body(const ZArgs<T, TU>& a, int tile_, 
     if (MODE == Z_CG && a.st->done) return;
     __shared__ C ex[F::exch_elems()];
     __shared__ C tw[L];
+    __shared__ T fz[DISC ? 2 * L : 1];   // rotated scheme: D3[L] A3[L]
     __shared__ double red[16];
     const int tid = threadIdx.x;
     const long long M = (long long)a.g.n2 * a.g.nh;
     const long long m0 = (long long)tile_ * TX;
     for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
+    if constexpr (DISC) stage_factors<T>(fz, a.g.ftab + 2 * a.g.nh + 2 * a.g.n2, 2 * L, tid, blockDim.x);
     const bool hasA = tid < F::NA, hasB = tid < F::NB;
     const int tA = tid % TX, j1 = tid / TX, tB = tid % TX, k1 = tid / TX;
     const bool colA = m0 + tA < M, colB = m0 + tB < M;
@@ -1675,8 +1727,8 @@ __device__ __forceinline__ void k_z2_fwd_body(const ZArgs<T, TU>& a, int tile_, 
                 for (int k2 = 0; k2 < P; ++k2) {
                     const int zz = k1 + Q * k2;
                     if constexpr (DISC) {
-                        if (sub == 0) v[i][k2] = cscale(y[k2], T(fac_a3(a.g, zz)));
-                        else v[i][k2] = cadd(v[i][k2], cscale(y[k2], T(fac_d3(a.g, zz))));
+                        if (sub == 0) v[i][k2] = cscale(y[k2], fz[L + zz]);
+                        else v[i][k2] = cadd(v[i][k2], cscale(y[k2], fz[zz]));
                     } else {
                         if (sub == 0) v[i][k2] = y[k2];
                         else v[i][k2] = cadd(v[i][k2], cscale(y[k2], xs3 * T(freq_of(zz, L))));
@@ -1688,11 +1740,23 @@ __device__ __forceinline__ void k_z2_fwd_body(const ZArgs<T, TU>& a, int tile_, 
     }
     double s1 = 0.0, s2 = 0.0;
     if (hasB && colB) {
-        const ColFreq cf = col_freq(a.g, (int)(m0 + tB));   // one column per thread
+        if constexpr (DISC) {
+            const int m = (int)(m0 + tB), ky = m / a.g.nh, kx = m - ky * a.g.nh;   // one column per thread
+            const ColFreq cf = col_freq_rot(a.g, ky, kx);
 #pragma unroll
-        for (int k2 = 0; k2 < P; ++k2) {
-            C vv[3] = {v[0][k2], v[1][k2], v[2][k2]};
-            z_epilogue<T, TU, MODE>(a, cf, m0 + tB, k1 + Q * k2, vv, s1, s2);
+            for (int k2 = 0; k2 < P; ++k2) {
+                const int zz = k1 + Q * k2;
+                C vv[3] = {v[0][k2], v[1][k2], v[2][k2]};
+                const Freq f = freq_z_rot(cf, double(fz[L + zz]), double(fz[zz]));
+                z_epilogue<T, TU, MODE>(a, f, (long long)zz * M + m, vv, s1, s2);
+            }
+        } else {
+            const ColFreq cf = col_freq(a.g, (int)(m0 + tB));   // one column per thread
+#pragma unroll
+            for (int k2 = 0; k2 < P; ++k2) {
+                C vv[3] = {v[0][k2], v[1][k2], v[2][k2]};
+                z_epilogue_at<T, TU, MODE>(a, cf, m0 + tB, k1 + Q * k2, vv, s1, s2);
+            }
         }
     }
     if (MODE == Z_CG || MODE == Z_RHS) {
@@ -1725,10 +1789,12 @@ __device__ __forceinline__ void k_z2_inv_body(const ZArgs<T, TU>& a, int tile_, 
     if (MODE == Z_INV_CG && a.st->done) return;
     __shared__ C ex[F::exch_elems()];
     __shared__ C tw[L];
+    __shared__ T fz[DISC ? 2 * L : 1];   // rotated scheme: D3[L] A3[L]
     const int tid = threadIdx.x;
     const long long M = (long long)a.g.n2 * a.g.nh;
     const long long m0 = (long long)tile_ * TX;
     for (int i = tid; i < L; i += blockDim.x) tw[i] = a.tw[i];
+    if constexpr (DISC) stage_factors<T>(fz, a.g.ftab + 2 * a.g.nh + 2 * a.g.n2, 2 * L, tid, blockDim.x);
     const bool hasA = tid < F::NA, hasB = tid < F::NB;
     const int tA = tid % TX, j1 = tid / TX, tB = tid % TX, k1 = tid / TX;
     const bool colA = m0 + tA < M, colB = m0 + tB < M;
@@ -1780,7 +1846,7 @@ __device__ __forceinline__ void k_z2_inv_body(const ZArgs<T, TU>& a, int tile_, 
 #pragma unroll
                 for (int j2 = 0; j2 < Q; ++j2) {
                     const int zz = j1 + P * j2;
-                    if (DISC) x[j2] = cscale(u[j2], T(sub ? fac_d3(a.g, zz) : fac_a3(a.g, zz)));
+                    if (DISC) x[j2] = cscale(u[j2], fz[sub ? zz : L + zz]);
                     else x[j2] = sub ? cscale(u[j2], xs3 * T(freq_of(zz, L))) : u[j2];
                 }
                 fft2_stageA<P, Q, TX, +1, T>(x, tA, j1, ex, tw);

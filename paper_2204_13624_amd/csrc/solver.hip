@@ -1742,6 +1742,7 @@ int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2,
     ctx->g.disc = COMBO_DISC_MS;
     ctx->g.ftab = nullptr;
     ctx->g.nh = (n1 % 2 == 0) ? n1 / 2 : (n1 + 1) / 2;
+    ctx->g.nkx = ctx->g.nh;
     ctx->g.n = (long long)n1 * n2 * n3;
     ctx->g.nspec = (long long)ctx->g.nh * n2 * n3;
     const double twopi = 6.283185307179586476925286766559;
@@ -1794,7 +1795,12 @@ int combo_set_discretization(combo_ctx* ctx, int disc) {
     if (st != COMBO_OK || disc == COMBO_DISC_MS) return st;
     Grid& g = ctx->g;
     g.disc = COMBO_DISC_WILLOT;
-    g.nh = n1 / 2 + 1;   // x frequencies 0 .. floor(n1/2): an even n1 keeps its Nyquist bin
+    g.nkx = n1 / 2 + 1;   // x frequencies 0 .. floor(n1/2): an even n1 keeps its Nyquist bin
+    // Rows of nkx = 16 m + 1 values would start off the 128-byte lines that the y pass
+    // reads in tiles of 16 columns; pad them to a multiple of 16 where that adds at
+    // most a quarter of zero modes (n1 >= 128).
+    const int padded = (g.nkx + 15) / 16 * 16;
+    g.nh = (4 * (padded - g.nkx) <= g.nkx) ? padded : g.nkx;
     g.nspec = (long long)g.nh * n2 * n3;
     g.xwbits = -1;       // natural state order: the rotated scheme runs the generic x pass
     // D = (2/h) sin(theta/2), A = cos(theta/2); x: theta = 2 pi k / n1 (k >= 0), y and z:
@@ -1810,6 +1816,7 @@ int combo_set_discretization(combo_ctx* ctx, int disc) {
             const long double half = 3.14159265358979323846264338327950288L * (long double)f / (long double)ns[d];
             D[j] = (double)(2.0L / h * sinl(half));
             A[j] = (2 * f == ns[d] || 2 * f == -ns[d]) ? 0.0 : (double)cosl(half);
+            if (d == 0 && j >= g.nkx) D[j] = A[j] = 0.0;   // row padding: zero modes
         }
         tab.insert(tab.end(), D.begin(), D.end());
         tab.insert(tab.end(), A.begin(), A.end());

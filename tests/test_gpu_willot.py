@@ -2,7 +2,9 @@
 through the C-ABI, against the oracle: both Green operators and the CG operator
 on even and odd grids (even n1 keeps its x-Nyquist plane), Newton-CG solves in
 FP64 and mixed precision under both laws, the effective tangent, an exact layered
-RVE on an even grid, and the 256^3 sphere workload."""
+RVE on an even grid, and the 256^3 sphere workload.  Grids with n1 >= 128 store the
+half spectrum in rows padded to a multiple of 16 (zero modes): 128, 192 and 256 cover
+that layout."""
 import numpy as np
 import pytest
 
@@ -47,7 +49,7 @@ SHAPES = [((8, 6, 4), (1.0, 1.0, 1.0)), ((9, 6, 4), (0.9, 1.2, 0.8)), ((12, 16, 
           ((2, 3, 8), (1.0, 1.0, 1.0)), ((1, 6, 4), (1.0, 1.0, 1.0)), ((16, 18, 12), (1.0, 1.0, 1.0))]
 
 
-@pytest.mark.parametrize("n,l", SHAPES)
+@pytest.mark.parametrize("n,l", SHAPES + [((128, 3, 4), (1.0, 0.7, 1.1))])
 def test_green_operators_match_oracle(ctx, n, l):
     ms = synth.random_composite_field(n, 3, frac_composite=0.2, l=l)
     setup(ctx, ms)
@@ -64,8 +66,10 @@ def test_green_operators_match_oracle(ctx, n, l):
             assert rel(out, ref) <= tol, (which, prec)
 
 
-# x lengths 32, 48 and 64 run the two-stage x pass (with the x-Nyquist bin); the others the LDS x pass
-CG_SHAPES = SHAPES[:3] + [((32, 6, 4), (1.0, 1.0, 1.0)), ((64, 8, 6), (1.0, 0.5, 0.4)), ((48, 9, 4), (1.0, 1.0, 1.0))]
+# x lengths 32, 48, 64 and 128 run the two-stage x pass (with the x-Nyquist bin); the others
+# the LDS x pass; 128 and 192 pad the rows (65 -> 80 and 97 -> 112 values)
+CG_SHAPES = SHAPES[:3] + [((32, 6, 4), (1.0, 1.0, 1.0)), ((64, 8, 6), (1.0, 0.5, 0.4)), ((48, 9, 4), (1.0, 1.0, 1.0)),
+                          ((128, 4, 4), (1.0, 1.0, 1.0)), ((192, 3, 4), (1.2, 1.0, 0.9))]
 
 
 @pytest.mark.parametrize("n,l", CG_SHAPES)
@@ -94,7 +98,7 @@ def test_cg_operator_matches_oracle(ctx, n, l):
             assert rel(q, ref.reshape(pc.shape)) <= tol, (prec, xv)
 
 
-@pytest.mark.parametrize("n", [(16, 16, 16), (9, 12, 8)])
+@pytest.mark.parametrize("n", [(16, 16, 16), (9, 12, 8), (128, 4, 4)])
 def test_solves_match_oracle(ctx, n):
     ms = synth.single_sphere(n, radius=0.3, center=(0.02, -0.03, 0.01))
     ref = osol.solve(oracle_problem(ms), FBAR, osol.Options(tol_newton=1e-10, tol_cg=1e-12))
@@ -199,11 +203,12 @@ def test_full_size_sphere_workload(ctx):
 
 
 def test_batch_mixes_discretizations():
-    """Two rotated-scheme members of different grids and one Moulinec-Suquet member in one
+    """Three rotated-scheme members of different grids and one Moulinec-Suquet member in one
     batch: each equals its single solve and the oracle of its discretization."""
     cases = [(synth.single_sphere((16, 16, 16), radius=0.3), "willot"),
              (synth.random_spheres((24, 16, 12), 3, 0.2, seed=21), "willot"),
-             (synth.single_sphere((16, 12, 8), radius=0.3), "ms")]
+             (synth.single_sphere((16, 12, 8), radius=0.3), "ms"),
+             (synth.random_spheres((128, 4, 6), 2, 0.2, seed=5), "willot")]   # padded rows
     o = combo.combo_default_options()
     o.tol_newton = 1e-10
     o.tol_cg = 1e-12
@@ -215,7 +220,7 @@ def test_batch_mixes_discretizations():
             assert combo.combo_batch_add(b, ms.n, ms.l, MATS, ms.phase, ms.c, ms.N) == i
         with pytest.raises(combo.ComboError):
             combo.combo_batch_set_discretization(b, 5)
-        res = combo.combo_batch_solve(b, np.stack([FBAR] * 3), n_increments=[1, 1, 1])
+        res = combo.combo_batch_solve(b, np.stack([FBAR] * 4), n_increments=[1, 1, 1, 1])
     finally:
         combo.combo_batch_destroy(b)
     for i, (ms, disc) in enumerate(cases):
