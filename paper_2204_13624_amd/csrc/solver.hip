@@ -1798,11 +1798,11 @@ int combo_set_discretization(combo_ctx* ctx, int disc) {
     g.nkx = n1 / 2 + 1;   // x frequencies 0 .. floor(n1/2): an even n1 keeps its Nyquist bin
     // Rows of nkx = 16 m + 1 values would start off the 128-byte lines that the y pass
     // reads in tiles of 16 columns; pad them to a multiple of 16 where that adds at
-    // most a quarter of zero modes (n1 >= 128).
+    // most a quarter of zero modes (e.g. 256: 129 -> 144, 112: 57 -> 64; 64: none).
     const int padded = (g.nkx + 15) / 16 * 16;
     g.nh = (4 * (padded - g.nkx) <= g.nkx) ? padded : g.nkx;
     g.nspec = (long long)g.nh * n2 * n3;
-    g.xwbits = -1;       // natural state order: the rotated scheme runs the generic x pass
+    g.xwbits = -1;       // natural state order: the rotated scheme has no wavefront x pass
     // D = (2/h) sin(theta/2), A = cos(theta/2); x: theta = 2 pi k / n1 (k >= 0), y and z:
     // theta = 2 pi freq / n with freq in [-n/2, n/2); A = 0 exactly at |theta| = pi
     const int ns[3] = {n1, n2, n3};

@@ -2,8 +2,8 @@
 through the C-ABI, against the oracle: both Green operators and the CG operator
 on even and odd grids (even n1 keeps its x-Nyquist plane), Newton-CG solves in
 FP64 and mixed precision under both laws, the effective tangent, an exact layered
-RVE on an even grid, and the 256^3 sphere workload.  Grids with n1 >= 128 store the
-half spectrum in rows padded to a multiple of 16 (zero modes): 128, 192 and 256 cover
+RVE on an even grid, and the 256^3 sphere workload.  Grids from about n1 = 100 on store
+the half spectrum in rows padded to a multiple of 16 (zero modes): 128, 192 and 256 cover
 that layout."""
 import numpy as np
 import pytest
