@@ -1,0 +1,149 @@
+"""Staggered-grid finite differences and the doubly-fine material grid (DFMG) law
+(paper App. A).  Test infrastructure: only tests/ use it.  No solver and no GPU
+path use these operators yet; they are the first pinned pieces of that
+discretization.
+
+Fields are arrays [3, n3, n2, n1] (vectors) and [3, 3, n3, n2, n1] (tensors), x
+the last array axis, cell xi = (i, j, k) at array index [k, j, i].
+
+Placement (App. A): U_a sits on the face of cell xi normal to e_a; the diagonal
+F_aa (and P_aa) at the cell centre; F_ab = F_ba (a != b) on the edge of cell xi
+parallel to the third axis at the lower corner in a and b, e.g. F_12 at
+(i h1, j h2, (k + 1/2) h3).
+
+Forward and backward differences (eq. forward_backward_difference):
+    D_j^+ phi[I] = (phi[I + e_j] - phi[I]) / h_j,   D_j^- phi[I] = (phi[I] - phi[I - e_j]) / h_j.
+Gradient (eq. gradient_operator): F_aA = D_A^+ U_a on the diagonal, D_A^- U_a off it.
+
+Readings (the printed formulas are not all consistent with that placement):
+  * Div: the printed matrix pairs D_B with P_Ba (derivative on the first index),
+    the gradient D_A with F_aA (derivative on the second).  Taken here as the
+    negative adjoint of Grad, (Div P)_a = sum_A D_A^{-s} P_aA with s the sign
+    Grad uses for (a, A); for a symmetric P the two agree.
+  * DFMG material offsets: P^{ab}_l[xi] for a < b is printed as the law of cell
+    xi + l^{+a,+b}, while the same formula takes the diagonal entries of
+    F^{ab}_l from cells xi + l^{-a,-b}.  The edge of F_ab borders the cells
+    xi - l^{a,b} (l_a, l_b in {0, 1}), so the law of cell xi + l^{-a,-b} is used.
+"""
+import numpy as np
+
+AXIS = {0: -1, 1: -2, 2: -3}     # direction (x, y, z) -> array axis
+
+
+def shift(phi, d, s):
+    """phi[I + s e_d] for a periodic field (d = 0, 1, 2 for x, y, z)."""
+    return np.roll(phi, -s, axis=AXIS[d])
+
+
+def d_fwd(phi, d, h):
+    return (shift(phi, d, 1) - phi) / h[d]
+
+
+def d_bwd(phi, d, h):
+    return (phi - shift(phi, d, -1)) / h[d]
+
+
+def grad(U, h):
+    """Staggered gradient [3, 3, ...] of U [3, ...] (eq. gradient_operator)."""
+    F = np.empty((3, 3) + U.shape[1:])
+    for a in range(3):
+        for A in range(3):
+            F[a, A] = d_fwd(U[a], A, h) if a == A else d_bwd(U[a], A, h)
+    return F
+
+
+def div(P, h):
+    """Staggered divergence [3, ...] of P [3, 3, ...]: the negative adjoint of grad."""
+    out = np.zeros((3,) + P.shape[2:])
+    for a in range(3):
+        for A in range(3):
+            out[a] += d_bwd(P[a, A], A, h) if a == A else d_fwd(P[a, A], A, h)
+    return out
+
+
+def grad_symbols(n, l):
+    """Fourier multipliers g[a, A] (shape [3, 3, n3, n2, n1], complex) of grad for
+    numpy's fftn convention: fftn(grad(U))[a, A] = g[a, A] * fftn(U[a]).
+    Forward difference: (e^{i theta} - 1) / h, backward: (1 - e^{-i theta}) / h,
+    theta_d = 2 pi k_d / n_d."""
+    h = [l[d] / n[d] for d in range(3)]
+    th = []
+    for d in range(3):
+        t = 2.0 * np.pi * np.arange(n[d]) / n[d]
+        shape = [1, 1, 1]
+        shape[2 - d] = n[d]
+        th.append(t.reshape(shape))
+    g = np.empty((3, 3, n[2], n[1], n[0]), complex)
+    for a in range(3):
+        for A in range(3):
+            if a == A:
+                sym = (np.exp(1j * th[A]) - 1.0) / h[A]
+            else:
+                sym = (1.0 - np.exp(-1j * th[A])) / h[A]
+            g[a, A] = np.broadcast_to(sym, (n[2], n[1], n[0]))
+    return g
+
+
+def _offset(l, a, b, sa, sb):
+    """The cell offset l^{sa a, sb b}: l_a sa on axis a, l_b sb on axis b, 0 elsewhere."""
+    o = [0, 0, 0]
+    o[a] = sa * l[a]
+    o[b] = sb * l[b]
+    return o
+
+
+def _at(field, o):
+    """field[xi + o] for an offset o = (ox, oy, oz)."""
+    out = field
+    for d in range(3):
+        if o[d]:
+            out = shift(out, d, o[d])
+    return out
+
+
+# Sign pattern of App. A: for the matrix F^{ab}_l (a < b, or aa = the diagonal
+# matrix), the entry (c, d) is F_cd at xi + l^{s1 p, s2 q}; None = unshifted.
+def _pattern(pair):
+    if pair == "aa":
+        return {(0, 1): (0, 1, +1, +1), (0, 2): (0, 2, +1, +1), (1, 2): (1, 2, +1, +1),
+                (1, 0): (1, 0, +1, +1), (2, 0): (2, 0, +1, +1), (2, 1): (2, 1, +1, +1)}
+    if pair == (0, 1):
+        return {(0, 0): (0, 1, -1, -1), (1, 1): (0, 1, -1, -1), (2, 2): (0, 1, -1, -1),
+                (0, 2): (1, 2, -1, +1), (2, 0): (1, 2, -1, +1),
+                (1, 2): (0, 2, -1, +1), (2, 1): (0, 2, -1, +1)}
+    if pair == (0, 2):
+        return {(0, 0): (0, 2, -1, -1), (1, 1): (0, 2, -1, -1), (2, 2): (0, 2, -1, -1),
+                (0, 1): (1, 2, +1, -1), (1, 0): (1, 2, +1, -1),
+                (1, 2): (0, 1, -1, +1), (2, 1): (0, 1, -1, +1)}
+    if pair == (1, 2):
+        return {(0, 0): (1, 2, -1, -1), (1, 1): (1, 2, -1, -1), (2, 2): (1, 2, -1, -1),
+                (0, 1): (0, 2, +1, -1), (1, 0): (0, 2, +1, -1),
+                (0, 2): (0, 1, +1, -1), (2, 0): (0, 1, +1, -1)}
+    raise ValueError(pair)
+
+
+LSET = [(l1, l2, l3) for l3 in (0, 1) for l2 in (0, 1) for l1 in (0, 1)]
+
+
+def dfmg_F(F, pair, l):
+    """The deformation F^{pair}_l[xi] [3, 3, ...] of App. A for pair = "aa" or (a, b), a < b."""
+    out = np.array(F, copy=True)
+    for (c, d), (p, q, sp, sq) in _pattern(pair).items():
+        out[c, d] = _at(F[c, d], _offset(l, p, q, sp, sq))
+    return out
+
+
+def dfmg_stress(F, law):
+    """DFMG stress (eq. constitutive_law): P_ab[xi] = 1/8 sum_l (P^{ab}_l(F^{ab}_l[xi]))_ab.
+    law(Fm, cell_offset) returns the stress [3, 3, ...] of the laws of cells
+    xi + cell_offset evaluated at the field Fm."""
+    P = np.zeros_like(F)
+    for l in LSET:
+        Pd = law(dfmg_F(F, "aa", l), (0, 0, 0))
+        for a in range(3):
+            P[a, a] += Pd[a, a] / 8.0
+        for a, b in ((0, 1), (0, 2), (1, 2)):
+            Po = law(dfmg_F(F, (a, b), l), _offset(l, a, b, -1, -1))
+            P[a, b] += Po[a, b] / 8.0
+            P[b, a] += Po[b, a] / 8.0
+    return P
