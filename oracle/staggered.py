@@ -1,7 +1,7 @@
 """Staggered-grid finite differences and the doubly-fine material grid (DFMG) law
-(paper App. A).  Test infrastructure: only tests/ use it.  No solver and no GPU
-path use these operators yet; they are the first pinned pieces of that
-discretization.
+(paper App. A).  Test infrastructure: only tests/ use it.  It holds the
+operators, the DFMG law and a small-strain CG solve on them; the finite-strain
+Newton solve and a GPU path of this discretization do not exist yet.
 
 Fields are arrays [3, n3, n2, n1] (vectors) and [3, 3, n3, n2, n1] (tensors), x
 the last array axis, cell xi = (i, j, k) at array index [k, j, i].
@@ -101,8 +101,9 @@ def _at(field, o):
     return out
 
 
-# Sign pattern of App. A: for the matrix F^{ab}_l (a < b, or aa = the diagonal
-# matrix), the entry (c, d) is F_cd at xi + l^{s1 p, s2 q}; None = unshifted.
+# Sign pattern of App. A: in the matrix F^{ab}_l (a < b, or "aa" for the one of the
+# diagonal stresses), entry (c, d) -> (p, q, sp, sq) is F_cd at xi + l^{sp p, sq q};
+# entries not listed are F_cd[xi].
 def _pattern(pair):
     if pair == "aa":
         return {(0, 1): (0, 1, +1, +1), (0, 2): (0, 2, +1, +1), (1, 2): (1, 2, +1, +1),
@@ -147,3 +148,54 @@ def dfmg_stress(F, law):
             P[a, b] += Po[a, b] / 8.0
             P[b, a] += Po[b, a] / 8.0
     return P
+
+
+def linear_cells(phase, mats):
+    """Law callback for dfmg_stress: the small-strain isotropic law
+    sigma = lambda tr(eps) I + 2 mu eps, eps = sym(F - I), of cell xi + offset."""
+    mu = np.where(phase == 1, mats[1][0], mats[0][0])
+    lam = np.where(phase == 1, mats[1][1], mats[0][1])
+
+    def law(Fm, off):
+        m, la = _at(mu, off), _at(lam, off)
+        Hm = Fm - np.eye(3)[:, :, None, None, None]
+        eps = 0.5 * (Hm + np.swapaxes(Hm, 0, 1))
+        tr = eps[0, 0] + eps[1, 1] + eps[2, 2]
+        return la * tr * np.eye(3)[:, :, None, None, None] + 2.0 * m * eps
+    return law
+
+
+def solve_linear(phase, l, mats, Hbar, tol=1e-12, maxit=20000):
+    """Small-strain equilibrium on the staggered grid with the DFMG law: find the
+    periodic displacement U (zero mean) with Div P(I + Hbar + Grad U) = 0, by plain
+    CG on the symmetric positive semi-definite operator U -> -Div(P(I + Grad U) - P(I)).
+    Returns U, F = I + Hbar + Grad U, P and the mean stress per component."""
+    n = (phase.shape[2], phase.shape[1], phase.shape[0])
+    h = tuple(l[d] / n[d] for d in range(3))
+    law = linear_cells(phase, mats)
+    I = np.broadcast_to(np.eye(3)[:, :, None, None, None], (3, 3) + phase.shape)
+    P0 = dfmg_stress(np.array(I), law)
+
+    def A(U):
+        return -div(dfmg_stress(I + grad(U, h), law) - P0, h)
+
+    Fbar = I + np.asarray(Hbar)[:, :, None, None, None]
+    b = div(dfmg_stress(Fbar, law), h)
+    U = np.zeros((3,) + phase.shape)
+    r = b.copy()
+    p = r.copy()
+    rr = np.sum(r * r)
+    r0 = np.sqrt(rr)
+    it = 0
+    while r0 > 0 and np.sqrt(rr) > tol * r0 and it < maxit:
+        Ap = A(p)
+        alpha = rr / np.sum(p * Ap)
+        U += alpha * p
+        r -= alpha * Ap
+        rr_new = np.sum(r * r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+    F = Fbar + grad(U, h)
+    P = dfmg_stress(F, law)
+    return {"U": U, "F": F, "P": P, "Pbar": P.mean(axis=(2, 3, 4)), "iters": it}

@@ -172,3 +172,53 @@ def test_dfmg_equals_the_doubly_fine_grid_construction(n, seed):
     P = st.dfmg_stress(F, law_cells(phase, material.stress))
     ref = dfmg_by_geometry(F, phase, material.stress)
     assert np.abs(P - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_linear_operator_is_symmetric():
+    rng = np.random.default_rng(10)
+    n = (5, 4, 3)
+    phase = rng.integers(0, 2, size=(n[2], n[1], n[0]))
+    h = tuple(a / b for a, b in zip(L, n))
+    law = st.linear_cells(phase, MATS)
+    I = np.broadcast_to(np.eye(3)[:, :, None, None, None], (3, 3) + phase.shape)
+    P0 = st.dfmg_stress(np.array(I), law)
+    A = lambda U: -st.div(st.dfmg_stress(I + st.grad(U, h), law) - P0, h)
+    u, v = rng.normal(size=(2, 3) + phase.shape)
+    assert abs(np.sum(A(u) * v) - np.sum(u * A(v))) <= 1e-12 * abs(np.sum(A(u) * v))
+    assert np.sum(A(u) * u) > 0
+
+
+def test_linear_solve_homogeneous_is_uniform():
+    phase = np.zeros((3, 4, 5), int)
+    Hb = np.array([[0.01, 0.004, -0.002], [0.001, -0.006, 0.003], [0.005, -0.001, 0.008]])
+    r = st.solve_linear(phase, L, MATS, Hb)
+    mu, lam = MATS[0]
+    eps = 0.5 * (Hb + Hb.T)
+    ref = lam * np.trace(eps) * np.eye(3) + 2 * mu * eps
+    assert np.abs(r["U"]).max() <= 1e-14
+    assert np.abs(r["Pbar"] - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_linear_solve_of_a_shear_laminate_has_the_closed_form(seed):
+    """Layers normal to x (phase depends on i only) under H = gamma e2 (x) e1: only U_2(i)
+    moves; P_21 = mu_e F_21 on the edges x = i h1 with mu_e = (mu[i-1] + mu[i]) / 2 (DFMG
+    edge modulus); Div P = 0 makes P_21 uniform, and sum_i (F_21 - gamma) = 0 gives
+    P_21 = P_12 = gamma / mean_i(1 / mu_e), every other stress 0."""
+    rng = np.random.default_rng(seed)
+    n = (8, 3, 2)
+    layers = rng.integers(0, 2, size=n[0])
+    layers[:2] = (0, 1)
+    phase = np.broadcast_to(layers[None, None, :], (n[2], n[1], n[0])).copy()
+    gamma = 0.02
+    Hb = np.zeros((3, 3))
+    Hb[1, 0] = gamma
+    r = st.solve_linear(phase, L, MATS, Hb)
+    mu = np.where(layers == 1, MATS[1][0], MATS[0][0])
+    mu_e = 0.5 * (np.roll(mu, 1) + mu)
+    tau = gamma / np.mean(1.0 / mu_e)
+    assert abs(r["Pbar"][1, 0] - tau) <= 1e-10 * tau
+    assert abs(r["Pbar"][0, 1] - tau) <= 1e-10 * tau
+    assert np.abs(r["P"][1, 0] - tau).max() <= 1e-10 * tau
+    others = [(a, b) for a in range(3) for b in range(3) if (a, b) not in ((1, 0), (0, 1))]
+    assert max(np.abs(r["P"][a, b]).max() for a, b in others) <= 1e-10 * tau
