@@ -70,6 +70,23 @@ def cpu_cores_used(cpu_s, wall_s):
     return max(1, int(round(cpu_s / max(wall_s, 1e-9))))
 
 
+def host_cpu():
+    """CPU model (from /proc/cpuinfo) and the number of cores this process may use."""
+    model = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return model, nproc
+
+
 def cpu_baseline(ms, lc, sub=128, iters=3):
     """Time the FP64 oracle's CG iterations on a sub-block of the same workload."""
     from oracle import solver as osol
@@ -92,11 +109,14 @@ def cpu_baseline(ms, lc, sub=128, iters=3):
         pass
     wall, cpu = time.perf_counter() - t0, time.process_time() - c0
     nv = sub ** 3
-    return {"value": nv * iters / wall, "unit": "voxel-CG-iters/s", "cores": cpu_cores_used(cpu, wall),
-            "kind": "oracle",
-            "sample": "%d CG iterations of the FP64 numpy oracle on a %d^3 block of the same microstructure "
-                      "at the first load increment (%.1f s wall, host %s)" % (iters, sub, wall, platform.processor()
-                                                                             or platform.machine())}
+    model, nproc = host_cpu()
+    cores = cpu_cores_used(cpu, wall)
+    return {"value": nv * iters / wall, "unit": "voxel-CG-iters/s", "cores": cores,
+            "kind": "oracle", "host_cpu": model, "host_nproc": nproc,
+            "sample": "%d CG iterations of the FP64 numpy oracle (numpy FFT and einsum: one thread; %d core(s) "
+                      "busy on average) on a %d^3 block of the same microstructure, a cropped (not periodic) "
+                      "RVE, at the first load increment; %.1f s wall on %s, %d cores available"
+                      % (iters, cores, sub, wall, model, nproc)}
 
 
 def image_bench(combo, synth, ms, steps):
@@ -301,6 +321,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = combo.combo_profile_all(ctx) if not args.no_profile else {}
+    idle = combo.combo_profile_all_idle(ctx) if not args.no_profile else {}
     schedule = combo.combo_get_schedule(ctx)[0]
     combo.combo_profile_enable(ctx, False)
     n = ms.nvox
@@ -318,10 +339,16 @@ def main():
             continue
         avg = msec / cnt
         b = kernel_bytes(name, n, nspec, nc, 4)
+        # launches that did work; the launches of chunk iterations after the CG had
+        # finished return at once and are listed apart
         kernels[name] = {"ms_total": round(msec, 3), "launches": cnt, "avg_us": round(avg * 1e3, 2)}
+        if idle.get(name, (0, 0))[1]:
+            kernels[name]["idle_launches"] = idle[name][1]
+            kernels[name]["idle_ms_total"] = round(idle[name][0], 3)
         if b is not None:
             kernels[name]["GBps"] = round(b / (avg * 1e-3) / 1e9, 1)
             kernels[name]["bytes_per_launch"] = b
+            kernels[name]["frac"] = round(b / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     cg_kernels = {k: v for k, v in kernels.items() if "GBps" in v}
     if cg_kernels:
         dom = max(cg_kernels, key=lambda k: cg_kernels[k]["ms_total"])

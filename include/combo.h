@@ -293,8 +293,15 @@ enum combo_kernel {
     COMBO_K_COUNT = 12
 };
 int combo_profile_enable(combo_ctx* ctx, int enable);
-/* Accumulated milliseconds and number of timed launches of one kernel class. */
+/* Accumulated milliseconds and number of timed launches of one kernel class.
+ * CG iterations run in chunks (8, or graph_chunk) between host checks; the
+ * launches of a chunk's iterations after the one that finished the CG find it
+ * done and return at once.  Those are not counted here, so that ms_total /
+ * launches is the time of a launch that did its work. */
 int combo_profile_read(combo_ctx* ctx, int kernel, double* ms_total, long long* launches);
+/* The launches combo_profile_read leaves out: chunk iterations after the CG had
+ * finished (each returns at once). */
+int combo_profile_read_idle(combo_ctx* ctx, int kernel, double* ms_total, long long* launches);
 
 /* Batches of RVEs -----------------------------------------------------------
  * Many independent RVEs, each with its own grid, box, materials and

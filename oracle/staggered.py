@@ -152,7 +152,11 @@ def dfmg_stress(F, law):
 
 def linear_cells(phase, mats):
     """Law callback for dfmg_stress: the small-strain isotropic law
-    sigma = lambda tr(eps) I + 2 mu eps, eps = sym(F - I), of cell xi + offset."""
+    sigma = lambda tr(eps) I + 2 mu eps, eps = sym(F - I), of cell xi + offset.
+    Pure cells only (phase 0 or 1): composite cells have no law here."""
+    bad = (phase != 0) & (phase != 1)
+    if np.any(bad):
+        raise ValueError("linear_cells: phase ids other than 0 and 1 (%d cells)" % int(np.count_nonzero(bad)))
     mu = np.where(phase == 1, mats[1][0], mats[0][0])
     lam = np.where(phase == 1, mats[1][1], mats[0][1])
 
@@ -196,6 +200,8 @@ def solve_linear(phase, l, mats, Hbar, tol=1e-12, maxit=20000):
         p = r + (rr_new / rr) * p
         rr = rr_new
         it += 1
+    if r0 > 0 and np.sqrt(rr) > tol * r0:
+        raise RuntimeError("solve_linear: CG did not reach %g in %d iterations (%g)" % (tol, maxit, np.sqrt(rr) / r0))
     F = Fbar + grad(U, h)
     P = dfmg_stress(F, law)
     return {"U": U, "F": F, "P": P, "Pbar": P.mean(axis=(2, 3, 4)), "iters": it}

@@ -117,6 +117,7 @@ _SIGS = {
     "combo_apply_operator": (_I, [_P, _I, _P, _P, _I]),
     "combo_profile_enable": (_I, [_P, _I]),
     "combo_profile_read": (_I, [_P, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
+    "combo_profile_read_idle": (_I, [_P, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
     "combo_autotune": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "combo_set_schedule": (_I, [_P, _I, _I, _I]),
     "combo_get_schedule": (_I, [_P] + [ctypes.POINTER(_I)] * 6),
@@ -384,8 +385,20 @@ def combo_profile_read(ctx, kernel):
     return ms.value, nl.value
 
 
+def combo_profile_read_idle(ctx, kernel):
+    """(milliseconds, launches) of the launches that found the CG finished (left out above)."""
+    ms = ctypes.c_double()
+    nl = ctypes.c_longlong()
+    _check(ctx, load_library().combo_profile_read_idle(ctx, int(kernel), ctypes.byref(ms), ctypes.byref(nl)))
+    return ms.value, nl.value
+
+
 def combo_profile_all(ctx):
     return {name: combo_profile_read(ctx, k) for k, name in enumerate(KERNEL_NAMES)}
+
+
+def combo_profile_all_idle(ctx):
+    return {name: combo_profile_read_idle(ctx, k) for k, name in enumerate(KERNEL_NAMES)}
 
 
 def combo_autotune(ctx, precision):

@@ -111,11 +111,17 @@ struct combo_ctx {
 
     // per-kernel event timing
     bool profile = false;
-    struct ProfRec { int kernel; hipEvent_t start, stop; };
+    // iter: position of the launch's CG iteration in its chunk (-1 outside a chunk);
+    // launches of iterations after the one that finished the CG return at once and
+    // are counted apart (prof_idle_*), so the averages cover launches that did work
+    struct ProfRec { int kernel; hipEvent_t start, stop; int iter; };
     std::vector<ProfRec> prof_pending;
     std::vector<hipEvent_t> prof_pool;
+    int prof_iter = -1;
     double prof_ms[COMBO_K_COUNT] = {};
     long long prof_n[COMBO_K_COUNT] = {};
+    double prof_idle_ms[COMBO_K_COUNT] = {};
+    long long prof_idle_n[COMBO_K_COUNT] = {};
 };
 
 // A batch of independent RVEs solved together (each member is a full context

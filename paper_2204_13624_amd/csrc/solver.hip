@@ -167,7 +167,7 @@ hipEvent_t prof_event(combo_ctx* ctx) {
 
 int prof_begin(combo_ctx* ctx, int kernel) {
     if (!ctx->profile) return -1;
-    combo_ctx::ProfRec r{kernel, prof_event(ctx), prof_event(ctx)};
+    combo_ctx::ProfRec r{kernel, prof_event(ctx), prof_event(ctx), ctx->prof_iter};
     if (!r.start || !r.stop) return -1;
     (void)hipEventRecord(r.start, ctx->stream);
     ctx->prof_pending.push_back(r);
@@ -179,13 +179,19 @@ void prof_end(combo_ctx* ctx, int idx) {
     (void)hipEventRecord(ctx->prof_pending[idx].stop, ctx->stream);
 }
 
-// call after the stream has been synchronised
-void prof_harvest(combo_ctx* ctx) {
+// call after the stream has been synchronised; launches of a CG chunk's
+// iterations at positions >= work_iters found the CG finished and did no work
+void prof_harvest(combo_ctx* ctx, int work_iters = 1 << 30) {
     for (auto& r : ctx->prof_pending) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
-            ctx->prof_ms[r.kernel] += ms;
-            ctx->prof_n[r.kernel] += 1;
+            if (r.iter >= work_iters) {
+                ctx->prof_idle_ms[r.kernel] += ms;
+                ctx->prof_idle_n[r.kernel] += 1;
+            } else {
+                ctx->prof_ms[r.kernel] += ms;
+                ctx->prof_n[r.kernel] += 1;
+            }
         }
         ctx->prof_pool.push_back(r.start);
         ctx->prof_pool.push_back(r.stop);
@@ -518,10 +524,12 @@ int cg_solve(combo_ctx* ctx, double mu0, double kappa0, int& iters) {
         gr.iters = chunk;
     }
     const int max_rounds = ctx->opt.max_cg / chunk + 2;
+    int iter_before = -1;   // CG iterations done before the pending chunk (-1: no chunk pending)
     for (int round = 0; round < max_rounds; ++round) {
         HIP_OR_FAIL(hipMemcpyAsync(&ctx->hs->cg, ctx->cgst.p, sizeof(CGState), hipMemcpyDeviceToHost, ctx->stream));
         HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
-        prof_harvest(ctx);
+        prof_harvest(ctx, iter_before < 0 ? (1 << 30) : ctx->hs->cg.iter - iter_before);
+        iter_before = ctx->hs->cg.iter;
         if (verbose())
             fprintf(stderr, "[combo] cg iter %d  |r|/|b| %.3e  alpha %.3e  beta %.3e  done %d  status %d\n",
                     ctx->hs->cg.iter, std::sqrt(std::max(ctx->hs->cg.rho, 0.0) / std::max(ctx->hs->cg.rho0, 1e-300)),
@@ -531,7 +539,9 @@ int cg_solve(combo_ctx* ctx, double mu0, double kappa0, int& iters) {
             HIP_OR_FAIL(hipGraphLaunch(gr.exec, ctx->stream));
         } else {
             for (int k = 0; k < chunk; ++k) {
+                ctx->prof_iter = k;
                 int st = cg_iteration<T>(ctx, mu0, kappa0);
+                ctx->prof_iter = -1;
                 if (st) return st;
             }
         }
@@ -2334,6 +2344,8 @@ int combo_profile_enable(combo_ctx* ctx, int enable) {
     for (int k = 0; k < COMBO_K_COUNT; ++k) {
         ctx->prof_ms[k] = 0.0;
         ctx->prof_n[k] = 0;
+        ctx->prof_idle_ms[k] = 0.0;
+        ctx->prof_idle_n[k] = 0;
     }
     return COMBO_OK;
 }
@@ -2344,6 +2356,15 @@ int combo_profile_read(combo_ctx* ctx, int kernel, double* ms_total, long long* 
     prof_harvest(ctx);
     if (ms_total) *ms_total = ctx->prof_ms[kernel];
     if (launches) *launches = ctx->prof_n[kernel];
+    return COMBO_OK;
+}
+
+int combo_profile_read_idle(combo_ctx* ctx, int kernel, double* ms_total, long long* launches) {
+    if (!ctx || kernel < 0 || kernel >= COMBO_K_COUNT) return COMBO_E_INVAL;
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    prof_harvest(ctx);
+    if (ms_total) *ms_total = ctx->prof_idle_ms[kernel];
+    if (launches) *launches = ctx->prof_idle_n[kernel];
     return COMBO_OK;
 }
 

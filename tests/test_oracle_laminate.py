@@ -206,3 +206,32 @@ def test_backprojection_step_matches_algorithm():
     assert (a * mb).sum() == pytest.approx(0.5 * (beta0 + 0.7), abs=1e-15)
     perp = lambda v: v - (v * mb).sum() * mb
     assert np.abs(perp(a) - perp(a1)).max() <= 1e-15
+
+
+def test_stop_bound_holds_between_two_stopping_solves():
+    """The per-voxel bound the GPU back-projection parity test asserts holds between
+    two oracle solves of the same hard cases (extreme fractions, contrast 1000,
+    compression) that stop from different starts, and is tight (1e-12 of the
+    stress scale) in the median voxel."""
+    from laminate_bound import laminate_stop_bound
+    rng = np.random.default_rng(7)
+    nv = 512
+    c = np.where(rng.random(nv) < 0.5, rng.uniform(0.97, 0.999, nv), rng.uniform(0.001, 0.03, nv))
+    N = rng.normal(size=(3, nv))
+    N /= np.linalg.norm(N, axis=0)
+    mats = ((1.0, 2.0), (1000.0, 2000.0))
+    F = np.eye(3)[:, :, None] + rng.uniform(-0.45, 0.45, (3, 3, nv))
+    F[0, 0] -= 0.3
+    bad = np.linalg.det(np.moveaxis(F, -1, 0)) < 0.05
+    F[:, :, bad] = np.eye(3)[:, :, None]
+    Fv = np.moveaxis(F, -1, 0)
+    r = laminate.solve(Fv, c, N.T, mats[0], mats[1])
+    ok = r["status"] == laminate.STATUS_OK
+    assert ok.all()
+    r2 = laminate.solve(Fv, c, N.T, mats[0], mats[1], a_init=r["a"] * (1.0 + 1e-9))
+    bound = laminate_stop_bound(r, c, N.T, mats)
+    scale = np.abs(r["P"]).max()
+    diff = np.abs(r2["P"] - r["P"]).reshape(nv, 9).max(axis=1)
+    assert np.all(diff <= bound + 1e-12 * scale)
+    assert np.median(bound) <= 1e-12 * scale
+    assert diff.max() > 1e-10 * scale    # the cases are hard: a flat 1e-10 bound would not hold

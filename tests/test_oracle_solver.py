@@ -26,9 +26,10 @@ def rotation(rng):
     return q
 
 
-def exact_laminate(Fbar, phi, N, mats):
+def exact_laminate_layers(Fbar, phi, N, mats):
     """Rank-one laminate with inclusion fraction phi and normal N: traction
-    continuity solved by scipy, F+- built here from the Hadamard condition."""
+    continuity solved by scipy, F+- built here from the Hadamard condition.
+    Returns the (uniform) stresses of the inclusion and matrix layers."""
     N = np.asarray(N, float)
 
     def parts(a):
@@ -37,7 +38,11 @@ def exact_laminate(Fbar, phi, N, mats):
         return material.stress(Fp[None], *mats[1])[0], material.stress(Fm[None], *mats[0])[0]
 
     sol = optimize.root(lambda a: (parts(a)[0] - parts(a)[1]) @ N, np.zeros(3), method="hybr", tol=1e-15)
-    Pp, Pm = parts(sol.x)
+    return parts(sol.x)
+
+
+def exact_laminate(Fbar, phi, N, mats):
+    Pp, Pm = exact_laminate_layers(Fbar, phi, N, mats)
     return phi * Pp + (1 - phi) * Pm
 
 
@@ -92,6 +97,46 @@ def test_laminate_through_composite_columns_is_exact(n, interfaces):
     r = solver.solve(problem(ms), FBAR, TIGHT)
     ref = exact_laminate(FBAR, phi, np.eye(3)[0], MATS)
     assert np.abs(r["Pbar"] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,l,axis,interfaces", [
+    ((9, 2, 3), (1.0, 1.0, 1.0), 0, (-0.5 + 2.25 / 9, -0.5 + 6.5 / 9)),     # composite columns c = 0.75, 0.5
+    ((3, 7, 2), (1.0, 1.4, 1.0), 1, (-0.7 + 1.4 * 1.75 / 7, -0.7 + 1.4 * 4.9 / 7)),  # normal e2, c = 0.25, 0.9
+    ((2, 3, 9), (1.0, 1.0, 2.0), 2, (-1.0 + 2 * 1.25 / 9, -1.0 + 2 * 5.5 / 9)),   # normal e3, c = 0.75, 0.5
+])
+def test_phase_averages_equal_the_exact_layer_stresses(n, l, axis, interfaces):
+    """A planar laminate through composite columns is exact under ComBo, so the
+    stress is uniform in each layer and the phase averages (with c+ P+ and c- P-
+    counted inside the composite voxels, fractions away from 1/2) are the exact
+    layer stresses P+ and P-, not merely their mixture."""
+    ms = synth.layered(n, l, axis, interfaces)
+    cc = ms.c[ms.phase == 2]
+    assert ms.n_composite > 0 and np.abs(cc - 0.5).max() > 0.2
+    phi = float(ms.c.mean())
+    r = solver.solve(problem(ms), FBAR, TIGHT)
+    Pp, Pm = exact_laminate_layers(FBAR, phi, np.eye(3)[axis], MATS)
+    scale = max(np.abs(Pp).max(), np.abs(Pm).max())
+    assert np.abs(r["Pbar_phase"][0] - Pp).max() <= 1e-12 * scale
+    assert np.abs(r["Pbar_phase"][1] - Pm).max() <= 1e-12 * scale
+    # the layers really differ, so a swap of the phases or of c+ and c- would show
+    assert np.abs(Pp - Pm).max() > 0.1 * scale
+
+
+def test_phase_averages_recombine_to_the_mean_stress():
+    """v+ Pbar+ + v- Pbar- = n Pbar with the phase volumes v+ = #inclusion + sum c,
+    v- = #matrix + sum (1 - c): the volume weights of the composite voxels are
+    their own fractions (a swap of c+ and c- breaks this identity)."""
+    ms = _sphere8()
+    r = solver.solve(problem(ms), FBAR, TIGHT)
+    comp = ms.phase == 2
+    vp = np.count_nonzero(ms.phase == 1) + ms.c[comp].sum()
+    vm = np.count_nonzero(ms.phase == 0) + (1.0 - ms.c[comp]).sum()
+    assert vp + vm == pytest.approx(ms.nvox, rel=1e-14)
+    Pp, Pm = r["Pbar_phase"]
+    lhs = vp * Pp + vm * Pm
+    assert np.abs(lhs - ms.nvox * r["Pbar"]).max() <= 1e-12 * ms.nvox * np.abs(r["Pbar"]).max()
+    # inclusion 10x stiffer under stretch: its average stress is the larger one
+    assert Pp[0, 0] > r["Pbar"][0, 0] > Pm[0, 0]
 
 
 def _sphere8():

@@ -222,3 +222,16 @@ def test_linear_solve_of_a_shear_laminate_has_the_closed_form(seed):
     assert np.abs(r["P"][1, 0] - tau).max() <= 1e-10 * tau
     others = [(a, b) for a in range(3) for b in range(3) if (a, b) not in ((1, 0), (0, 1))]
     assert max(np.abs(r["P"][a, b]).max() for a, b in others) <= 1e-10 * tau
+
+
+def test_linear_cells_and_solve_refuse_what_they_cannot_do():
+    """Composite cells (phase 2) have no law in the small-strain DFMG callback, and
+    a CG that stops at its iteration cap is an error, not a result."""
+    phase = np.zeros((3, 4, 5), np.uint8)
+    phase[1, 2, 3] = 2
+    with pytest.raises(ValueError):
+        st.linear_cells(phase, ((1.0, 2.0), (10.0, 20.0)))
+    phase[1, 2, 3] = 1
+    with pytest.raises(RuntimeError):
+        st.solve_linear(phase, (1.0, 1.0, 1.0), ((1.0, 2.0), (10.0, 20.0)),
+                               np.array([[0.0, 0.01, 0], [0.01, 0, 0], [0, 0, 0.0]]), maxit=2)
