@@ -223,6 +223,24 @@ int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, in
  * kept on the device. */
 int combo_set_microstructure_from_image(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, int s3, int method,
                                         int mem_kind);
+/* combo_image_to_boxels for callers that cannot allocate device memory (tight
+ * serving loops, code that must not call hipMalloc): the same kernels and
+ * outputs, with every intermediate buffer (counters, block offsets, composite
+ * list, packed fine words, moments) in one static device array of 64 MiB per
+ * GPU, held from the library's first use on that GPU until the process ends.
+ * No device or host memory is allocated by this call.  chi, phase, c and N are
+ * device pointers of the context's GPU (layouts as combo_image_to_boxels).
+ * Limits: 12 bytes per boxel (+ 8 more with s = (4, s2, s3), s2 s3 <= 16) plus
+ * 104 bytes per composite boxel must fit in the 64 MiB; a grid that does not
+ * fit is refused with COMBO_E_SIZE before any GPU work, and a composite count
+ * that does not fit with COMBO_E_SIZE after phase and c are written (N is then
+ * unspecified).  Every call on one GPU uses the same array and leaves its
+ * contents behind: calls that overlap in time on one GPU (from several host
+ * threads, or on several streams) race and must be serialised by the caller.
+ * Returns after the outputs are written (one host wait in the middle for the
+ * composite count). */
+int combo_image_to_boxels_static(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, int s3, int method,
+                                 uint8_t* phase, double* c, double* N);
 int combo_set_options(combo_ctx* ctx, const combo_options* opt);
 
 /* Solve HOM for the macroscopic deformation gradient Fbar (host, 9 doubles,

@@ -110,6 +110,7 @@ _SIGS = {
     "combo_get_grid": (_I, [_P] + [ctypes.POINTER(ctypes.c_int)] * 3 + [ctypes.POINTER(ctypes.c_double)] * 3),
     "combo_image_to_boxels": (_I, [_P, _P, _I, _I, _I, _I, _P, _P, _P, _I]),
     "combo_set_microstructure_from_image": (_I, [_P, _P, _I, _I, _I, _I, _I]),
+    "combo_image_to_boxels_static": (_I, [_P, _P, _I, _I, _I, _I, _P, _P, _P]),
     "combo_set_options": (_I, [_P, ctypes.POINTER(combo_options)]),
     "combo_solve": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(combo_stats), _I]),
     "combo_eval_law": (_I, [_P, _P, _P, _P, _P, _P, _I]),
@@ -294,6 +295,23 @@ def combo_image_to_boxels(ctx, chi, s, method=COMBO_NORMALS_LAPLACE, out=None):
     nn, k3 = _ptr(out[2], np.float64)
     _check(ctx, load_library().combo_image_to_boxels(ctx, cp, int(s[0]), int(s[1]), int(s[2]), int(method),
                                                      pp, cc, nn, _mem_kind(kind, k1, k2, k3)))
+    return out
+
+
+def combo_image_to_boxels_static(ctx, chi, s, out, method=COMBO_NORMALS_LAPLACE):
+    """combo_image_to_boxels into out = (phase, c, N), all device tensors, with the
+    library's static device scratch (no allocation in the library)."""
+    (n1, n2, n3), _ = combo_get_grid(ctx)
+    if tuple(chi.shape) != (n3 * s[2], n2 * s[1], n1 * s[0]):
+        raise ValueError("image shape %s does not match grid %s x boxel %s" % (tuple(chi.shape), (n1, n2, n3), tuple(s)))
+    cp, kind = _ptr(chi, np.uint8)
+    pp, k1 = _ptr(out[0], np.uint8)
+    cc, k2 = _ptr(out[1], np.float64)
+    nn, k3 = _ptr(out[2], np.float64)
+    if _mem_kind(kind, k1, k2, k3) != COMBO_MEM_DEVICE:
+        raise ValueError("combo_image_to_boxels_static takes device tensors only")
+    _check(ctx, load_library().combo_image_to_boxels_static(ctx, cp, int(s[0]), int(s[1]), int(s[2]), int(method),
+                                                            pp, cc, nn))
     return out
 
 

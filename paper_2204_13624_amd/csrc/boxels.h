@@ -27,6 +27,8 @@ struct BoxelArgs {
                                 // value is not 0/1
 };
 
+// Zero n ints (the counters before pass 1) with a kernel rather than a memset.
+hipError_t launch_boxel_zero(int* p, int n, hipStream_t s);
 // Pass 1, one thread per boxel: volume fraction and phase.
 hipError_t launch_boxel_count(const BoxelArgs& a, hipStream_t s);
 // Pass 2a: N = 0 for pure boxels, the ordered list of composite boxels (blockcnt: boxel_blocks(nb)

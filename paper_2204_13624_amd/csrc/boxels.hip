@@ -28,6 +28,11 @@ namespace combo {
 namespace {
 
 constexpr int kTeam = 16;
+
+__global__ void __launch_bounds__(256) k_boxel_zero(int* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
 constexpr int kPer = 4;    // fine voxels per lane and load round in pass 2
 
 __global__ void __launch_bounds__(256) k_boxel_count(BoxelArgs a) {
@@ -448,6 +453,12 @@ __global__ void __launch_bounds__(256) k_boxel_eigen(BoxelArgs a, const int* lis
 }
 
 }  // namespace
+
+hipError_t launch_boxel_zero(int* p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_boxel_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_boxel_count(const BoxelArgs& a, hipStream_t s) {
     const long long nb = (long long)a.n1 * a.n2 * a.n3;

@@ -1623,6 +1623,43 @@ double det9(const double* F) {
 }  // namespace
 
 // ==============================================================================
+// Static device scratch of combo_image_to_boxels_static.  Each GPU holds its own
+// copy of the array from the library's first use on it until the process ends.
+// In host code `scratch` only names the symbol: its device address on a GPU is
+// looked up once per device (static_scratch_setup, called by combo_create with
+// that device current) and only that address is passed to kernels.
+// ==============================================================================
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on `device` (the current device); 0 or a HIP error code
+hipError_t static_scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void* static_scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
+// ==============================================================================
 // C-ABI
 // ==============================================================================
 extern "C" {
@@ -1706,6 +1743,7 @@ int combo_create(combo_ctx** out, int device, void* stream) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return COMBO_E_HIP;
     if (std::string(prop.gcnArchName).find("gfx950") == std::string::npos) return COMBO_E_HIP;
+    if (static_scratch_setup(device) != hipSuccess) return COMBO_E_HIP;
     combo_ctx* ctx = new combo_ctx();
     ctx->device = device;
     ctx->lds_limit = prop.sharedMemPerBlock;
@@ -1871,12 +1909,15 @@ int combo_get_grid(const combo_ctx* ctx, int* n1, int* n2, int* n3, double* l1, 
     return COMBO_OK;
 }
 
-int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, int s3, int method, uint8_t* phase,
-                          double* c, double* N, int mem_kind) {
-    if (!ctx) return COMBO_E_INVAL;
+}  // extern "C"
+
+namespace {
+
+// checks shared by the image -> boxels entry points
+int boxel_check(combo_ctx* ctx, const void* chi, const void* phase, const void* c, const void* N, int s1, int s2,
+                int s3, int method) {
     if (!ctx->has_grid) return set_err(ctx, COMBO_E_STATE, "combo_set_grid has not been called");
     if (!chi || !phase || !c || !N) return set_err(ctx, COMBO_E_INVAL, "null image or output pointer");
-    if (mem_kind != COMBO_MEM_HOST && mem_kind != COMBO_MEM_DEVICE) return set_err(ctx, COMBO_E_INVAL, "bad mem_kind");
     if (s1 < 1 || s2 < 1 || s3 < 1 || s1 > 4096 || s2 > 4096 || s3 > 4096)
         return set_err(ctx, COMBO_E_INVAL, "fine voxels per boxel must be in [1, 4096]");
     if (method != COMBO_NORMALS_LAPLACE && method != COMBO_NORMALS_BARYCENTRE)
@@ -1885,11 +1926,61 @@ int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, in
     const long long N1 = (long long)g.n1 * s1, N2 = (long long)g.n2 * s2, N3 = (long long)g.n3 * s3;
     if ((double)N1 * (double)N2 * (double)N3 > 1.0e12 || (long long)s1 * s2 * s3 > (1LL << 30))
         return set_err(ctx, COMBO_E_INVAL, "image too large");
+    return COMBO_OK;
+}
+
+// argument block of the boxel kernels for device image and outputs (packed and counter left null)
+BoxelArgs boxel_args(const combo_ctx* ctx, const uint8_t* chi_d, int s1, int s2, int s3, int method, uint8_t* phase_d,
+                     double* c_d, double* N_d) {
+    const Grid& g = ctx->g;
+    BoxelArgs a{};
+    a.chi = chi_d;
+    a.N1 = (long long)g.n1 * s1;
+    a.N2 = (long long)g.n2 * s2;
+    a.N3 = (long long)g.n3 * s3;
+    a.n1 = g.n1;
+    a.n2 = g.n2;
+    a.n3 = g.n3;
+    a.s1 = s1;
+    a.s2 = s2;
+    a.s3 = s3;
+    a.h[0] = ctx->l[0] / (double)a.N1;
+    a.h[1] = ctx->l[1] / (double)a.N2;
+    a.h[2] = ctx->l[2] / (double)a.N3;
+    a.r[0] = a.h[1] * a.h[2] / a.h[0];
+    a.r[1] = a.h[0] * a.h[2] / a.h[1];
+    a.r[2] = a.h[0] * a.h[1] / a.h[2];
+    a.method = method;
+    a.vec4 = (s1 % 4 == 0) && (a.N1 % 4 == 0) && (reinterpret_cast<uintptr_t>(chi_d) % 4 == 0);
+    a.vec16 = (s1 == 4) && (g.n1 % 4 == 0) && (a.N1 % 16 == 0) && (reinterpret_cast<uintptr_t>(chi_d) % 16 == 0) &&
+              (reinterpret_cast<uintptr_t>(phase_d) % 4 == 0) && (reinterpret_cast<uintptr_t>(c_d) % 16 == 0);
+    a.phase = phase_d;
+    a.c = c_d;
+    a.N = N_d;
+    a.packed = nullptr;
+    a.counter = nullptr;
+    return a;
+}
+
+// pass 1 (counts, phases) needs packed fine words: the four-boxel path with s2 s3 <= 16
+bool boxel_wants_packed(const BoxelArgs& a) { return a.vec16 && (long long)a.s2 * a.s3 <= 16; }
+
+}  // namespace
+
+extern "C" {
+
+int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, int s3, int method, uint8_t* phase,
+                          double* c, double* N, int mem_kind) {
+    if (!ctx) return COMBO_E_INVAL;
+    if (mem_kind != COMBO_MEM_HOST && mem_kind != COMBO_MEM_DEVICE) return set_err(ctx, COMBO_E_INVAL, "bad mem_kind");
+    const int chk = boxel_check(ctx, chi, phase, c, N, s1, s2, s3, method);
+    if (chk != COMBO_OK) return chk;
     HIP_OR_FAIL(hipSetDevice(ctx->device));
+    const Grid& g = ctx->g;
     const long long nb = g.n;
-    const size_t img_bytes = (size_t)(N1 * N2 * N3);
+    const size_t img_bytes = (size_t)((long long)g.n1 * s1 * (long long)g.n2 * s2 * (long long)g.n3 * s3);
     DevBuf dchi, dphase, dc, dN;
-    DevBuf& scratch = ctx->bx_scratch;   // kept by the context: repeated calls allocate nothing new
+    DevBuf& bx = ctx->bx_scratch;   // kept by the context: repeated calls allocate nothing new
     const uint8_t* chi_d = chi;
     uint8_t* phase_d = phase;
     double* c_d = c;
@@ -1905,37 +1996,13 @@ int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, in
         c_d = static_cast<double*>(dc.p);
         N_d = static_cast<double*>(dN.p);
     }
-    HIP_OR_FAIL(scratch.ensure(sizeof(int) * (2 + (size_t)boxel_blocks(nb) + (size_t)nb)));
-    BoxelArgs a{};
-    a.chi = chi_d;
-    a.N1 = N1;
-    a.N2 = N2;
-    a.N3 = N3;
-    a.n1 = g.n1;
-    a.n2 = g.n2;
-    a.n3 = g.n3;
-    a.s1 = s1;
-    a.s2 = s2;
-    a.s3 = s3;
-    a.h[0] = ctx->l[0] / (double)N1;
-    a.h[1] = ctx->l[1] / (double)N2;
-    a.h[2] = ctx->l[2] / (double)N3;
-    a.r[0] = a.h[1] * a.h[2] / a.h[0];
-    a.r[1] = a.h[0] * a.h[2] / a.h[1];
-    a.r[2] = a.h[0] * a.h[1] / a.h[2];
-    a.method = method;
-    a.vec4 = (s1 % 4 == 0) && (N1 % 4 == 0) && (reinterpret_cast<uintptr_t>(chi_d) % 4 == 0);
-    a.vec16 = (s1 == 4) && (g.n1 % 4 == 0) && (N1 % 16 == 0) && (reinterpret_cast<uintptr_t>(chi_d) % 16 == 0) &&
-              (reinterpret_cast<uintptr_t>(phase_d) % 4 == 0) && (reinterpret_cast<uintptr_t>(c_d) % 16 == 0);
-    a.phase = phase_d;
-    a.c = c_d;
-    a.N = N_d;
-    a.packed = nullptr;
-    if (a.vec16 && (long long)s2 * s3 <= 16) {
+    HIP_OR_FAIL(bx.ensure(sizeof(int) * (2 + (size_t)boxel_blocks(nb) + (size_t)nb)));
+    BoxelArgs a = boxel_args(ctx, chi_d, s1, s2, s3, method, phase_d, c_d, N_d);
+    if (boxel_wants_packed(a)) {
         HIP_OR_FAIL(ctx->bx_packed.ensure(sizeof(uint64_t) * (size_t)nb));
         a.packed = static_cast<uint64_t*>(ctx->bx_packed.p);
     }
-    a.counter = static_cast<int*>(scratch.p);
+    a.counter = static_cast<int*>(bx.p);
     HIP_OR_FAIL(hipMemsetAsync(a.counter, 0, 2 * sizeof(int), ctx->stream));
     {
         ProfScope ps(ctx, COMBO_K_BOXEL_COUNT);
@@ -1961,6 +2028,74 @@ int combo_image_to_boxels(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, in
     HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
     prof_harvest(ctx);
     if (hcnt[1]) return set_err(ctx, COMBO_E_INVAL, "image values must be 0 or 1");
+    return COMBO_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------
+// image -> boxels without allocation: the counters, block offsets, composite
+// list, packed fine words and moments live in one static device array per GPU
+// ------------------------------------------------------------------------------
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// byte offsets of the pieces of the static scratch for nb boxels
+struct StaticBoxelLayout {
+    size_t blockcnt, list, packed, mom;
+};
+
+StaticBoxelLayout static_boxel_layout(long long nb, bool packed) {
+    StaticBoxelLayout L{};
+    L.blockcnt = 256;   // the two counters sit at offset 0
+    L.list = align256(L.blockcnt + sizeof(int) * (size_t)boxel_blocks(nb));
+    L.packed = align256(L.list + sizeof(int) * (size_t)nb);
+    L.mom = align256(L.packed + (packed ? sizeof(uint64_t) * (size_t)nb : 0));
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int combo_image_to_boxels_static(combo_ctx* ctx, const uint8_t* chi, int s1, int s2, int s3, int method,
+                                 uint8_t* phase, double* c, double* N) {
+    if (!ctx) return COMBO_E_INVAL;
+    const int chk = boxel_check(ctx, chi, phase, c, N, s1, s2, s3, method);
+    if (chk != COMBO_OK) return chk;
+    HIP_OR_FAIL(hipSetDevice(ctx->device));
+    char* base = static_cast<char*>(static_scratch_ptr(ctx->device));
+    if (!base) return set_err(ctx, COMBO_E_STATE, "the static scratch of this device was not set up");
+    const long long nb = ctx->g.n;
+    BoxelArgs a = boxel_args(ctx, chi, s1, s2, s3, method, phase, c, N);
+    const bool packed = boxel_wants_packed(a);
+    const StaticBoxelLayout L = static_boxel_layout(nb, packed);
+    if (L.mom > kStaticScratchBytes)
+        return set_err(ctx, COMBO_E_SIZE,
+                       "grid of " + std::to_string(nb) + " boxels needs " + std::to_string(L.mom) +
+                           " bytes of scratch before the moments; the static scratch holds " +
+                           std::to_string(kStaticScratchBytes));
+    a.counter = reinterpret_cast<int*>(base);
+    a.packed = packed ? reinterpret_cast<uint64_t*>(base + L.packed) : nullptr;
+    int* blockcnt = reinterpret_cast<int*>(base + L.blockcnt);
+    int* list = reinterpret_cast<int*>(base + L.list);
+    double* mom = reinterpret_cast<double*>(base + L.mom);
+    HIP_OR_FAIL(launch_boxel_zero(a.counter, 2, ctx->stream));
+    HIP_OR_FAIL(launch_boxel_count(a, ctx->stream));
+    HIP_OR_FAIL(launch_boxel_list(a, blockcnt, list, ctx->stream));
+    int hcnt[2] = {0, 0};
+    HIP_OR_FAIL(hipMemcpyAsync(hcnt, a.counter, sizeof(hcnt), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    if (hcnt[1]) return set_err(ctx, COMBO_E_INVAL, "image values must be 0 or 1");
+    const size_t need = L.mom + sizeof(double) * 13 * (size_t)hcnt[0];
+    if (need > kStaticScratchBytes)
+        return set_err(ctx, COMBO_E_SIZE,
+                       std::to_string(hcnt[0]) + " composite boxels need " + std::to_string(need) +
+                           " bytes of scratch with their moments; the static scratch holds " +
+                           std::to_string(kStaticScratchBytes) + " (phase and c are written, N is not)");
+    HIP_OR_FAIL(launch_boxel_normals(a, list, mom, hcnt[0], ctx->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
     return COMBO_OK;
 }
 
