@@ -61,6 +61,7 @@ class combo_options(ctypes.Structure):
         ("autotune", ctypes.c_int),
         ("line_search", ctypes.c_int),
         ("law", ctypes.c_int),
+        ("batch_streams", ctypes.c_int),
     ]
 
 

@@ -135,6 +135,7 @@ struct combo_batch {
     combo_options opt{};
     int disc = COMBO_DISC_MS;           // discretization of members added from now on
     std::vector<combo_ctx*> members;
+    std::vector<hipStream_t> lane_streams;   // streams of lanes 1.. (lane 0 runs on `stream`); owned
     combo::DevBuf scal;                 // [members] x kScalStride bytes: CGState at 0, sums at kScalSums
     char* hscal = nullptr;              // pinned host copy of scal
     size_t hscal_bytes = 0;

@@ -33,6 +33,8 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "combo.h"
@@ -797,7 +799,7 @@ int solve_impl(combo_ctx* ctx, const double Fbar[9], const double Fbar0[9], Solv
     double tol_cg = ctx->opt.tol_cg;
     if (sizeof(T) == 4) tol_cg = std::max(tol_cg, 1e-5);
     const int K = std::max(1, ctx->opt.n_increments);
-    hipMemsetAsync(ctx->a_prev.p, 0, sizeof(double) * 3 * std::max(ctx->nc, 1), ctx->stream);
+    HIP_OR_FAIL(hipMemsetAsync(ctx->a_prev.p, 0, sizeof(double) * 3 * std::max(ctx->nc, 1), ctx->stream));
     auto load = [&](double t, int c) { return Fbar0[c] + t * (Fbar[c] - Fbar0[c]); };
     double* Fc = ctx->F_cur.as<double>();
     double* Ft = ctx->F_trial.as<double>();
@@ -1055,6 +1057,7 @@ enum MemberPhase { PH_INC = 0, PH_RES, PH_CG, PH_STEP, PH_LSRES, PH_DONE, PH_FAI
 struct Member {
     combo_ctx* ctx = nullptr;
     int index = 0;
+    size_t slot = 0;   // position of the member's CG state and sums in the batch's scalar array
     double Fbar[9]{}, Fbar0[9]{};
     int K = 1;
     double mu0 = 0, kappa0 = 0, tol_cg = 0;
@@ -1292,11 +1295,11 @@ MatArgs<T> member_matargs(const Member& m) {
 // the launches of one tick: increment starts, Newton directions, material
 // updates, residuals (the CG chunk has its own cached plan)
 template <typename T>
-void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
-    hipStream_t s = B->stream;
+void plan_tick(std::vector<Member>& ms, const std::vector<int>& list, LaunchPlan& lp, hipStream_t s) {
     lp.clear();
     // F_save <- F at the start of a (sub)increment
-    for (Member& m : ms) {
+    for (int mi : list) {
+        Member& m = ms[mi];
         if (m.phase != PH_INC) continue;
         combo_ctx* ctx = m.ctx;
         void* dst = ctx->F_save.p;
@@ -1311,7 +1314,8 @@ void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
         std::vector<XArgs<double>> xa;
         std::vector<long long> kz, ky, kx;
         std::vector<int> nz, ny, nx;
-        for (Member& m : ms) {
+        for (int mi : list) {
+            Member& m = ms[mi];
             if (m.phase != PH_STEP || m.h != 0) continue;
             combo_ctx* ctx = m.ctx;
             ZArgs<double, T> z = zargs<double, T>(ctx, 1.0, 0.0);
@@ -1344,7 +1348,8 @@ void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
         std::vector<MatArgs<T>> ma;
         std::vector<MatReduceArgs> red;
         std::vector<TileMap> mp, ml;
-        for (Member& m : ms) {
+        for (int mi : list) {
+            Member& m = ms[mi];
             if (m.phase != PH_INC && m.phase != PH_STEP) continue;
             combo_ctx* ctx = m.ctx;
             const int i = (int)ma.size();
@@ -1380,7 +1385,8 @@ void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
         std::vector<FinArgs> fa;
         std::vector<long long> kx, ky, kz, ku;
         std::vector<int> nx, ny, nz, nu;
-        for (Member& m : ms) {
+        for (int mi : list) {
+            Member& m = ms[mi];
             if (m.phase != PH_RES && m.phase != PH_LSRES) continue;
             combo_ctx* ctx = m.ctx;
             XArgs<double> x = xargs<double>(ctx);
@@ -1420,8 +1426,7 @@ void plan_tick(combo_batch* B, std::vector<Member>& ms, LaunchPlan& lp) {
 
 // one CG iteration over the members listed (8 launches per kernel shape)
 template <typename T>
-void plan_cg(combo_batch* B, std::vector<Member>& ms, const std::vector<int>& list, LaunchPlan& lp) {
-    hipStream_t s = B->stream;
+void plan_cg(std::vector<Member>& ms, const std::vector<int>& list, LaunchPlan& lp, hipStream_t s) {
     lp.clear();
     std::vector<ZArgs<T, T>> zi, zf;
     std::vector<YArgs<T>> yi, yf;
@@ -1473,8 +1478,65 @@ void plan_cg(combo_batch* B, std::vector<Member>& ms, const std::vector<int>& li
     plan_finalize(lp, FIN_BETA, fbe, s);
 }
 
-// COMBO_BATCH_STATS=1 in the environment prints one line per batch solve: ticks,
-// host planning time, time waiting for the GPU, and members still active over time.
+// A lane: the members whose passes share launches, on a stream of their own.  Lanes
+// run their ticks independently (each on a host thread of its own), so members of
+// small grids with long Newton-CG chains progress at their own pace beside the
+// launches of larger grids instead of waiting for them every iteration.
+struct Lane {
+    std::vector<int> members;   // indices into the member list; their scalar slots are contiguous
+    size_t slot0 = 0;           // first scalar slot of the lane
+    hipStream_t stream = nullptr;
+    LaunchPlan tick, cgp;
+    std::vector<int> cg_list, cg_prev;
+    bool cg_valid = false;
+    hipGraph_t cg_graph = nullptr;
+    hipGraphExec_t cg_exec = nullptr;
+    int cg_same = 0;
+    int status = COMBO_OK;
+    std::string err;
+    long long ticks = 0, cg_ticks = 0, graph_ticks = 0, cg_rebuilds = 0;
+    double host_ms = 0.0, wait_ms = 0.0, wall_ms = 0.0;
+    Lane() = default;
+    Lane(const Lane&) = delete;
+    Lane& operator=(const Lane&) = delete;
+    void drop_graph() {
+        if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
+        if (cg_graph) (void)hipGraphDestroy(cg_graph);
+        cg_exec = nullptr;
+        cg_graph = nullptr;
+    }
+    ~Lane() { drop_graph(); }
+};
+
+// Members -> at most L lanes.  Members of one grid shape (n1, n2, n3, discretization)
+// share a lane; shapes are ordered by voxel count and cut into contiguous lanes of
+// about nm / L members each.  Returns member lists in ascending grid size.
+std::vector<std::vector<int>> assign_lanes(const std::vector<combo_ctx*>& mem, int L) {
+    const int nm = (int)mem.size();
+    std::vector<int> order(nm);
+    for (int i = 0; i < nm; ++i) order[i] = i;
+    auto key = [&](int i) {
+        const Grid& g = mem[i]->g;
+        return std::make_tuple(g.n, g.n1, g.n2, g.n3, g.disc);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
+    std::vector<std::vector<int>> shapes;
+    for (int k = 0; k < nm; ++k) {
+        if (k == 0 || key(order[k]) != key(order[k - 1])) shapes.emplace_back();
+        shapes.back().push_back(order[k]);
+    }
+    if ((int)shapes.size() <= L) return shapes;
+    std::vector<std::vector<int>> lanes;
+    const double target = (double)nm / L;
+    for (const auto& sh : shapes) {
+        if (lanes.empty() || ((double)lanes.back().size() >= target && (int)lanes.size() < L)) lanes.emplace_back();
+        for (int i : sh) lanes.back().push_back(i);
+    }
+    return lanes;
+}
+
+// COMBO_BATCH_STATS=1 in the environment prints one line per batch solve: per lane
+// its members, ticks, host time, time waiting for its stream and wall time.
 bool batch_stats() {
     static int v = -1;
     if (v < 0) {
@@ -1484,97 +1546,163 @@ bool batch_stats() {
     return v == 1;
 }
 
+// a HIP failure inside a lane: recorded in the lane (lanes run on threads of their own)
+#define LHIP_OR_FAIL(ln, ...)                                                                          \
+    do {                                                                                             \
+        hipError_t e__ = (__VA_ARGS__);                                                              \
+        if (e__ != hipSuccess) {                                                                     \
+            (ln).err = std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e__);                    \
+            return e__ == hipErrorOutOfMemory ? COMBO_E_NOMEM : COMBO_E_HIP;                         \
+        }                                                                                            \
+    } while (0)
+
+// Plans and enqueues one tick of a lane: its members' non-CG work, then a CG chunk
+// for the members in CG, then the copy of the lane's scalar slots to the host.
 template <typename T>
-int batch_solve_impl(combo_batch* B, std::vector<Member>& ms) {
+int lane_launch(combo_batch* B, std::vector<Member>& ms, Lane& ln, int chunk, bool use_graph) {
     const size_t stride = combo_batch::kScalStride;
-    const size_t nm = ms.size();
-    LaunchPlan tick, cgp;
-    std::vector<int> cg_list, cg_prev;
-    bool cg_valid = false;
-    // graph_chunk > 0: CG chunks of that many iterations, captured as a hipGraph once
-    // the set of members in CG has stayed the same for a tick, and replayed until it changes
-    const bool use_graph = B->opt.graph_chunk > 0;
-    const int chunk = use_graph ? B->opt.graph_chunk : 8;
-    hipGraph_t cg_graph = nullptr;
-    hipGraphExec_t cg_exec = nullptr;
-    int cg_same = 0;
-    long long graph_ticks = 0;
-    auto drop_graph = [&]() {
-        if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
-        if (cg_graph) (void)hipGraphDestroy(cg_graph);
-        cg_exec = nullptr;
-        cg_graph = nullptr;
-    };
-    long long ticks = 0, cg_ticks = 0, cg_rebuilds = 0;
-    double host_ms = 0.0, wait_ms = 0.0, tail_ms = 0.0;
-    const auto t_begin = clk::now();
-    for (;;) {
-        bool active = false;
-        for (Member& m : ms) active = active || (m.phase != PH_DONE && m.phase != PH_FAIL);
-        if (!active) break;
-        const auto t_plan = clk::now();
-        ++ticks;
-        plan_tick<T>(B, ms, tick);
-        BHIP_OR_FAIL(tick.upload(B->stream));
-        cg_list.clear();
-        for (size_t i = 0; i < nm; ++i)
-            if (ms[i].phase == PH_CG) cg_list.push_back((int)i);
-        if (!cg_list.empty() && (!cg_valid || cg_list != cg_prev)) {
-            drop_graph();
-            cg_same = 0;
-            plan_cg<T>(B, ms, cg_list, cgp);
-            BHIP_OR_FAIL(cgp.upload(B->stream));
-            cg_prev = cg_list;
-            cg_valid = true;
-            ++cg_rebuilds;
-        } else if (!cg_list.empty()) {
-            ++cg_same;
+    ++ln.ticks;
+    plan_tick<T>(ms, ln.members, ln.tick, ln.stream);
+    LHIP_OR_FAIL(ln, ln.tick.upload(ln.stream));
+    ln.cg_list.clear();
+    for (int i : ln.members)
+        if (ms[i].phase == PH_CG) ln.cg_list.push_back(i);
+    if (!ln.cg_list.empty() && (!ln.cg_valid || ln.cg_list != ln.cg_prev)) {
+        ln.drop_graph();
+        ln.cg_same = 0;
+        plan_cg<T>(ms, ln.cg_list, ln.cgp, ln.stream);
+        LHIP_OR_FAIL(ln, ln.cgp.upload(ln.stream));
+        ln.cg_prev = ln.cg_list;
+        ln.cg_valid = true;
+        ++ln.cg_rebuilds;
+    } else if (!ln.cg_list.empty()) {
+        ++ln.cg_same;
+    }
+    LHIP_OR_FAIL(ln, ln.tick.run());
+    if (!ln.cg_list.empty()) {
+        ++ln.cg_ticks;
+        if (use_graph && ln.cg_same >= 1 && !ln.cg_exec) {
+            LHIP_OR_FAIL(ln, hipStreamBeginCapture(ln.stream, hipStreamCaptureModeThreadLocal));
+            hipError_t ce = hipSuccess;
+            for (int k = 0; k < chunk && ce == hipSuccess; ++k) ce = ln.cgp.run();
+            hipError_t ee = hipStreamEndCapture(ln.stream, &ln.cg_graph);
+            LHIP_OR_FAIL(ln, ce);
+            LHIP_OR_FAIL(ln, ee);
+            LHIP_OR_FAIL(ln, hipGraphInstantiate(&ln.cg_exec, ln.cg_graph, nullptr, nullptr, 0));
         }
-        BHIP_OR_FAIL(tick.run());
-        if (!cg_list.empty()) {
-            ++cg_ticks;
-            if (use_graph && cg_same >= 1 && !cg_exec) {
-                BHIP_OR_FAIL(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-                hipError_t ce = hipSuccess;
-                for (int k = 0; k < chunk && ce == hipSuccess; ++k) ce = cgp.run();
-                hipError_t ee = hipStreamEndCapture(B->stream, &cg_graph);
-                BHIP_OR_FAIL(ce);
-                BHIP_OR_FAIL(ee);
-                BHIP_OR_FAIL(hipGraphInstantiate(&cg_exec, cg_graph, nullptr, nullptr, 0));
-            }
-            if (cg_exec) {
-                BHIP_OR_FAIL(hipGraphLaunch(cg_exec, B->stream));
-                ++graph_ticks;
-            } else {
-                for (int k = 0; k < chunk; ++k) BHIP_OR_FAIL(cgp.run());
-            }
-        }
-        BHIP_OR_FAIL(hipMemcpyAsync(B->hscal, B->scal.p, stride * nm, hipMemcpyDeviceToHost, B->stream));
-        const auto t_wait = clk::now();
-        host_ms += std::chrono::duration<double, std::milli>(t_wait - t_plan).count();
-        BHIP_OR_FAIL(hipStreamSynchronize(B->stream));
-        const double w = ms_since(t_wait);
-        wait_ms += w;
-        size_t live = 0;
-        for (Member& m : ms) live += (m.phase != PH_DONE && m.phase != PH_FAIL) ? 1 : 0;
-        if (live * 4 <= nm) tail_ms += w;   // GPU time while at most a quarter of the members are left
-        for (size_t i = 0; i < nm; ++i) {
-            Member& m = ms[i];
-            if (m.phase == PH_DONE || m.phase == PH_FAIL) continue;
-            const char* src = B->hscal + i * stride;
-            memcpy(&m.ctx->hs->cg, src, sizeof(CGState));
-            memcpy(m.ctx->hs->sums, src + combo_batch::kScalSums, sizeof(double) * kSumsLen);
-            int st = member_advance(m);
-            if (st) {
-                member_fail(m, st, m.ctx->err);
-            }
+        if (ln.cg_exec) {
+            LHIP_OR_FAIL(ln, hipGraphLaunch(ln.cg_exec, ln.stream));
+            ++ln.graph_ticks;
+        } else {
+            for (int k = 0; k < chunk; ++k) LHIP_OR_FAIL(ln, ln.cgp.run());
         }
     }
-    drop_graph();
-    if (batch_stats())
-        fprintf(stderr, "[combo] batch: %zu members, %lld ticks (%lld with CG, %lld from a graph, %lld CG plan rebuilds), "
-                        "host %.1f ms, GPU wait %.1f ms (%.1f ms with <= 1/4 of the members left), wall %.1f ms\n",
-                nm, ticks, cg_ticks, graph_ticks, cg_rebuilds, host_ms, wait_ms, tail_ms, ms_since(t_begin));
+    LHIP_OR_FAIL(ln, hipMemcpyAsync(B->hscal + ln.slot0 * stride, static_cast<char*>(B->scal.p) + ln.slot0 * stride,
+                                    stride * ln.members.size(), hipMemcpyDeviceToHost, ln.stream));
+    return COMBO_OK;
+}
+
+// host decisions of a lane whose tick has completed
+void lane_advance(combo_batch* B, std::vector<Member>& ms, Lane& ln) {
+    const size_t stride = combo_batch::kScalStride;
+    for (int i : ln.members) {
+        Member& m = ms[i];
+        if (m.phase == PH_DONE || m.phase == PH_FAIL) continue;
+        const char* src = B->hscal + m.slot * stride;
+        memcpy(&m.ctx->hs->cg, src, sizeof(CGState));
+        memcpy(m.ctx->hs->sums, src + combo_batch::kScalSums, sizeof(double) * kSumsLen);
+        int st = member_advance(m);
+        if (st) member_fail(m, st, m.ctx->err);
+    }
+}
+
+bool lane_active(const std::vector<Member>& ms, const Lane& ln) {
+    for (int i : ln.members)
+        if (ms[i].phase != PH_DONE && ms[i].phase != PH_FAIL) return true;
+    return false;
+}
+
+// One lane from start to finish: tick, wait for it on the lane's stream, decide,
+// until every member of the lane is done or failed.  Lanes share no member and
+// write disjoint ranges of the scalar arrays, so each runs on a host thread of
+// its own.
+template <typename T>
+int lane_run(combo_batch* B, std::vector<Member>& ms, Lane& ln, int chunk, bool use_graph) {
+    const auto t_begin = clk::now();
+    while (lane_active(ms, ln)) {
+        const auto t0 = clk::now();
+        const int st = lane_launch<T>(B, ms, ln, chunk, use_graph);
+        if (st) {
+            ln.status = st;
+            break;
+        }
+        const auto t1 = clk::now();
+        ln.host_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+        const hipError_t e = hipStreamSynchronize(ln.stream);
+        const auto t2 = clk::now();
+        ln.wait_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
+        if (e != hipSuccess) {
+            ln.err = std::string("batch lane: ") + hipGetErrorString(e);
+            ln.status = COMBO_E_HIP;
+            break;
+        }
+        lane_advance(B, ms, ln);
+        ln.host_ms += ms_since(t2);
+    }
+    (void)hipStreamSynchronize(ln.stream);   // nothing of the lane is left in flight, on error as on success
+    ln.drop_graph();
+    ln.wall_ms = ms_since(t_begin);
+    return ln.status;
+}
+
+template <typename T>
+int batch_solve_impl(combo_batch* B, std::vector<Member>& ms, std::vector<Lane>& lanes) {
+    const size_t nm = ms.size();
+    // graph_chunk > 0: CG chunks of that many iterations, captured as a hipGraph once
+    // the set of a lane's members in CG has stayed the same for a tick, and replayed until it changes
+    const bool use_graph = B->opt.graph_chunk > 0;
+    const int chunk = use_graph ? B->opt.graph_chunk : 8;
+    const bool stats = batch_stats();
+    (void)verbose();   // initialise the environment switches before the lanes' threads read them
+    const auto t_begin = clk::now();
+    const int dev = B->device;
+    std::vector<std::thread> threads;
+    for (size_t l = 1; l < lanes.size(); ++l) {
+        try {
+            threads.emplace_back([&, l]() {
+                if (hipSetDevice(dev) != hipSuccess) {
+                    lanes[l].status = COMBO_E_HIP;
+                    lanes[l].err = "hipSetDevice failed in a batch lane";
+                    return;
+                }
+                lane_run<T>(B, ms, lanes[l], chunk, use_graph);
+            });
+        } catch (...) {
+            lanes[l].status = COMBO_E_HIP;
+            lanes[l].err = "could not start the host thread of a batch lane";
+        }
+    }
+    if (!lanes.empty()) lane_run<T>(B, ms, lanes[0], chunk, use_graph);
+    for (std::thread& t : threads) t.join();
+    for (Lane& ln : lanes)
+        if (ln.status) return bset_err(B, ln.status, ln.err);
+    if (stats) {
+        long long ticks = 0, cg_ticks = 0, graph_ticks = 0, rebuilds = 0;
+        std::string per;
+        char buf[128];
+        for (const Lane& ln : lanes) {
+            ticks += ln.ticks;
+            cg_ticks += ln.cg_ticks;
+            graph_ticks += ln.graph_ticks;
+            rebuilds += ln.cg_rebuilds;
+            snprintf(buf, sizeof(buf), " [%zu members, %lld ticks, host %.0f ms, wait %.0f ms, wall %.0f ms]",
+                     ln.members.size(), ln.ticks, ln.host_ms, ln.wait_ms, ln.wall_ms);
+            per += buf;
+        }
+        fprintf(stderr, "[combo] batch: %zu members in %zu lanes%s; %lld ticks (%lld with CG, %lld from a graph, %lld CG "
+                        "plan rebuilds), wall %.1f ms\n",
+                nm, lanes.size(), per.c_str(), ticks, cg_ticks, graph_ticks, rebuilds, ms_since(t_begin));
+    }
     return COMBO_OK;
 }
 
@@ -1583,7 +1711,8 @@ const char* options_error(const combo_options* o) {
     if (!(o->tol_newton > 0) || !(o->tol_cg > 0) || o->max_newton < 0 || o->max_cg < 1 || o->max_laminate < 0 ||
         o->max_laminate > 64 || o->n_increments < 1 || o->max_step_halvings < 0 || o->max_cutbacks < 0 ||
         o->graph_chunk < 0 || o->graph_chunk > 256 || o->autotune < 0 || o->autotune > 1 ||
-        o->line_search < 0 || o->line_search > 1 || (o->law != COMBO_LAW_NEO_HOOKE && o->law != COMBO_LAW_LINEAR))
+        o->line_search < 0 || o->line_search > 1 || (o->law != COMBO_LAW_NEO_HOOKE && o->law != COMBO_LAW_LINEAR) ||
+        o->batch_streams < 0 || o->batch_streams > 16)
         return "option out of range";
     return nullptr;
 }
@@ -1701,6 +1830,7 @@ void combo_default_options(combo_options* o) {
     o->autotune = 0;
     o->line_search = 1;
     o->law = COMBO_LAW_NEO_HOOKE;
+    o->batch_streams = 0;
 }
 
 int combo_check_size(int n) { return size_ok(n) ? COMBO_OK : COMBO_E_SIZE; }
@@ -2534,8 +2664,11 @@ int combo_batch_destroy(combo_batch* b) {
     if (!b) return COMBO_E_INVAL;
     (void)hipSetDevice(b->device);
     (void)hipStreamSynchronize(b->stream);
+    for (hipStream_t ls : b->lane_streams) (void)hipStreamSynchronize(ls);
     for (combo_ctx* m : b->members) combo_destroy(m);
     b->members.clear();
+    for (hipStream_t ls : b->lane_streams) (void)hipStreamDestroy(ls);
+    b->lane_streams.clear();
     b->scal.release();
     if (b->hscal) (void)hipHostFree(b->hscal);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
@@ -2618,13 +2751,33 @@ int combo_batch_solve(combo_batch* B, const double* Fbar, const int* n_increment
             if (st) return bset_err(B, st, "member " + std::to_string(i) + ": " + ctx->err);
         }
     }
+    // lanes: members of similar grid size share launches on a stream of their own
+    const int nlanes_max = B->opt.batch_streams > 0 ? B->opt.batch_streams : 4;
+    const std::vector<std::vector<int>> lane_members = assign_lanes(B->members, nlanes_max);
+    while (B->lane_streams.size() + 1 < lane_members.size()) {
+        hipStream_t ls = nullptr;
+        BHIP_OR_FAIL(hipStreamCreateWithFlags(&ls, hipStreamNonBlocking));
+        B->lane_streams.push_back(ls);
+    }
+    std::vector<Lane> lanes(lane_members.size());
+    std::vector<size_t> slot_of(nm);
+    {
+        size_t next = 0;
+        for (size_t l = 0; l < lanes.size(); ++l) {
+            lanes[l].members = lane_members[l];
+            lanes[l].slot0 = next;
+            lanes[l].stream = l == 0 ? B->stream : B->lane_streams[l - 1];
+            for (int i : lane_members[l]) slot_of[i] = next++;
+        }
+    }
     std::vector<Member> ms(nm);
     for (size_t i = 0; i < nm; ++i) {
         Member& m = ms[i];
         combo_ctx* ctx = B->members[i];
         m.ctx = ctx;
         m.index = (int)i;
-        char* base = static_cast<char*>(B->scal.p) + i * stride;
+        m.slot = slot_of[i];
+        char* base = static_cast<char*>(B->scal.p) + m.slot * stride;
         ctx->cgst.borrow(base, sizeof(CGState));
         ctx->sums.borrow(base + combo_batch::kScalSums, sizeof(double) * (kSumsLen + 16));
         for (int c = 0; c < 9; ++c) {
@@ -2644,7 +2797,13 @@ int combo_batch_solve(combo_batch* B, const double* Fbar, const int* n_increment
         m.k = 1;
         member_begin_increment(m);
     }
-    int st = B->opt.precision == COMBO_MIXED ? batch_solve_impl<float>(B, ms) : batch_solve_impl<double>(B, ms);
+    // the set-up above runs on the batch stream; the lanes start after it
+    BHIP_OR_FAIL(hipStreamSynchronize(B->stream));
+    for (size_t l = 0; l < lanes.size(); ++l)
+        for (int i : lanes[l].members) B->members[i]->stream = lanes[l].stream;
+    int st = B->opt.precision == COMBO_MIXED ? batch_solve_impl<float>(B, ms, lanes)
+                                             : batch_solve_impl<double>(B, ms, lanes);
+    for (combo_ctx* ctx : B->members) ctx->stream = B->stream;
     if (st) return st;
     // effective tangents, member by member
     for (Member& m : ms) {
