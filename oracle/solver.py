@@ -47,7 +47,7 @@ import dataclasses
 
 import numpy as np
 
-from . import laminate, material, spectral
+from . import laminate, material, spectral, staggered
 
 OK = 0
 E_NOCONV = -5
@@ -80,7 +80,8 @@ class Problem:
     N: np.ndarray       # [3, n3, n2, n1]
     mats: tuple         # ((mu-, lam-), (mu+, lam+))
     law: str = "neo_hooke"   # or "linear": small strain, P = sigma(sym(F - I))
-    disc: str = "ms"         # or "willot": rotated-scheme gradient (spectral.willot_frequencies)
+    disc: str = "ms"         # or "willot": rotated-scheme gradient (spectral.willot_frequencies);
+                             # or "staggered": staggered grid with the DFMG law (App. A, oracle.staggered)
 
     @property
     def shape(self):
@@ -126,7 +127,12 @@ def to_field(vox, shape):
 
 
 def evaluate(F, prob):
-    """Pointwise law on the whole field: P [3,3,...], A [n,9,9] and statistics."""
+    """Pointwise law on the whole field: P [3,3,...], A [n,9,9] and statistics
+    (staggered grid: the DFMG law and its term tangents, oracle.staggered.evaluate)."""
+    if prob.disc == "staggered":
+        if prob.law != "neo_hooke":
+            raise ValueError("the staggered-grid solve takes the finite-strain law")
+        return staggered.evaluate(F, prob)
     Fv = to_voxels(F)
     n = Fv.shape[0]
     phase = prob.phase.reshape(-1)
@@ -185,7 +191,10 @@ def _evaluate_linear(Fv, prob, phase, Pv, Av, stats):
 
 
 def apply_tangent(Av, p, shape):
-    """(A : p) as a field, A [n,9,9] per voxel."""
+    """(A : p) as a field, A [n,9,9] per voxel (a dict of DFMG term tangents on the
+    staggered grid)."""
+    if isinstance(Av, dict):
+        return staggered.tangent_action(Av, p)
     pv = to_voxels(p).reshape(-1, 9)
     return to_field(np.einsum("nab,nb->na", Av, pv).reshape(-1, 3, 3), shape)
 
@@ -197,9 +206,19 @@ def inner_c0(x, y, mu0, kappa0):
     return float(mu0 * np.sum(x * y) + kappa0 * np.sum(trx * tr_y))
 
 
+def gamma0(tau, prob, mu0, kappa0):
+    """Gamma^0[tau] of the problem's discretization."""
+    if prob.disc == "staggered":
+        return staggered.apply_gamma0(tau, prob.n, prob.l, mu0, kappa0)
+    return spectral.apply_gamma0(tau, prob.n, prob.l, mu0, kappa0, prob.disc)
+
+
 def residual(P, prob):
     """eta = |G[P]|_2 / (sqrt(n) |Pbar|_F)."""
-    R = spectral.apply_g(P, prob.n, prob.l, prob.disc)
+    if prob.disc == "staggered":
+        R = staggered.apply_g(P, prob.n, prob.l)
+    else:
+        R = spectral.apply_g(P, prob.n, prob.l, prob.disc)
     Pbar = P.mean(axis=(2, 3, 4))
     den = np.sqrt(prob.nvox) * max(np.linalg.norm(Pbar), 1e-300)
     return float(np.linalg.norm(R) / den)
@@ -219,7 +238,7 @@ def cg(Av, b, prob, mu0, kappa0, tol, maxit):
     while True:
         if it >= maxit:
             raise SolveError(E_NOCONV, "CG did not converge in %d iterations" % maxit)
-        q = spectral.apply_gamma0(apply_tangent(Av, p, shape), prob.n, prob.l, mu0, kappa0, prob.disc)
+        q = gamma0(apply_tangent(Av, p, shape), prob, mu0, kappa0)
         gam = inner_c0(p, q, mu0, kappa0)
         if gam != gam:
             raise SolveError(E_NUMERIC, "CG breakdown: <p, q> = %r" % gam)
@@ -245,7 +264,7 @@ def effective_tangent(F, prob, opts, mu0, kappa0):
         E = np.zeros((3, 3) + tuple(shape))
         E[kL // 3, kL % 3] = 1.0
         tau = apply_tangent(Av, E, shape)
-        b = -spectral.apply_gamma0(tau, prob.n, prob.l, mu0, kappa0, prob.disc)
+        b = -gamma0(tau, prob, mu0, kappa0)
         try:
             dF, it = cg(Av, b, prob, mu0, kappa0, opts.tol_cg, opts.max_cg)
         except NegativeCurvature as e:
@@ -257,7 +276,10 @@ def effective_tangent(F, prob, opts, mu0, kappa0):
 
 def phase_averages(P, prob, lam_parts):
     """Volume-weighted averages of P over the inclusion (+) and matrix (-) phases,
-    counting c+ P+ and c- P- inside composite voxels."""
+    counting c+ P+ and c- P- inside composite voxels (staggered grid: computed by
+    the DFMG law over its doubly-fine cells)."""
+    if "Pphase" in lam_parts:
+        return lam_parts["Pphase"]
     Pv = to_voxels(P)
     phase = prob.phase.reshape(-1)
     sp = Pv[phase == 1].sum(axis=0)
@@ -318,7 +340,7 @@ def solve(prob, Fbar, opts=None, F_init=None):
                         break
                     if _ == opts.max_newton:
                         break
-                    b = -spectral.apply_gamma0(P, prob.n, prob.l, mu0, kappa0, prob.disc)
+                    b = -gamma0(P, prob, mu0, kappa0)
                     try:
                         dF, it = cg(Av, b, prob, mu0, kappa0, opts.tol_cg, opts.max_cg)
                     except NegativeCurvature as e:
