@@ -184,10 +184,23 @@ int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2,
  *   are projected out; an even n1 keeps its x-Nyquist plane.  Runs the same FFT
  *   passes with the rotated factors; combo_autotune tunes and caches its schedules
  *   separately ("mixed-willot" / "fp64-willot").  Batches: combo_batch_set_discretization.
+ * COMBO_DISC_STAGGERED: the staggered grid of the paper's appendix (App. A): the
+ *   displacement component U_a lives on the cell faces normal to e_a; F_aa (and P_aa)
+ *   at the cell centre from forward differences, F_ab (a != b) on the cell edge at the
+ *   lower corner in a and b from backward differences (eq. gradient_operator); the
+ *   material law is the doubly-fine material grid average (eq. constitutive_law):
+ *   each cell's eight doubly-fine cells evaluate the law of the cell (Neo-Hooke, or
+ *   the laminate with one solve per doubly-fine cell) at the deformation assembled
+ *   from the staggered values on their boundary.  Only the mean mode is projected
+ *   out.  Fields passed in or out (F_init, F_out, P_out, combo_eval_law,
+ *   combo_apply_green, combo_apply_operator) hold the staggered values: component
+ *   (a, b) at index xi is the value at cell xi's own position of that component.
+ *   Finite-strain law only; no effective tangent (want_tangent) and no batches.
  * Rebuilds the grid's frequency data like combo_set_grid and therefore resets the
  * microstructure: call after combo_set_grid, before combo_set_microstructure. */
 #define COMBO_DISC_MS 0
 #define COMBO_DISC_WILLOT 1
+#define COMBO_DISC_STAGGERED 2
 int combo_set_discretization(combo_ctx* ctx, int disc);
 /* The grid and box set by combo_set_grid (host only; COMBO_E_STATE before it). */
 int combo_get_grid(const combo_ctx* ctx, int* n1, int* n2, int* n3, double* l1, double* l2, double* l3);
@@ -256,7 +269,8 @@ int combo_solve(combo_ctx* ctx, const double Fbar[9], const double* F_init, doub
 
 /* Diagnostics used by the test-suite ------------------------------------- */
 /* Evaluate the pointwise law (Sec. 6.1 in pure voxels, Sec. 4 Alg. 1 + 2 in
- * composite voxels, cold start a = 0) at the field F [9][n].  Writes P [9][n]
+ * composite voxels, cold start a = 0) at the field F [9][n] (staggered grid: the
+ * DFMG law; A, a and iters must then be NULL).  Writes P [9][n]
  * (may be NULL), the tangent dP/dF A [81][n] (may be NULL; FP64), the jump
  * vector a [3][n] (may be NULL; 0 in pure voxels) and laminate updates
  * iters [n] (may be NULL; int32, 0 in pure voxels).  Also leaves the tangent

@@ -32,6 +32,7 @@ COMBO_GREEN_GAMMA0 = 0
 COMBO_GREEN_G = 1
 COMBO_DISC_MS = 0
 COMBO_DISC_WILLOT = 1
+COMBO_DISC_STAGGERED = 2
 COMBO_NORMALS_LAPLACE = 0
 COMBO_NORMALS_BARYCENTRE = 1
 COMBO_LAW_NEO_HOOKE = 0

@@ -53,9 +53,11 @@ struct Grid {
     double xs1, xs2, xs3; // 2 pi / l_d: xi_d(k) = xs_d * k
     int xm, xwbits;       // wavefront x pass: m values per lane, log2 of lanes per row (-1: none)
     int xv, yv, zv;       // schedule: variant of the x, y and z FFT passes (0 = default)
-    int disc;             // 0: Moulinec-Suquet frequencies, 1: Willot's rotated scheme
+    int disc;             // 0: Moulinec-Suquet frequencies, 1: Willot's rotated scheme, 2: staggered grid
     const double* ftab;   // disc 1: device table D1[nh] A1[nh] D2[n2] A2[n2] D3[n3] A3[n3]
-                          // (D1 = A1 = 0 on the padding x >= nkx: every padded mode is a zero mode)
+                          // (D1 = A1 = 0 on the padding x >= nkx: every padded mode is a zero mode);
+                          // disc 2: the same slots hold Re f_d and Im f_d of the forward-difference
+                          // symbol f_d = (e^{i theta} - 1) / h_d (0 on the padding)
 };
 
 // Position of voxel `vox` in the tangent-state arrays.  With the wavefront x
@@ -108,6 +110,17 @@ __device__ inline double fac_a3(const Grid& g, int j) { return g.disc ? g.ftab[2
 template <typename T>
 __device__ inline void stage_factors(T* dst, const double* src, int count, int tid, int nthreads) {
     for (int i = tid; i < count; i += nthreads) dst[i] = T(src[i]);
+}
+// Staggered grid (disc 2): forward-difference symbol of each axis at a stored index
+// (x: 0 <= k < nh, y and z: array index), complex, in the precision of the pass.
+template <typename T> __device__ inline cpx<T> fst1(const Grid& g, int k) {
+    return mk<T>(T(g.ftab[k]), T(g.ftab[g.nh + k]));
+}
+template <typename T> __device__ inline cpx<T> fst2(const Grid& g, int j) {
+    return mk<T>(T(g.ftab[2 * g.nh + j]), T(g.ftab[2 * g.nh + g.n2 + j]));
+}
+template <typename T> __device__ inline cpx<T> fst3(const Grid& g, int j) {
+    return mk<T>(T(g.ftab[2 * g.nh + 2 * g.n2 + j]), T(g.ftab[2 * g.nh + 2 * g.n2 + g.n3 + j]));
 }
 // true if index j is the Nyquist index of an even axis of length n
 __host__ __device__ inline bool is_nyquist(int j, int n) { return (n % 2 == 0) && (j == n / 2) && n > 1; }

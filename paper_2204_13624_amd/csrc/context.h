@@ -98,6 +98,9 @@ struct combo_ctx {
     int nc = 0;
     double n_mat = 0, n_incl = 0, sum_c = 0;
     combo::DevBuf slot, slot_s, comp_vox, comp_c, comp_N, a_prev, a_trial;   // slot: natural order, slot_s: state_pos order
+    // staggered grid with the DFMG law: stresses, tangent states and stress increments of the
+    // doubly-fine cells, the shifted-layout fields of the CG operator and a layout scratch field
+    combo::DevBuf dfmg_Pd, dfmg_Sd, dfmg_Ad, dfmg_dPd, dfmg_dH, dfmg_dQ, stag_tmp;
 
     // fields (FP64) and work buffers
     combo::DevBuf F_cur, F_trial, F_save, dF, P;

@@ -122,6 +122,7 @@ template <typename T, int MODE>
 __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int ntiles_) {
     using C = cpx<T>;
     if (MODE == X_CG && a.st->done) return;
+    if (MODE != X_CG && a.skip_done && a.st->done) return;
     extern __shared__ char smem_raw[];
     const int L = a.g.n1, nh = a.g.nh, nk = a.g.nkx, R = a.R;   // row stride, stored bins
     C* tw = reinterpret_cast<C*>(smem_raw);
@@ -150,7 +151,11 @@ __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int n
                 const int ca = 2 * s, cb = 2 * s + 1;
                 ha = a.in[ca * a.g.nspec + off];
                 if (s < 4) hb = a.in[cb * a.g.nspec + off];
-                if (a.g.disc) {
+                if (a.g.disc == 2) {
+                    const C f1 = fst1<T>(a.g, k);
+                    if (xi1_comp(ca)) ha = cmul(ha, f1);
+                    if (s < 4 && xi1_comp(cb)) hb = cmul(hb, f1);
+                } else if (a.g.disc) {
                     const T d1 = T(fac_d1(a.g, k)), a1 = T(fac_a1(a.g, k));
                     ha = cscale(ha, xi1_comp(ca) ? d1 : a1);
                     if (s < 4) hb = cscale(hb, xi1_comp(cb) ? d1 : a1);
@@ -258,6 +263,10 @@ __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int n
         const int ca = 2 * s, cb = 2 * s + 1;
         if (k >= nk) {   // row padding: zero modes
             ha = hb = mk<T>(0, 0);
+        } else if (a.g.disc == 2) {
+            const C f1c = cconj(fst1<T>(a.g, k));
+            if (xi1_comp(ca)) ha = cmul(ha, f1c);
+            if (xi1_comp(cb)) hb = cmul(hb, f1c);
         } else if (a.g.disc) {
             const T d1 = T(fac_d1(a.g, k)), a1 = T(fac_a1(a.g, k));
             ha = cscale(ha, xi1_comp(ca) ? d1 : a1);
@@ -766,9 +775,14 @@ __device__ __forceinline__ void k_ypass_fwd_body(const YArgs<T>& a, int tile_, i
             const int e = threadIdx.x + q * kBlock;
             if (e < items) {
                 const int y = e / TX, t = e - y * TX;
-                const T x2 = DISC ? T(fac_d2(a.g, y)) : xs2 * T(freq_of(y, L));
-                const C a0 = DISC ? cscale(acc[q], T(fac_a2(a.g, y))) : acc[q];
-                const C v = cadd(a0, cscale(buf[e], x2));
+                C v;
+                if (DISC == 2) {
+                    v = cadd(acc[q], cmul(buf[e], cconj(fst2<T>(a.g, y))));
+                } else {
+                    const T x2 = DISC ? T(fac_d2(a.g, y)) : xs2 * T(freq_of(y, L));
+                    const C a0 = DISC ? cscale(acc[q], T(fac_a2(a.g, y))) : acc[q];
+                    v = cadd(a0, cscale(buf[e], x2));
+                }
                 const int kx = kx0 + t;
                 if (kx < a.g.nh) a.out[i * a.g.nspec + ((long long)z * L + y) * a.g.nh + kx] = v;
             }
@@ -777,7 +791,7 @@ __device__ __forceinline__ void k_ypass_fwd_body(const YArgs<T>& a, int tile_, i
         y_load(a, buf, 3 * i + 2, z, kx0, TX);
         __syncthreads();
         fft_lds<-1, false, T>(buf, a.plan, TX, tw);
-        if (DISC) {
+        if (DISC == 1) {
             for (int e = threadIdx.x; e < items; e += kBlock) buf[e] = cscale(buf[e], T(fac_a2(a.g, e / TX)));
             __syncthreads();
         }
@@ -821,7 +835,7 @@ __device__ __forceinline__ void k_ypass_inv_body(const YArgs<T>& a, int tile_, i
                 const int y = e / TX, t = e - y * TX;
                 const int kx = kx0 + t;
                 av[q] = (kx < a.g.nh) ? a.in[i * a.g.nspec + ((long long)z * L + y) * a.g.nh + kx] : mk<T>(0, 0);
-                buf[e] = DISC ? cscale(av[q], T(fac_a2(a.g, y))) : av[q];
+                buf[e] = (DISC == 1) ? cscale(av[q], T(fac_a2(a.g, y))) : av[q];
             }
         }
         __syncthreads();
@@ -833,7 +847,8 @@ __device__ __forceinline__ void k_ypass_inv_body(const YArgs<T>& a, int tile_, i
             const int e = threadIdx.x + q * kBlock;
             if (e < items) {
                 const int y = e / TX;
-                buf[e] = cscale(av[q], DISC ? T(fac_d2(a.g, y)) : xs2 * T(freq_of(y, L)));
+                buf[e] = (DISC == 2) ? cmul(av[q], fst2<T>(a.g, y))
+                                     : cscale(av[q], DISC ? T(fac_d2(a.g, y)) : xs2 * T(freq_of(y, L)));
             }
         }
         __syncthreads();
@@ -842,7 +857,7 @@ __device__ __forceinline__ void k_ypass_inv_body(const YArgs<T>& a, int tile_, i
         __syncthreads();
         y_load(a, buf, 3 + i, z, kx0, TX);
         __syncthreads();
-        if (DISC) {
+        if (DISC == 1) {
             for (int e = threadIdx.x; e < items; e += kBlock) buf[e] = cscale(buf[e], T(fac_a2(a.g, e / TX)));
             __syncthreads();
         }
@@ -1000,6 +1015,76 @@ __device__ __forceinline__ void kmul(const Freq& f, double mu0, double kappa0, c
     }
 }
 
+// Staggered grid (disc 2): the complex forward-difference symbols f = (f1, f2, f3)
+// of one stored mode.  The displacement coefficients u of a compatible field give
+// its gradient in the shifted layout as H_hat_iJ = f_J u_i, and the reference
+// medium's acoustic tensor is K_ab = mu0 |f|^2 d_ab + kappa0 conj(f_a) f_b.
+struct FreqC {
+    double fr[3], fi[3];    // Re and Im of f_d
+    double s;               // |f|^2
+    bool zero;              // the mean, the only mode with f = 0: projected out
+    double w;               // Parseval weight of the half spectrum (1 or 2)
+};
+
+__device__ __forceinline__ FreqC freqc_k(const Grid& g, int ky, int kx, int z) {
+    FreqC f;
+    f.fr[0] = g.ftab[kx];
+    f.fi[0] = g.ftab[g.nh + kx];
+    f.fr[1] = g.ftab[2 * g.nh + ky];
+    f.fi[1] = g.ftab[2 * g.nh + g.n2 + ky];
+    f.fr[2] = g.ftab[2 * g.nh + 2 * g.n2 + z];
+    f.fi[2] = g.ftab[2 * g.nh + 2 * g.n2 + g.n3 + z];
+    f.s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) f.s += f.fr[d] * f.fr[d] + f.fi[d] * f.fi[d];
+    f.zero = !(f.s > 0.0);
+    f.w = (kx == 0 || 2 * kx == g.n1) ? 1.0 : 2.0;
+    return f;
+}
+
+__device__ __forceinline__ FreqC freqc_at(const Grid& g, long long m, int z) {
+    const int ky = (int)(m / g.nh);
+    return freqc_k(g, ky, (int)(m - (long long)ky * g.nh), z);
+}
+
+// w = K^{-1} v:  w = (v - theta conj(f) (f . v) / |f|^2) / (mu0 |f|^2), theta = kappa0 / (mu0 + kappa0)
+template <typename C, typename T>
+__device__ __forceinline__ void kinv_stag(const FreqC& f, T mu0, T kappa0, const C* v, C* w) {
+    T fvr = T(0), fvi = T(0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        fvr += T(f.fr[b]) * v[b].x - T(f.fi[b]) * v[b].y;
+        fvi += T(f.fr[b]) * v[b].y + T(f.fi[b]) * v[b].x;
+    }
+    const T s = T(f.s);
+    const T t = (kappa0 / (mu0 + kappa0)) / s;
+    const T inv = T(1) / (mu0 * s);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const T cr = T(f.fr[a]) * fvr + T(f.fi[a]) * fvi;    // conj(f_a) (f . v)
+        const T ci = T(f.fr[a]) * fvi - T(f.fi[a]) * fvr;
+        w[a].x = (v[a].x - t * cr) * inv;
+        w[a].y = (v[a].y - t * ci) * inv;
+    }
+}
+
+// K u (FP64), for the C0 inner products
+template <typename C>
+__device__ __forceinline__ void kmul_stag(const FreqC& f, double mu0, double kappa0, const C* u, double* kr,
+                                          double* ki) {
+    double fur = 0.0, fui = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        fur += f.fr[b] * double(u[b].x) - f.fi[b] * double(u[b].y);
+        fui += f.fr[b] * double(u[b].y) + f.fi[b] * double(u[b].x);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        kr[a] = mu0 * f.s * double(u[a].x) + kappa0 * (f.fr[a] * fur + f.fi[a] * fui);
+        ki[a] = mu0 * f.s * double(u[a].y) + kappa0 * (f.fr[a] * fui - f.fi[a] * fur);
+    }
+}
+
 // Per-frequency end of the forward z pass: given v = tau_hat xi at the frequency f
 // stored at idx (z M + m),
 //   Z_CG:   q = K^{-1} v / n, accumulate <p, q>_K = w Re(p^H v)/n
@@ -1070,6 +1155,63 @@ __device__ __forceinline__ void z_epilogue_at(const ZArgs<T, TU>& a, const ColFr
     z_epilogue<T, TU, MODE>(a, freq_z(a.g, cf, z), (long long)z * M + m, vv, s1, s2);
 }
 
+// z_epilogue of the staggered grid: the same modes with the complex acoustic tensor
+template <typename T, typename TU, int MODE>
+__device__ __forceinline__ void z_epilogue_stag(const ZArgs<T, TU>& a, const FreqC& f, long long idx,
+                                                const cpx<T>* vv, double& s1, double& s2) {
+    using C = cpx<T>;
+    using CU = cpx<TU>;
+    C w[3];
+    if (f.zero) {
+        w[0] = w[1] = w[2] = mk<T>(0, 0);
+    } else {
+        kinv_stag(f, T(a.mu0), T(a.kappa0), vv, w);
+    }
+    if (MODE == Z_CG) {
+        const T sc = T(a.inv_n);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            CU qi;
+            qi.x = TU(w[i].x * sc);
+            qi.y = TU(w[i].y * sc);
+            a.q[i * a.g.nspec + idx] = qi;
+            if (!f.zero) {
+                const CU pi = a.p[i * a.g.nspec + idx];
+                s1 += f.w * (double(pi.x) * double(vv[i].x) + double(pi.y) * double(vv[i].y)) * a.inv_n;
+            }
+        }
+    } else if (MODE == Z_RHS) {
+        CU b[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            b[i].x = TU(-w[i].x);
+            b[i].y = TU(-w[i].y);
+            a.r[i * a.g.nspec + idx] = b[i];
+            a.x[i * a.g.nspec + idx] = CU{TU(0), TU(0)};
+        }
+        if (!f.zero) {
+            double kr[3], ki[3];
+            kmul_stag(f, a.mu0, a.kappa0, b, kr, ki);
+            double bb = 0.0, vv2 = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                bb += double(b[i].x) * kr[i] + double(b[i].y) * ki[i];
+                vv2 += double(vv[i].x) * double(vv[i].x) + double(vv[i].y) * double(vv[i].y);
+            }
+            s1 += f.w * bb;
+            s2 += f.w * vv2 / f.s;
+        }
+    } else {  // Z_PROJ
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            CU o;
+            o.x = TU(w[i].x);
+            o.y = TU(w[i].y);
+            a.x[i * a.g.nspec + idx] = o;
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void z_load(const cpx<T>* in, const Grid& g, cpx<T>* buf, int comp, long long m0, int TX) {
     const long long M = (long long)g.n2 * g.nh;
@@ -1120,7 +1262,7 @@ __device__ __forceinline__ void k_zpass_fwd_body(const ZArgs<T, TU>& a, int tile
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int e = threadIdx.x + q * kBlock;
-            if (e < items) v[i][q] = DISC ? cscale(buf[e], T(fac_a3(a.g, e / TX))) : buf[e];
+            if (e < items) v[i][q] = (DISC == 1) ? cscale(buf[e], T(fac_a3(a.g, e / TX))) : buf[e];
         }
         __syncthreads();
         z_load<T>(a.in, a.g, buf, 3 + i, m0, TX);
@@ -1131,7 +1273,9 @@ __device__ __forceinline__ void k_zpass_fwd_body(const ZArgs<T, TU>& a, int tile
             const int e = threadIdx.x + q * kBlock;
             if (e < items) {
                 const int z = e / TX;
-                v[i][q] = cadd(v[i][q], cscale(buf[e], DISC ? T(fac_d3(a.g, z)) : xs3 * T(freq_of(z, L))));
+                v[i][q] = (DISC == 2)
+                              ? cadd(v[i][q], cmul(buf[e], cconj(fst3<T>(a.g, z))))
+                              : cadd(v[i][q], cscale(buf[e], DISC ? T(fac_d3(a.g, z)) : xs3 * T(freq_of(z, L))));
             }
         }
         __syncthreads();
@@ -1145,7 +1289,10 @@ __device__ __forceinline__ void k_zpass_fwd_body(const ZArgs<T, TU>& a, int tile
         const long long m = m0 + t;
         if (m >= M) continue;
         C vv[3] = {v[0][q], v[1][q], v[2][q]};
-        z_epilogue<T, TU, MODE>(a, freq_at(a.g, m, z), (long long)z * M + m, vv, s1, s2);
+        if (DISC == 2)
+            z_epilogue_stag<T, TU, MODE>(a, freqc_at(a.g, m, z), (long long)z * M + m, vv, s1, s2);
+        else
+            z_epilogue<T, TU, MODE>(a, freq_at(a.g, m, z), (long long)z * M + m, vv, s1, s2);
     }
     if (MODE == Z_CG || MODE == Z_RHS) {
         const double t1 = block_sum(s1, red);
@@ -1219,7 +1366,7 @@ __device__ __forceinline__ void k_zpass_inv_body(const ZArgs<T, TU>& a, int tile
                         u[q] = mk<T>(T(xi.x), T(xi.y));
                     }
                 }
-                buf[e] = DISC ? cscale(u[q], T(fac_a3(a.g, e / TX))) : u[q];
+                buf[e] = (DISC == 1) ? cscale(u[q], T(fac_a3(a.g, e / TX))) : u[q];
             }
         }
         __syncthreads();
@@ -1231,7 +1378,8 @@ __device__ __forceinline__ void k_zpass_inv_body(const ZArgs<T, TU>& a, int tile
             const int e = threadIdx.x + q * kBlock;
             if (e < items) {
                 const int z = e / TX;
-                buf[e] = cscale(u[q], DISC ? T(fac_d3(a.g, z)) : xs3 * T(freq_of(z, L)));
+                buf[e] = (DISC == 2) ? cmul(u[q], fst3<T>(a.g, z))
+                                     : cscale(u[q], DISC ? T(fac_d3(a.g, z)) : xs3 * T(freq_of(z, L)));
             }
         }
         __syncthreads();
@@ -1290,6 +1438,7 @@ __device__ __forceinline__ bool selfconj_plane(const Grid& g, int kx) { return k
 
 __device__ __forceinline__ bool herm_mode(const Grid& g, int kx, int ky, int z) {
     if (!g.disc) return false;
+    if (g.disc == 2) return true;   // staggered grid: coefficients of real fields, no phase carried
     if (kx != 0) return true;
     return is_nyquist(ky, g.n2) != is_nyquist(z, g.n3);
 }
@@ -1339,6 +1488,18 @@ __device__ __forceinline__ double rkr(const UArgs<TU>& a, const cpx<TU>* rr, con
     return f.w * t;
 }
 
+// w Re(r^H K r) at one frequency of the staggered grid
+template <typename TU>
+__device__ __forceinline__ double rkr_stag(const UArgs<TU>& a, const cpx<TU>* rr, const FreqC& f) {
+    if (f.zero) return 0.0;
+    double kr[3], ki[3];
+    kmul_stag(f, a.mu0, a.kappa0, rr, kr, ki);
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) t += double(rr[i].x) * kr[i] + double(rr[i].y) * ki[i];
+    return f.w * t;
+}
+
 // element e of the half spectrum (e < 2^31): row = z n2 + ky, kx
 __device__ __forceinline__ void split_index(const Grid& g, int e, int& z, int& ky, int& kx) {
     const int row = e / g.nh;
@@ -1365,7 +1526,7 @@ __device__ __forceinline__ void k_cg_update_body(const UArgs<TU>& a, int tile_, 
             cg_update_one(a, idx, alpha, r1);
 #pragma unroll
             for (int i = 0; i < 3; ++i) a.r[i * a.g.nspec + idx] = r1[i];
-            s += rkr(a, r1, freq_z(a.g, cf, z));
+            s += (a.g.disc == 2) ? rkr_stag(a, r1, freqc_k(a.g, ky, kx, z)) : rkr(a, r1, freq_z(a.g, cf, z));
             continue;
         }
         const long long idx2 = kx0_partner(a.g, M, z, ky) + kx;
@@ -1388,11 +1549,12 @@ __device__ __forceinline__ void k_cg_update_body(const UArgs<TU>& a, int tile_, 
                 a.r[i * a.g.nspec + idx2] = r2[i];
             }
             const int z2 = (a.g.n3 - z) % a.g.n3, ky2 = (a.g.n2 - ky) % a.g.n2;
-            s += rkr(a, r2, freq_z(a.g, col_freq_k(a.g, ky2, kx), z2));
+            s += (a.g.disc == 2) ? rkr_stag(a, r2, freqc_k(a.g, ky2, kx, z2))
+                                 : rkr(a, r2, freq_z(a.g, col_freq_k(a.g, ky2, kx), z2));
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) a.r[i * a.g.nspec + idx] = r1[i];
-        s += rkr(a, r1, freq_z(a.g, cf, z));
+        s += (a.g.disc == 2) ? rkr_stag(a, r1, freqc_k(a.g, ky, kx, z)) : rkr(a, r1, freq_z(a.g, cf, z));
     }
     const double tot = block_sum(s, red);
     if (threadIdx.x == 0) a.partials[tile_] = tot;
@@ -1928,14 +2090,14 @@ int fft2_tx(int L, int v) {
 
 template <typename T>
 int y_tile(const Grid& g) {
-    const int tx = fft2_tx<T>(g.n2, g.yv);
+    const int tx = g.disc == 2 ? 0 : fft2_tx<T>(g.n2, g.yv);   // the staggered grid runs the LDS passes
     if (tx) return tx;
     return std::max(1, std::min(g.nh, max_elems<T>() / g.n2));
 }
 
 template <typename T>
 int z_tile(const Grid& g) {
-    const int tx = fft2_tx<T>(g.n3, g.zv);
+    const int tx = g.disc == 2 ? 0 : fft2_tx<T>(g.n3, g.zv);
     if (tx) return tx;
     return (int)std::max<long long>(1, std::min<long long>((long long)g.n2 * g.nh, max_elems<T>() / g.n3));
 }
@@ -2026,7 +2188,9 @@ template <typename T>
 hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const BatchLaunch* b) {
     using XA = XArgs<T>;
     const long long nrows = (long long)a.g.n2 * a.g.n3;
-    if (mode == X_CG || mode == X_AVG) {
+    // the staggered grid transforms real fields only (its tangent action is a separate stencil)
+    if (a.g.disc == 2 && mode != X_FWD_REAL && mode != X_INV_REAL) return hipErrorInvalidValue;
+    if (a.g.disc != 2 && (mode == X_CG || mode == X_AVG)) {
         const int vv = xpass_lds_pick(a.g.n1, a.g.xv, std::is_same<T, float>::value);
 #define COMBO_XL_CASE(LL, PP, QQ, RR, VV)                                                                    \
         if constexpr (VV == 0 || std::is_same<T, float>::value) {                                            \
@@ -2093,6 +2257,12 @@ hipError_t launch_y(int dir, const YArgs<T>& a0, hipStream_t s, const BatchLaunc
     y_fill_tiles(a);
     const int nblk = a.g.n3 * a.ntile;
     const int vv = fft2_pick<T>(a.g.n2, a.g.yv);
+    if (a.g.disc == 2) {   // staggered grid: LDS Stockham passes with complex multipliers
+        const size_t lds2 = sizeof(cpx<T>) * ((size_t)a.g.n2 + (size_t)a.g.n2 * a.TX);
+        if (dir < 0) COMBO_LAUNCH(k_ypass_fwd, (T, 2), YA, nblk, kBlock, lds2);
+        else COMBO_LAUNCH(k_ypass_inv, (T, 2), YA, nblk, kBlock, lds2);
+        return hipGetLastError();
+    }
 #define COMBO_Y_CASE(TT, LL, PP, QQ, TXX, VV)                                                                   \
     if constexpr (std::is_same<T, TT>::value) {                                                               \
         if (a.g.n2 == LL && vv == VV) {                                                                        \
@@ -2125,6 +2295,17 @@ hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb, co
     const int nblk = blocks_z(a.g, a.TX);
     if (nb) *nb = nblk;
     const int vv = fft2_pick<T>(a.g.n3, a.g.zv);
+    if (a.g.disc == 2) {   // staggered grid: LDS Stockham passes with complex multipliers
+        const size_t lds2 = sizeof(cpx<T>) * ((size_t)a.g.n3 + (size_t)a.g.n3 * a.TX);
+        switch (mode) {
+            case Z_CG: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_CG, 2), ZA, nblk, kBlock, lds2); break;
+            case Z_RHS: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_RHS, 2), ZA, nblk, kBlock, lds2); break;
+            case Z_PROJ: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_PROJ, 2), ZA, nblk, kBlock, lds2); break;
+            case Z_INV_CG: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_CG, 2), ZA, nblk, kBlock, lds2); break;
+            default: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_PLAIN, 2), ZA, nblk, kBlock, lds2); break;
+        }
+        return hipGetLastError();
+    }
 #define COMBO_Z_CASE(TT, LL, PP, QQ, TXX, VV)                                                                  \
     if constexpr (std::is_same<T, TT>::value) {                                                              \
         if (a.g.n3 == LL && vv == VV) {                                                                       \

@@ -55,6 +55,7 @@ struct XArgs {
     double E[9];
     double* partials;           // X_AVG: [gridDim.x][9]
     const CGState* st;          // X_CG: skip when st->done
+    int skip_done;              // other modes: skip as well when st->done (CG operator of the staggered grid)
 };
 
 template <typename T>

@@ -29,62 +29,10 @@
 #include <hip/hip_runtime.h>
 
 #include "common.h"
+#include "laminate_point.h"
 #include "material.h"
 
 namespace combo {
-
-__device__ __forceinline__ double det3(const double* F) {
-    return F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) + F[2] * (F[3] * F[7] - F[4] * F[6]);
-}
-
-// adjugate: F^{-1} = adj(F) / det F
-__device__ __forceinline__ void adj3(const double* F, double* A) {
-    A[0] = F[4] * F[8] - F[5] * F[7];
-    A[1] = F[2] * F[7] - F[1] * F[8];
-    A[2] = F[1] * F[5] - F[2] * F[4];
-    A[3] = F[5] * F[6] - F[3] * F[8];
-    A[4] = F[0] * F[8] - F[2] * F[6];
-    A[5] = F[2] * F[3] - F[0] * F[5];
-    A[6] = F[3] * F[7] - F[4] * F[6];
-    A[7] = F[1] * F[6] - F[0] * F[7];
-    A[8] = F[0] * F[4] - F[1] * F[3];
-}
-
-// Neo-Hooke stress at F with a known J > 0: Finv, P and m = mu - lambda ln J
-__device__ __forceinline__ void nh_stress(const double* F, double J, double mu, double lam, double* Finv, double* P,
-                                          double& m) {
-    adj3(F, Finv);
-    const double iJ = 1.0 / J;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) Finv[i] *= iJ;
-    m = mu - lam * log(J);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int J2 = 0; J2 < 3; ++J2) P[3 * i + J2] = mu * F[3 * i + J2] - m * Finv[3 * J2 + i];
-}
-
-// small-strain isotropic stress of the displacement gradient F - I; Finv = I and
-// m = mu make the Neo-Hooke tangent formulas give the isotropic stiffness
-__device__ __forceinline__ void lin_stress(const double* F, double mu, double lam, double* Finv, double* P,
-                                           double& m) {
-    const double tr = F[0] + F[4] + F[8] - 3.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int J = 0; J < 3; ++J) {
-            const double e = 0.5 * (F[3 * i + J] + F[3 * J + i]) - (i == J ? 1.0 : 0.0);
-            P[3 * i + J] = 2.0 * mu * e + (i == J ? lam * tr : 0.0);
-            Finv[3 * i + J] = (i == J) ? 1.0 : 0.0;
-        }
-    m = mu;
-}
-
-// full tangent entry A_(iJ)(kL) of Neo-Hooke
-__device__ __forceinline__ double nh_tangent(const double* Finv, double mu, double lam, double m, int i, int J, int k,
-                                             int L) {
-    return ((i == k && J == L) ? mu : 0.0) + lam * Finv[3 * J + i] * Finv[3 * L + k] + m * Finv[3 * J + k] * Finv[3 * L + i];
-}
 
 // per-block reduction of NV doubles per thread into out[0..NV) (thread 0 writes)
 template <int NV>
@@ -198,163 +146,35 @@ __device__ __forceinline__ void k_material_laminate_body(const MatArgs<T>& a, in
         double N[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) N[d] = a.NN[(long long)d * a.nc + ic];
-        const double mup = a.mu[1], lamp = a.lam[1], mum = a.mu[0], lamm = a.lam[0];
-        const double floor_t = fmax(1e-3 * fmax(mup, mum), 1e-2 * fmax(lamp, lamm));
-
-        int status = 1;   // 0 ok, 1 iteration limit, 2 bad F_box, 3 inadmissible
-        int iters = 0, nbp = 0;
-        double a3[3] = {0.0, 0.0, 0.0};
-        double Pp[9], Pm[9], Fip[9], Fim[9], mp = 0.0, mm = 0.0;
-        const double Jb = det3(Fb);
-        double v[3] = {0, 0, 0}, mb[3] = {0, 0, 0}, bp = 0.0, bm = 0.0;
-        if (a.law == kLawLinear) {
-            // closed form: one exact Newton step from a = 0 (the traction jump is linear in a)
-            lin_stress(Fb, mup, lamp, Fip, Pp, mp);
-            lin_stress(Fb, mum, lamm, Fim, Pm, mm);
-            double f[3];
+        const double mats[4] = {a.mu[0], a.lam[0], a.mu[1], a.lam[1]};
+        double ainit[3];
+        if (a.warm) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
-                f[i] = (Pp[3 * i] - Pm[3 * i]) * N[0] + (Pp[3 * i + 1] - Pm[3 * i + 1]) * N[1] +
-                       (Pp[3 * i + 2] - Pm[3 * i + 2]) * N[2];
-            const double kp = (lamp + mup) / cp, km = (lamm + mum) / cm, d0 = mup / cp + mum / cm;
-            double D[6];
-            D[0] = d0 + (kp + km) * N[0] * N[0];
-            D[1] = (kp + km) * N[0] * N[1];
-            D[2] = (kp + km) * N[0] * N[2];
-            D[3] = d0 + (kp + km) * N[1] * N[1];
-            D[4] = (kp + km) * N[1] * N[2];
-            D[5] = d0 + (kp + km) * N[2] * N[2];
-            double Di[6], da[3];
-            sym3_inv(D, Di);
-            sym3_mul(Di, f, da);
-            double Fp[9], Fm[9];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                a3[i] = -da[i];
-#pragma unroll
-                for (int J = 0; J < 3; ++J) {
-                    const double aN = -da[i] * N[J];
-                    Fp[3 * i + J] = Fb[3 * i + J] + aN / cp;
-                    Fm[3 * i + J] = Fb[3 * i + J] - aN / cm;
-                }
-            }
-            lin_stress(Fp, mup, lamp, Fip, Pp, mp);
-            lin_stress(Fm, mum, lamm, Fim, Pm, mm);
-            status = 0;
-        } else if (!(Jb > 0.0)) {
-            status = 2;
-        } else {
-            double adjb[9];
-            adj3(Fb, adjb);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) v[i] = (adjb[0 + i] * N[0] + adjb[3 + i] * N[1] + adjb[6 + i] * N[2]) / Jb;
-            const double nv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) mb[i] = v[i] / nv;
-            bp = -cp / nv;
-            bm = cm / nv;
-            if (a.warm) {
-#pragma unroll
-                for (int i = 0; i < 3; ++i) a3[i] = a.a_prev[(long long)i * a.nc + ic];
-                const double b0 = a3[0] * mb[0] + a3[1] * mb[1] + a3[2] * mb[2];
-                if (!(bp < b0 && b0 < bm)) a3[0] = a3[1] = a3[2] = 0.0;
-            }
-            for (;;) {
-                const double av = a3[0] * v[0] + a3[1] * v[1] + a3[2] * v[2];
-                const double Jp = (1.0 + av / cp) * Jb, Jm = (1.0 - av / cm) * Jb;
-                if (!(Jp > 0.0 && Jm > 0.0)) {
-                    status = 3;
-                    break;
-                }
-                double Fp[9], Fm[9];
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int J = 0; J < 3; ++J) {
-                        const double aN = a3[i] * N[J];
-                        Fp[3 * i + J] = Fb[3 * i + J] + aN / cp;
-                        Fm[3 * i + J] = Fb[3 * i + J] - aN / cm;
-                    }
-                nh_stress(Fp, Jp, mup, lamp, Fip, Pp, mp);
-                nh_stress(Fm, Jm, mum, lamm, Fim, Pm, mm);
-                double tp[3], tm[3], f[3];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    tp[i] = Pp[3 * i] * N[0] + Pp[3 * i + 1] * N[1] + Pp[3 * i + 2] * N[2];
-                    tm[i] = Pm[3 * i] * N[0] + Pm[3 * i + 1] * N[1] + Pm[3 * i + 2] * N[2];
-                    f[i] = tp[i] - tm[i];
-                }
-                const double err = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-                const double ntp = sqrt(tp[0] * tp[0] + tp[1] * tp[1] + tp[2] * tp[2]);
-                const double ntm = sqrt(tm[0] * tm[0] + tm[1] * tm[1] + tm[2] * tm[2]);
-                if (!(err == err)) {
-                    status = 3;
-                    break;
-                }
-                if (err <= 1e-12 * fmax(fmax(ntp, ntm), floor_t)) {
-                    status = 0;
-                    break;
-                }
-                double gp[3], gm[3];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    gp[i] = Fip[i] * N[0] + Fip[3 + i] * N[1] + Fip[6 + i] * N[2];
-                    gm[i] = Fim[i] * N[0] + Fim[3 + i] * N[1] + Fim[6 + i] * N[2];
-                }
-                const double kp = (lamp + mp) / cp, km = (lamm + mm) / cm, d0 = mup / cp + mum / cm;
-                double D[6];   // symmetric: 00 01 02 11 12 22
-                D[0] = d0 + kp * gp[0] * gp[0] + km * gm[0] * gm[0];
-                D[1] = kp * gp[0] * gp[1] + km * gm[0] * gm[1];
-                D[2] = kp * gp[0] * gp[2] + km * gm[0] * gm[2];
-                D[3] = d0 + kp * gp[1] * gp[1] + km * gm[1] * gm[1];
-                D[4] = kp * gp[1] * gp[2] + km * gm[1] * gm[2];
-                D[5] = d0 + kp * gp[2] * gp[2] + km * gm[2] * gm[2];
-                double Di[6];
-                sym3_inv(D, Di);
-                double da[3];
-                sym3_mul(Di, f, da);
-                const double nda = sqrt(da[0] * da[0] + da[1] * da[1] + da[2] * da[2]);
-                const double na = sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
-                if (nda <= 1e-13 * fmax(na, 1e-3)) {
-                    status = 0;
-                    break;
-                }
-                if (iters >= a.maxit) break;
-                double a1[3] = {a3[0] - da[0], a3[1] - da[1], a3[2] - da[2]};
-                const double b1 = a1[0] * mb[0] + a1[1] * mb[1] + a1[2] * mb[2];
-                if (!(bp < b1 && b1 < bm)) {
-                    const double b0 = a3[0] * mb[0] + a3[1] * mb[1] + a3[2] * mb[2];
-                    const double bc = (b1 <= bp) ? bp : bm;
-                    const double bs = 0.5 * (b0 + bc);
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) a1[i] += (bs - b1) * mb[i];
-                    ++nbp;
-                }
-#pragma unroll
-                for (int i = 0; i < 3; ++i) a3[i] = a1[i];
-                ++iters;
-            }
+            for (int i = 0; i < 3; ++i) ainit[i] = a.a_prev[(long long)i * a.nc + ic];
         }
+        LamPoint o;
+        laminate_point(Fb, cp, N, mats, a.law, a.maxit, a.warm ? ainit : nullptr, o);
+        const int status = o.status;
         double Pb[9];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) Pb[c] = (status == 0) ? cp * Pp[c] + cm * Pm[c] : 0.0;
+        for (int c = 0; c < 9; ++c) Pb[c] = (status == 0) ? cp * o.Pp[c] + cm * o.Pm[c] : 0.0;
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
             a.P[c * a.n + vox] = Pb[c];
             sums[c] += Pb[c];
-            sums[9 + c] += (status == 0) ? cp * Pp[c] : 0.0;
-            sums[18 + c] += (status == 0) ? cm * Pm[c] : 0.0;
+            sums[9 + c] += (status == 0) ? cp * o.Pp[c] : 0.0;
+            sums[18 + c] += (status == 0) ? cm * o.Pm[c] : 0.0;
         }
         sums[27] += (status == 0) ? 0.0 : 1.0;
-        sums[28] += iters;
-        sums[29] += nbp;
-        sums[30] = fmax(sums[30], (double)iters);
+        sums[28] += o.iters;
+        sums[29] += o.nbp;
+        sums[30] = fmax(sums[30], (double)o.iters);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) a.a_out[(long long)i * a.nc + ic] = a3[i];
+        for (int i = 0; i < 3; ++i) a.a_out[(long long)i * a.nc + ic] = o.a[i];
         if (a.a_full)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) a.a_full[i * a.n + vox] = a3[i];
-        if (a.iters_full) a.iters_full[vox] = iters;
+            for (int i = 0; i < 3; ++i) a.a_full[i * a.n + vox] = o.a[i];
+        if (a.iters_full) a.iters_full[vox] = o.iters;
 
         // consistent tangent at the converged jump
         const bool want_state = (a.Acomp != nullptr) || (a.A_full != nullptr);
@@ -366,55 +186,8 @@ __device__ __forceinline__ void k_material_laminate_body(const MatArgs<T>& a, in
                 for (int r = 0; r < 81; ++r) a.A_full[(long long)r * a.n + vox] = 0.0;
             continue;
         }
-        double gp[3], gm[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            gp[i] = Fip[i] * N[0] + Fip[3 + i] * N[1] + Fip[6 + i] * N[2];
-            gm[i] = Fim[i] * N[0] + Fim[3 + i] * N[1] + Fim[6 + i] * N[2];
-        }
-        const double kp = (lamp + mp) / cp, km = (lamm + mm) / cm, d0 = mup / cp + mum / cm;
-        double D[6];
-        D[0] = d0 + kp * gp[0] * gp[0] + km * gm[0] * gm[0];
-        D[1] = kp * gp[0] * gp[1] + km * gm[0] * gm[1];
-        D[2] = kp * gp[0] * gp[2] + km * gm[0] * gm[2];
-        D[3] = d0 + kp * gp[1] * gp[1] + km * gm[1] * gm[1];
-        D[4] = kp * gp[1] * gp[2] + km * gm[1] * gm[2];
-        D[5] = d0 + kp * gp[2] * gp[2] + km * gm[2] * gm[2];
-        double Di[6];
-        sym3_inv(D, Di);
-        // dB_{k,(pq)} = B+_{k,(pq)} - B-_{k,(pq)}
-        double dB[27];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int p = 0; p < 3; ++p)
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    const double bpl = (k == p ? mup * N[q] : 0.0) + lamp * gp[k] * Fip[3 * q + p] + mp * gp[p] * Fip[3 * q + k];
-                    const double bmi = (k == p ? mum * N[q] : 0.0) + lamm * gm[k] * Fim[3 * q + p] + mm * gm[p] * Fim[3 * q + k];
-                    dB[9 * k + 3 * p + q] = bpl - bmi;
-                }
-        // W_{l,(pq)} = sum_k Dinv_lk dB_{k,(pq)}
-        double W[27];
-#pragma unroll
-        for (int r = 0; r < 9; ++r) {
-            const double b0 = dB[r], b1 = dB[9 + r], b2 = dB[18 + r];
-            W[r] = Di[0] * b0 + Di[1] * b1 + Di[2] * b2;
-            W[9 + r] = Di[1] * b0 + Di[3] * b1 + Di[4] * b2;
-            W[18 + r] = Di[2] * b0 + Di[4] * b1 + Di[5] * b2;
-        }
-        int idx = 0;
-        for (int r = 0; r < 9; ++r) {
-            const int i = r / 3, J = r % 3;
-            for (int s = (a.A_full ? 0 : r); s < 9; ++s) {
-                const int k = s / 3, L = s % 3;
-                const double corr = dB[r] * W[s] + dB[9 + r] * W[9 + s] + dB[18 + r] * W[18 + s];
-                const double val = cp * nh_tangent(Fip, mup, lamp, mp, i, J, k, L) +
-                                   cm * nh_tangent(Fim, mum, lamm, mm, i, J, k, L) - corr;
-                if (a.A_full) a.A_full[(long long)(9 * r + s) * a.n + vox] = val;
-                if (a.Acomp && s >= r) a.Acomp[(long long)ic * 45 + idx++] = T(val);
-            }
-        }
+        laminate_tangent<T>(o, cp, N, mats, a.Acomp ? a.Acomp + (long long)ic * 45 : nullptr,
+                            a.A_full ? a.A_full + vox : nullptr, a.n);
     }
     // block reduction: sums 0..29 added, 30 = max
     double out[31];

@@ -40,6 +40,7 @@
 #include "combo.h"
 #include "boxels.h"
 #include "context.h"
+#include "dfmg.h"
 
 using namespace combo;
 
@@ -211,6 +212,24 @@ struct ProfScope {
 // ------------------------------------------------------------------------------
 // work buffers
 // ------------------------------------------------------------------------------
+// laminate points (warm-start slots): one per composite voxel, eight per composite cell
+// on the staggered grid (its doubly-fine cells)
+size_t lam_points(const combo_ctx* ctx) {
+    return (ctx->g.disc == COMBO_DISC_STAGGERED ? 8 : 1) * (size_t)std::max(ctx->nc, 1);
+}
+
+// staggered grid: fields at the caller's boundary hold the staggered values at each
+// cell's own positions; inside, off-diagonal components are shifted (dfmg.h)
+int to_shifted(combo_ctx* ctx, const double* src, double* dst) {
+    HIP_OR_FAIL(launch_stag_shift(src, dst, ctx->g.n1, ctx->g.n2, ctx->g.n3, +1, ctx->stream));
+    return COMBO_OK;
+}
+int to_natural(combo_ctx* ctx, const double* src, double* dst) {
+    HIP_OR_FAIL(launch_stag_shift(src, dst, ctx->g.n1, ctx->g.n2, ctx->g.n3, -1, ctx->stream));
+    return COMBO_OK;
+}
+bool staggered(const combo_ctx* ctx) { return ctx->g.disc == COMBO_DISC_STAGGERED; }
+
 int ensure_work(combo_ctx* ctx) {
     const long long n = ctx->g.n, ns = ctx->g.nspec;
     const size_t f9 = sizeof(double) * 9 * (size_t)n;
@@ -229,8 +248,18 @@ int ensure_work(combo_ctx* ctx) {
     HIP_OR_FAIL(ctx->Sinv.ensure(sizeof(double) * 9 * (size_t)n));
     HIP_OR_FAIL(ctx->sm.ensure(sizeof(double) * (size_t)n));
     HIP_OR_FAIL(ctx->Acomp.ensure(sizeof(double) * 45 * (size_t)std::max(ctx->nc, 1)));
-    HIP_OR_FAIL(ctx->a_prev.ensure(sizeof(double) * 3 * (size_t)std::max(ctx->nc, 1)));
-    HIP_OR_FAIL(ctx->a_trial.ensure(sizeof(double) * 3 * (size_t)std::max(ctx->nc, 1)));
+    HIP_OR_FAIL(ctx->a_prev.ensure(sizeof(double) * 3 * lam_points(ctx)));
+    HIP_OR_FAIL(ctx->a_trial.ensure(sizeof(double) * 3 * lam_points(ctx)));
+    if (ctx->g.disc == COMBO_DISC_STAGGERED) {
+        const size_t n8 = 8 * (size_t)n;
+        HIP_OR_FAIL(ctx->dfmg_Pd.ensure(sizeof(double) * 9 * n8));
+        HIP_OR_FAIL(ctx->dfmg_Sd.ensure(sizeof(double) * 10 * n8));
+        HIP_OR_FAIL(ctx->dfmg_Ad.ensure(sizeof(double) * 45 * 8 * (size_t)std::max(ctx->nc, 1)));
+        HIP_OR_FAIL(ctx->dfmg_dPd.ensure(sizeof(double) * 9 * n8));
+        HIP_OR_FAIL(ctx->dfmg_dH.ensure(f9));
+        HIP_OR_FAIL(ctx->dfmg_dQ.ensure(f9));
+        HIP_OR_FAIL(ctx->stag_tmp.ensure(f9));
+    }
     // partial sums: the largest consumer over all kernels
     size_t np = 0;
     for (int prec = 0; prec < 2; ++prec) {
@@ -253,6 +282,8 @@ int ensure_work(combo_ctx* ctx) {
     np = std::max(np, (size_t)blocks_u(ctx->g));
     np = std::max(np, (size_t)material_blocks_pure(n) * 19);
     np = std::max(np, (size_t)material_blocks_laminate(ctx->nc) * 31);
+    np = std::max(np, (size_t)dfmg_blocks_pure(n) * 19);
+    np = std::max(np, (size_t)dfmg_blocks_laminate(ctx->nc) * 31);
     np = std::max(np, (size_t)2048 * 9);
     HIP_OR_FAIL(ctx->part1.ensure(sizeof(double) * np));
     HIP_OR_FAIL(ctx->part2.ensure(sizeof(double) * np));
@@ -364,10 +395,59 @@ FinArgs finargs(const combo_ctx* ctx, const double* p1, const double* p2, int co
     return f;
 }
 
+// Staggered grid: the DFMG law at F = F_old + s dF + dFbar (shifted layout) -> F_new,
+// P (shifted layout), the doubly-fine tangent states (precision T), a_trial; sums as material().
+template <typename T>
+int material_dfmg(combo_ctx* ctx, const double* F_old, const double* dF, double s, const double dFbar[9],
+                  double* F_new, bool cold) {
+    DfmgArgs<T> d{};
+    d.n1 = ctx->g.n1;
+    d.n2 = ctx->g.n2;
+    d.n3 = ctx->g.n3;
+    d.n = ctx->g.n;
+    d.nc = ctx->nc;
+    d.F_old = F_old;
+    d.dF = dF;
+    d.s = s;
+    for (int c = 0; c < 9; ++c) d.dFbar[c] = dFbar ? dFbar[c] : 0.0;
+    d.F_new = F_new;
+    d.slot = ctx->slot.as<int>();
+    d.comp_vox = ctx->comp_vox.as<int>();
+    d.cc = ctx->comp_c.as<double>();
+    d.NN = ctx->comp_N.as<double>();
+    d.a_prev = ctx->a_prev.as<double>();
+    d.a_out = ctx->a_trial.as<double>();
+    d.warm = (!cold && ctx->opt.warm_start_laminate) ? 1 : 0;
+    d.maxit = ctx->opt.max_laminate;
+    for (int p = 0; p < 2; ++p) {
+        d.mu[p] = ctx->mats[p].mu;
+        d.lam[p] = ctx->mats[p].lambda;
+    }
+    d.Pd = ctx->dfmg_Pd.as<double>();
+    d.Sd = ctx->dfmg_Sd.as<T>();
+    d.Ad = ctx->dfmg_Ad.as<T>();
+    d.partials = ctx->part1.as<double>();
+    d.partials2 = ctx->part2.as<double>();
+    {
+        ProfScope ps(ctx, COMBO_K_MATERIAL);
+        HIP_OR_FAIL(launch_dfmg_update<T>(d, ctx->stream));
+        HIP_OR_FAIL(launch_dfmg_law<T>(d, ctx->sums.as<double>(), ctx->stream));
+        DfmgGatherArgs<double> ga{ctx->g.n1, ctx->g.n2, ctx->g.n3, ctx->g.n, d.Pd, ctx->P.as<double>(), nullptr};
+        HIP_OR_FAIL(launch_dfmg_gather<double>(ga, ctx->stream));
+    }
+    HIP_OR_FAIL(hipMemcpyAsync(ctx->hs->sums, ctx->sums.p, sizeof(double) * kSumsLen, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    prof_harvest(ctx);
+    ctx->state_prec = sizeof(T) == 4 ? COMBO_MIXED : COMBO_FP64;
+    return COMBO_OK;
+}
+
 // material law at F = F_old + s dF + dFbar -> F_trial, P, tangent state (precision T), a_trial.
 template <typename T>
 int material(combo_ctx* ctx, const double* F_old, const double* dF, double s, const double dFbar[9], double* F_new,
              bool cold, double* A_full, double* a_full, int* it_full) {
+    if (ctx->g.disc == COMBO_DISC_STAGGERED) return material_dfmg<T>(ctx, F_old, dF, s, dFbar, F_new, cold);
     MatArgs<T> m{};
     m.n = ctx->g.n;
     m.nc = ctx->nc;
@@ -457,7 +537,46 @@ int residual(combo_ctx* ctx, double mu0, double kappa0, double tol_cg, double& e
     return COMBO_OK;
 }
 
-// one CG iteration (8 launches)
+// The tangent action of the staggered grid on the spectrum in specB (after the y
+// inverse pass): inverse x pass to the shifted-layout field dH, per doubly-fine
+// cell A : dF, their DFMG sum dQ, forward x pass into specA.  Kernels skip once
+// the CG state says done.
+template <typename T>
+int stag_tangent_x(combo_ctx* ctx, hipStream_t s) {
+    XArgs<T> xi = xargs<T>(ctx);
+    xi.in = ctx->specB.as<cpx<T>>();
+    xi.real_out = ctx->dfmg_dH.as<double>();
+    xi.scale = 1.0;   // the 1/n of the operator is applied by the z pass
+    xi.skip_done = 1;
+    HIP_OR_FAIL(launch_x<T>(X_INV_REAL, xi, s));
+    DfmgActArgs<T> act{};
+    act.n1 = ctx->g.n1;
+    act.n2 = ctx->g.n2;
+    act.n3 = ctx->g.n3;
+    act.n = ctx->g.n;
+    act.dH = ctx->dfmg_dH.as<double>();
+    act.dPd = ctx->dfmg_dPd.as<T>();
+    act.slot = ctx->slot.as<int>();
+    act.Sd = ctx->dfmg_Sd.as<T>();
+    act.Ad = ctx->dfmg_Ad.as<T>();
+    for (int p = 0; p < 2; ++p) {
+        act.mu[p] = T(ctx->mats[p].mu);
+        act.lam[p] = T(ctx->mats[p].lambda);
+    }
+    act.st = ctx->cgst.as<CGState>();
+    HIP_OR_FAIL(launch_dfmg_action<T>(act, s));
+    DfmgGatherArgs<T> ga{ctx->g.n1, ctx->g.n2, ctx->g.n3, ctx->g.n, ctx->dfmg_dPd.as<T>(), ctx->dfmg_dQ.as<double>(),
+                         ctx->cgst.as<CGState>()};
+    HIP_OR_FAIL(launch_dfmg_gather<T>(ga, s));
+    XArgs<T> xf = xargs<T>(ctx);
+    xf.real_in = ctx->dfmg_dQ.as<double>();
+    xf.out = ctx->specA.as<cpx<T>>();
+    xf.skip_done = 1;
+    HIP_OR_FAIL(launch_x<T>(X_FWD_REAL, xf, s));
+    return COMBO_OK;
+}
+
+// one CG iteration (8 launches; 11 on the staggered grid)
 template <typename T>
 int cg_iteration(combo_ctx* ctx, double mu0, double kappa0) {
     hipStream_t s = ctx->stream;
@@ -471,10 +590,14 @@ int cg_iteration(combo_ctx* ctx, double mu0, double kappa0) {
         ProfScope ps(ctx, COMBO_K_YPASS_INV);
         HIP_OR_FAIL(launch_y<T>(+1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true), s));
     }
-    XArgs<T> xa = xargs<T>(ctx);
-    xa.in = ctx->specB.as<cpx<T>>();
-    xa.out = ctx->specA.as<cpx<T>>();
-    {
+    if (ctx->g.disc == COMBO_DISC_STAGGERED) {
+        ProfScope ps(ctx, COMBO_K_XPASS_CG);
+        const int st = stag_tangent_x<T>(ctx, s);
+        if (st) return st;
+    } else {
+        XArgs<T> xa = xargs<T>(ctx);
+        xa.in = ctx->specB.as<cpx<T>>();
+        xa.out = ctx->specA.as<cpx<T>>();
         ProfScope ps(ctx, COMBO_K_XPASS_CG);
         HIP_OR_FAIL(launch_x<T>(X_CG, xa, s));
     }
@@ -700,6 +823,10 @@ void apply_schedule(combo_ctx* ctx, const Schedule& sc) {
 }
 
 int autotune(combo_ctx* ctx, int precision) {
+    if (ctx->g.disc == COMBO_DISC_STAGGERED) {   // one schedule: the LDS Stockham passes
+        apply_schedule(ctx, Schedule{});
+        return COMBO_OK;
+    }
     const std::string key = tune_key(ctx, precision);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -799,7 +926,7 @@ int solve_impl(combo_ctx* ctx, const double Fbar[9], const double Fbar0[9], Solv
     double tol_cg = ctx->opt.tol_cg;
     if (sizeof(T) == 4) tol_cg = std::max(tol_cg, 1e-5);
     const int K = std::max(1, ctx->opt.n_increments);
-    HIP_OR_FAIL(hipMemsetAsync(ctx->a_prev.p, 0, sizeof(double) * 3 * std::max(ctx->nc, 1), ctx->stream));
+    HIP_OR_FAIL(hipMemsetAsync(ctx->a_prev.p, 0, sizeof(double) * 3 * lam_points(ctx), ctx->stream));
     auto load = [&](double t, int c) { return Fbar0[c] + t * (Fbar[c] - Fbar0[c]); };
     double* Fc = ctx->F_cur.as<double>();
     double* Ft = ctx->F_trial.as<double>();
@@ -1966,13 +2093,13 @@ int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2,
 int combo_set_discretization(combo_ctx* ctx, int disc) {
     if (!ctx) return COMBO_E_INVAL;
     if (!ctx->has_grid) return set_err(ctx, COMBO_E_STATE, "combo_set_grid has not been called");
-    if (disc != COMBO_DISC_MS && disc != COMBO_DISC_WILLOT)
-        return set_err(ctx, COMBO_E_INVAL, "disc must be COMBO_DISC_MS or COMBO_DISC_WILLOT");
+    if (disc != COMBO_DISC_MS && disc != COMBO_DISC_WILLOT && disc != COMBO_DISC_STAGGERED)
+        return set_err(ctx, COMBO_E_INVAL, "disc must be COMBO_DISC_MS, COMBO_DISC_WILLOT or COMBO_DISC_STAGGERED");
     const int n1 = ctx->g.n1, n2 = ctx->g.n2, n3 = ctx->g.n3;
     int st = combo_set_grid(ctx, n1, n2, n3, ctx->l[0], ctx->l[1], ctx->l[2]);
     if (st != COMBO_OK || disc == COMBO_DISC_MS) return st;
     Grid& g = ctx->g;
-    g.disc = COMBO_DISC_WILLOT;
+    g.disc = disc;
     g.nkx = n1 / 2 + 1;   // x frequencies 0 .. floor(n1/2): an even n1 keeps its Nyquist bin
     // Rows of nkx = 16 m + 1 values would start off the 128-byte lines that the y pass
     // reads in tiles of 16 columns; pad them to a multiple of 16 where that adds at
@@ -1981,8 +2108,10 @@ int combo_set_discretization(combo_ctx* ctx, int disc) {
     g.nh = (4 * (padded - g.nkx) <= g.nkx) ? padded : g.nkx;
     g.nspec = (long long)g.nh * n2 * n3;
     g.xwbits = -1;       // natural state order: the rotated scheme has no wavefront x pass
-    // D = (2/h) sin(theta/2), A = cos(theta/2); x: theta = 2 pi k / n1 (k >= 0), y and z:
-    // theta = 2 pi freq / n with freq in [-n/2, n/2); A = 0 exactly at |theta| = pi
+    // Rotated scheme: D = (2/h) sin(theta/2), A = cos(theta/2); x: theta = 2 pi k / n1 (k >= 0),
+    // y and z: theta = 2 pi freq / n with freq in [-n/2, n/2); A = 0 exactly at |theta| = pi.
+    // Staggered grid: D = Re f, A = Im f of f = (e^{i theta} - 1) / h = (cos theta - 1 + i sin theta) / h,
+    // written as -2 sin^2(theta/2) / h + i sin(theta) / h (sin theta = 0 exactly at |theta| = pi)
     const int ns[3] = {n1, n2, n3};
     const int len[3] = {g.nh, n2, n3};
     std::vector<double> tab;
@@ -1992,8 +2121,15 @@ int combo_set_discretization(combo_ctx* ctx, int disc) {
         for (int j = 0; j < len[d]; ++j) {
             const int f = (d == 0) ? j : freq_of(j, ns[d]);
             const long double half = 3.14159265358979323846264338327950288L * (long double)f / (long double)ns[d];
-            D[j] = (double)(2.0L / h * sinl(half));
-            A[j] = (2 * f == ns[d] || 2 * f == -ns[d]) ? 0.0 : (double)cosl(half);
+            const bool nyq = (2 * f == ns[d] || 2 * f == -ns[d]);
+            if (disc == COMBO_DISC_STAGGERED) {
+                const long double sh = sinl(half);
+                D[j] = (double)(-2.0L * sh * sh / h);
+                A[j] = nyq ? 0.0 : (double)(sinl(2.0L * half) / h);
+            } else {
+                D[j] = (double)(2.0L / h * sinl(half));
+                A[j] = nyq ? 0.0 : (double)cosl(half);
+            }
             if (d == 0 && j >= g.nkx) D[j] = A[j] = 0.0;   // row padding: zero modes
         }
         tab.insert(tab.end(), D.begin(), D.end());
@@ -2353,6 +2489,10 @@ int combo_solve(combo_ctx* ctx, const double Fbar[9], const double* F_init, doub
         if (stats) stats->status = COMBO_E_INADMISSIBLE;
         return set_err(ctx, COMBO_E_INADMISSIBLE, "det Fbar <= 0");
     }
+    if (staggered(ctx) && ctx->opt.law != COMBO_LAW_NEO_HOOKE)
+        return set_err(ctx, COMBO_E_INVAL, "the staggered grid takes the finite-strain law");
+    if (staggered(ctx) && ctx->opt.want_tangent && Abar)
+        return set_err(ctx, COMBO_E_INVAL, "no effective tangent on the staggered grid");
     HIP_OR_FAIL(hipSetDevice(ctx->device));
     const long long n = ctx->g.n;
     const size_t f9 = sizeof(double) * 9 * (size_t)n;
@@ -2366,8 +2506,13 @@ int combo_solve(combo_ctx* ctx, const double Fbar[9], const double* F_init, doub
                 }
             mean_field_host(F_init, n, Fbar0);
         }
-        st = copy_in(ctx, ctx->F_cur.p, F_init, f9, mem_kind);
-        if (st) return st;
+        if (staggered(ctx)) {
+            st = copy_in(ctx, ctx->stag_tmp.p, F_init, f9, mem_kind);
+            if (st || (st = to_shifted(ctx, ctx->stag_tmp.as<double>(), ctx->F_cur.as<double>()))) return st;
+        } else {
+            st = copy_in(ctx, ctx->F_cur.p, F_init, f9, mem_kind);
+            if (st) return st;
+        }
         if (mem_kind == COMBO_MEM_DEVICE) {
             const int nb = 1024;
             hipLaunchKernelGGL(k_colsum9, dim3(nb), dim3(256), 0, ctx->stream, ctx->F_cur.as<double>(), n,
@@ -2409,11 +2554,22 @@ int combo_solve(combo_ctx* ctx, const double Fbar[9], const double* F_init, doub
     }
     if (Aptr) memcpy(Abar, Atmp, sizeof(Atmp));
     if (F_out) {
-        st = copy_out(ctx, F_out, ctx->F_cur.p, f9, mem_kind);
+        const void* src = ctx->F_cur.p;
+        if (staggered(ctx)) {
+            if ((st = to_natural(ctx, ctx->F_cur.as<double>(), ctx->stag_tmp.as<double>()))) return st;
+            src = ctx->stag_tmp.p;
+        }
+        st = copy_out(ctx, F_out, src, f9, mem_kind);
         if (st) return st;
     }
     if (P_out) {
-        st = copy_out(ctx, P_out, ctx->P.p, f9, mem_kind);
+        const void* src = ctx->P.p;
+        if (staggered(ctx)) {
+            // stream order: the copy of F_out above has read stag_tmp before it is rewritten
+            if ((st = to_natural(ctx, ctx->P.as<double>(), ctx->stag_tmp.as<double>()))) return st;
+            src = ctx->stag_tmp.p;
+        }
+        st = copy_out(ctx, P_out, src, f9, mem_kind);
         if (st) return st;
     }
     HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
@@ -2425,11 +2581,18 @@ int combo_eval_law(combo_ctx* ctx, const double* F, double* Pout, double* A, dou
     if (st) return st;
     if (!F) return set_err(ctx, COMBO_E_INVAL, "F is null");
     if (mem_kind != COMBO_MEM_HOST && mem_kind != COMBO_MEM_DEVICE) return set_err(ctx, COMBO_E_INVAL, "bad mem_kind");
+    if (staggered(ctx) && (A || a || iters))
+        return set_err(ctx, COMBO_E_INVAL, "the staggered grid's law returns P only (A, a and iters must be NULL)");
     HIP_OR_FAIL(hipSetDevice(ctx->device));
     const long long n = ctx->g.n;
     const size_t f9 = sizeof(double) * 9 * (size_t)n;
-    st = copy_in(ctx, ctx->F_save.p, F, f9, mem_kind);
-    if (st) return st;
+    if (staggered(ctx)) {
+        st = copy_in(ctx, ctx->stag_tmp.p, F, f9, mem_kind);
+        if (st || (st = to_shifted(ctx, ctx->stag_tmp.as<double>(), ctx->F_save.as<double>()))) return st;
+    } else {
+        st = copy_in(ctx, ctx->F_save.p, F, f9, mem_kind);
+        if (st) return st;
+    }
     DevBuf dA, da, dit;
     if (A) HIP_OR_FAIL(dA.ensure(sizeof(double) * 81 * (size_t)n));
     if (a) HIP_OR_FAIL(da.ensure(sizeof(double) * 3 * (size_t)n));
@@ -2441,7 +2604,12 @@ int combo_eval_law(combo_ctx* ctx, const double* F, double* Pout, double* A, dou
         st = material<double>(ctx, ctx->F_save.as<double>(), nullptr, 0.0, nullptr, ctx->F_trial.as<double>(), true,
                               dA.as<double>(), da.as<double>(), dit.as<int>());
     if (st) return st;
-    if (Pout && (st = copy_out(ctx, Pout, ctx->P.p, f9, mem_kind))) return st;
+    if (Pout && staggered(ctx)) {
+        if ((st = to_natural(ctx, ctx->P.as<double>(), ctx->stag_tmp.as<double>()))) return st;
+        if ((st = copy_out(ctx, Pout, ctx->stag_tmp.p, f9, mem_kind))) return st;
+    } else if (Pout && (st = copy_out(ctx, Pout, ctx->P.p, f9, mem_kind))) {
+        return st;
+    }
     if (A && (st = copy_out(ctx, A, dA.p, sizeof(double) * 81 * (size_t)n, mem_kind))) return st;
     if (a && (st = copy_out(ctx, a, da.p, sizeof(double) * 3 * (size_t)n, mem_kind))) return st;
     if (iters && (st = copy_out(ctx, iters, dit.p, sizeof(int) * (size_t)n, mem_kind))) return st;
@@ -2491,10 +2659,15 @@ int apply_operator_impl(combo_ctx* ctx, const double* p_dev, double* q_dev) {
     zi.out = ctx->specA.as<cpx<T>>();
     HIP_OR_FAIL(launch_z<T, T>(Z_INV_PLAIN, zi, ctx->stream));
     HIP_OR_FAIL(launch_y<T>(+1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true), ctx->stream));
-    XArgs<T> xa = xargs<T>(ctx);
-    xa.in = ctx->specB.as<cpx<T>>();
-    xa.out = ctx->specA.as<cpx<T>>();
-    HIP_OR_FAIL(launch_x<T>(X_CG, xa, ctx->stream));
+    if (staggered(ctx)) {
+        st = stag_tangent_x<T>(ctx, ctx->stream);
+        if (st) return st;
+    } else {
+        XArgs<T> xa = xargs<T>(ctx);
+        xa.in = ctx->specB.as<cpx<T>>();
+        xa.out = ctx->specA.as<cpx<T>>();
+        HIP_OR_FAIL(launch_x<T>(X_CG, xa, ctx->stream));
+    }
     HIP_OR_FAIL(launch_y<T>(-1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, true), ctx->stream));
     ZArgs<T, T> zc = zargs<T, T>(ctx, mu0, kappa0);
     zc.in = ctx->specB.as<cpx<T>>();
@@ -2534,10 +2707,20 @@ int combo_apply_green(combo_ctx* ctx, int which, int precision, const double* ta
     const size_t f9 = sizeof(double) * 9 * (size_t)ctx->g.n;
     int st = copy_in(ctx, ctx->F_save.p, tau, f9, mem_kind);
     if (st) return st;
-    if (precision == COMBO_MIXED) st = apply_green_impl<float>(ctx, which, ctx->F_save.as<double>(), ctx->dF.as<double>());
-    else st = apply_green_impl<double>(ctx, which, ctx->F_save.as<double>(), ctx->dF.as<double>());
+    const double* in_dev = ctx->F_save.as<double>();
+    if (staggered(ctx)) {
+        if ((st = to_shifted(ctx, ctx->F_save.as<double>(), ctx->stag_tmp.as<double>()))) return st;
+        in_dev = ctx->stag_tmp.as<double>();
+    }
+    if (precision == COMBO_MIXED) st = apply_green_impl<float>(ctx, which, in_dev, ctx->dF.as<double>());
+    else st = apply_green_impl<double>(ctx, which, in_dev, ctx->dF.as<double>());
     if (st) return st;
-    st = copy_out(ctx, out, ctx->dF.p, f9, mem_kind);
+    const void* res = ctx->dF.p;
+    if (staggered(ctx)) {
+        if ((st = to_natural(ctx, ctx->dF.as<double>(), ctx->stag_tmp.as<double>()))) return st;
+        res = ctx->stag_tmp.p;
+    }
+    st = copy_out(ctx, out, res, f9, mem_kind);
     if (st) return st;
     HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
     return COMBO_OK;
@@ -2555,10 +2738,20 @@ int combo_apply_operator(combo_ctx* ctx, int precision, const double* p, double*
     const size_t f9 = sizeof(double) * 9 * (size_t)ctx->g.n;
     st = copy_in(ctx, ctx->F_save.p, p, f9, mem_kind);
     if (st) return st;
-    if (precision == COMBO_MIXED) st = apply_operator_impl<float>(ctx, ctx->F_save.as<double>(), ctx->dF.as<double>());
-    else st = apply_operator_impl<double>(ctx, ctx->F_save.as<double>(), ctx->dF.as<double>());
+    const double* in_dev = ctx->F_save.as<double>();
+    if (staggered(ctx)) {
+        if ((st = to_shifted(ctx, ctx->F_save.as<double>(), ctx->stag_tmp.as<double>()))) return st;
+        in_dev = ctx->stag_tmp.as<double>();
+    }
+    if (precision == COMBO_MIXED) st = apply_operator_impl<float>(ctx, in_dev, ctx->dF.as<double>());
+    else st = apply_operator_impl<double>(ctx, in_dev, ctx->dF.as<double>());
     if (st) return st;
-    st = copy_out(ctx, q, ctx->dF.p, f9, mem_kind);
+    const void* res = ctx->dF.p;
+    if (staggered(ctx)) {
+        if ((st = to_natural(ctx, ctx->dF.as<double>(), ctx->stag_tmp.as<double>()))) return st;
+        res = ctx->stag_tmp.p;
+    }
+    st = copy_out(ctx, q, res, f9, mem_kind);
     if (st) return st;
     HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
     return COMBO_OK;
@@ -2692,7 +2885,7 @@ int combo_batch_set_options(combo_batch* b, const combo_options* o) {
 int combo_batch_set_discretization(combo_batch* b, int disc) {
     if (!b) return COMBO_E_INVAL;
     if (disc != COMBO_DISC_MS && disc != COMBO_DISC_WILLOT)
-        return bset_err(b, COMBO_E_INVAL, "disc must be COMBO_DISC_MS or COMBO_DISC_WILLOT");
+        return bset_err(b, COMBO_E_INVAL, "batches take COMBO_DISC_MS or COMBO_DISC_WILLOT members");
     b->disc = disc;
     return COMBO_OK;
 }
