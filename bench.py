@@ -254,6 +254,7 @@ def main():
     ap.add_argument("--no-small-strain", action="store_true")
     ap.add_argument("--no-image", action="store_true")
     ap.add_argument("--no-willot", action="store_true")
+    ap.add_argument("--no-staggered", action="store_true")
     ap.add_argument("--increments", type=int, default=0,
                     help="override the workload's load increments (shorter runs for counter collection)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -418,6 +419,47 @@ def main():
                                                       np.abs(Pbar_mixed).max()),
                          "kernels_avg_us": {k: round(v[0] / v[1] * 1e3, 1) for k, v in pw.items() if v[1]}}
         log("willot: %.2f s, newton %d, cg %d" % (el, rw["stats"]["newton_iters"], rw["stats"]["cg_iters_total"]))
+        combo.combo_set_discretization(ctx, combo.COMBO_DISC_MS)
+        combo.combo_set_materials(ctx, lc.mats)
+        combo.combo_set_microstructure(ctx, torch.from_numpy(ms.phase).to(dev), torch.from_numpy(ms.c).to(dev),
+                                       torch.from_numpy(np.ascontiguousarray(ms.N)).to(dev))
+    if not args.no_staggered:
+        # the same workload on the staggered grid with the DFMG law (App. A), mixed: the
+        # first five increments of the load path (10 % stretch, same increment size)
+        combo.combo_set_discretization(ctx, combo.COMBO_DISC_STAGGERED)
+        combo.combo_set_materials(ctx, lc.mats)
+        combo.combo_set_microstructure(ctx, torch.from_numpy(ms.phase).to(dev), torch.from_numpy(ms.c).to(dev),
+                                       torch.from_numpy(np.ascontiguousarray(ms.N)).to(dev))
+        o = options(combo.COMBO_MIXED)
+        o.autotune = 0
+        K_st = max(1, lc.n_increments // 2)
+        o.n_increments = K_st
+        combo.combo_set_options(ctx, o)
+        Fb_st = np.eye(3) + (lc.Fbar - np.eye(3)) * K_st / lc.n_increments
+        combo.combo_profile_enable(ctx, True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rs = combo.combo_solve(ctx, Fb_st)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        ps = combo.combo_profile_all(ctx)
+        combo.combo_profile_enable(ctx, False)
+        cg_st = rs["stats"]["cg_iters_total"]
+        # algorithmic bytes of one CG iteration's tangent part (x passes, DFMG action, DFMG sum):
+        # real FP64 field out and in (2 x 72 B), DFMG action: dH (72 B) + state (80 s) + dP (72 s) per cell,
+        # DFMG sum: dP (72 s) in + dQ (72 B) out; s = 4
+        nspec_st = (ms.n[0] // 2 + 1) * ms.n[1] * ms.n[2]
+        xb = n * (72 * 2 + 72 + 80 * 4 + 72 * 4 + 72 * 4 + 72) + 2 * 9 * 8 * nspec_st
+        xms, xcnt = ps.get("xpass_cg", (0.0, 0))
+        out["staggered"] = {"discretization": "staggered grid, DFMG law (8 doubly-fine cells per cell), mixed",
+                            "load": "first %d of %d increments (%.0f %% stretch)" % (
+                                K_st, lc.n_increments, 100 * (Fb_st[0, 0] - 1.0)),
+                            "time_to_solution_s": el, "newton_iters": rs["stats"]["newton_iters"],
+                            "cg_iters": cg_st, "voxel_cg_iters_per_s": n * cg_st / el,
+                            "laminate_solves_per_composite_per_eval": 8,
+                            "kernels_avg_us": {k: round(v[0] / v[1] * 1e3, 1) for k, v in ps.items() if v[1]},
+                            "tangent_part_GBps": round(xb / (xms / xcnt * 1e-3) / 1e9, 1) if xcnt else None}
+        log("staggered: %.2f s, newton %d, cg %d" % (el, rs["stats"]["newton_iters"], cg_st))
         combo.combo_set_discretization(ctx, combo.COMBO_DISC_MS)
         combo.combo_set_materials(ctx, lc.mats)
         combo.combo_set_microstructure(ctx, torch.from_numpy(ms.phase).to(dev), torch.from_numpy(ms.c).to(dev),
