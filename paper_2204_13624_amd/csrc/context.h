@@ -100,7 +100,8 @@ struct combo_ctx {
     combo::DevBuf slot, slot_s, comp_vox, comp_c, comp_N, a_prev, a_trial;   // slot: natural order, slot_s: state_pos order
     // staggered grid with the DFMG law: stresses, tangent states and stress increments of the
     // doubly-fine cells, the shifted-layout fields of the CG operator and a layout scratch field
-    combo::DevBuf dfmg_Pd, dfmg_Sd, dfmg_Ad, dfmg_dPd, dfmg_dH, dfmg_dQ, stag_tmp;
+    combo::DevBuf dfmg_Pd, dfmg_Ad, dfmg_act, dfmg_dH, dfmg_dQ, stag_tmp;
+    const double* dfmg_Feval = nullptr;   // F (shifted layout) of the last law evaluation, for the tangent action
 
     // fields (FP64) and work buffers
     combo::DevBuf F_cur, F_trial, F_save, dF, P;

@@ -41,7 +41,6 @@ struct DfmgArgs {
     int warm, maxit;
     double mu[2], lam[2];
     double* Pd;              // [9][8][n] stress of every doubly-fine cell (index (c 8 + l) n + cell)
-    T* Sd;                   // [10][8][n] F^{-1} (9) and mu - lambda ln J of pure doubly-fine cells
     T* Ad;                   // [nc][8][45] packed tangent of composite doubly-fine cells
     double* partials;        // pure kernel: [blocks][19]
     double* partials2;       // laminate kernel: [blocks][31]
@@ -55,21 +54,42 @@ int dfmg_blocks_pure(long long n);
 int dfmg_blocks_laminate(int nc);
 template <typename T> hipError_t launch_dfmg_law(const DfmgArgs<T>& a, double* sums_out, hipStream_t s);
 
-// Tangent action on a field in the shifted layout: per doubly-fine cell
-// dP(xi, l) = A(xi, l) : dF(xi, l) into dPd [9][8][n].
+// Tangent action on a field dH in the shifted layout, summed per destination.
+// Each doubly-fine cell (c, l) gives dP(c, l) = A(c, l) : dF(c, l).  Its diagonal
+// components belong to cell c; its component (a, b), a != b, to the edge stored
+// at Q_ab[c + l_a e_a + (l_b - 1) e_b] (shifted layout).  The kernel adds the
+// contributions that land on cell c itself into own[9][c] (weight 1/8) and the
+// rest, summed over l_d of the third axis d, into part[18][c]: for the ordered
+// pair p = (a, b) (order (0,1) (0,2) (1,0) (1,2) (2,0) (2,1)) the offsets
+// e_a, -e_b and e_a - e_b in part[3 p + k], k = 0, 1, 2.  Pure cells evaluate the
+// Neo-Hooke tangent from the deformation F of the last law evaluation (FP64 det F
+// and ln J); composite cells read their doubly-fine laminate tangents Ad.
 template <typename T>
 struct DfmgActArgs {
     int n1, n2, n3;
     long long n;
-    const double* dH;        // [9][n] shifted layout
-    T* dPd;                  // [9][8][n]
+    const T* dH;             // [9][n] shifted layout
+    const double* F;         // [9][n] shifted layout, the deformation the law was evaluated at
+    T* own;                  // [9][n]
+    T* part;                 // [18][n]
     const int* slot;
-    const T* Sd;
-    const T* Ad;
-    T mu[2], lam[2];
+    const T* Ad;             // [nc][8][45]
+    double mu[2], lam[2];
     const CGState* st;       // skip when st->done (null: always run)
 };
 template <typename T> hipError_t launch_dfmg_action(const DfmgActArgs<T>& a, hipStream_t s);
+
+// Q = own + the neighbours' parts (see DfmgActArgs): the DFMG sum of the action.
+template <typename T>
+struct DfmgSumArgs {
+    int n1, n2, n3;
+    long long n;
+    const T* own;
+    const T* part;
+    T* Q;                    // [9][n] shifted layout
+    const CGState* st;
+};
+template <typename T> hipError_t launch_dfmg_sum(const DfmgSumArgs<T>& a, hipStream_t s);
 
 // DFMG sum of doubly-fine cell stresses into a field in the shifted layout:
 // Q_aa[xi] = 1/8 sum_l Pd_aa(xi, l), Q_ab[xi] = P_ab[xi + e_b] (a != b).

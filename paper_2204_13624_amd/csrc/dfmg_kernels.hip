@@ -35,8 +35,8 @@ __device__ __forceinline__ long long cell_at(const CellIdx& c, int di, int dj, i
 
 // the deformation of doubly-fine cell (c, l) from a field H in the shifted layout:
 // F_aa = H_aa[c], F_ab = H_ab[c + l_a e_a + l_b e_b - e_b]
-template <typename TF>
-__device__ __forceinline__ void gather_dfc(const double* H, long long n, const CellIdx& c, int l, int n1, int n2,
+template <typename TF, typename TH>
+__device__ __forceinline__ void gather_dfc(const TH* H, long long n, const CellIdx& c, int l, int n1, int n2,
                                            int n3, TF* Fd) {
     const int lb[3] = {l & 1, (l >> 1) & 1, (l >> 2) & 1};
     const long long self = ((long long)c.k * n2 + c.j) * n1 + c.i;
@@ -115,11 +115,6 @@ __global__ void __launch_bounds__(256) k_dfmg_pure(DfmgArgs<T> a) {
             for (int c = 0; c < 9; ++c) {
                 a.Pd[(long long)(c * 8 + l) * a.n + cell] = P[c];
                 sums[9 * ph + c] += 0.125 * P[c];
-            }
-            if (a.Sd) {
-#pragma unroll
-                for (int c = 0; c < 9; ++c) a.Sd[(long long)(c * 8 + l) * a.n + cell] = T(Finv[c]);
-                a.Sd[(long long)(9 * 8 + l) * a.n + cell] = T(m);
             }
         }
     }
@@ -221,7 +216,119 @@ __global__ void __launch_bounds__(256) k_dfmg_reduce(const double* pp, int nbp, 
     }
 }
 
-// tangent action per doubly-fine cell (thread per cell)
+// The 27 staggered values of one component set that a cell's eight doubly-fine cells
+// use: the diagonal (a, a) at the cell (slot a), and for each ordered pair p = (a, b)
+// of the order of dfmg.h the value at cell + l_a e_a + (l_b - 1) e_b (slot
+// 3 + 4 p + 2 l_a + l_b), read from the shifted layout.
+__device__ __forceinline__ constexpr int pair_a(int p) { return p / 2; }
+__device__ __forceinline__ constexpr int pair_b(int p) { return (p % 2 == 0) ? (p / 2 == 0 ? 1 : 0) : (p / 2 == 2 ? 1 : 2); }
+
+template <typename TV, typename TH>
+__device__ __forceinline__ void load27(const TH* H, long long n, const CellIdx& c, int n1, int n2, int n3, TV* v) {
+    const long long self = ((long long)c.k * n2 + c.j) * n1 + c.i;
+#pragma unroll
+    for (int a0 = 0; a0 < 3; ++a0) v[a0] = TV(H[(long long)(4 * a0) * n + self]);
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const int aa = pair_a(p), bb = pair_b(p);
+#pragma unroll
+        for (int la = 0; la < 2; ++la)
+#pragma unroll
+            for (int lb = 0; lb < 2; ++lb) {
+                int d[3] = {0, 0, 0};
+                d[aa] += la;
+                d[bb] += lb - 1;
+                v[3 + 4 * p + 2 * la + lb] = TV(H[(long long)(3 * aa + bb) * n + cell_at(c, d[0], d[1], d[2], n1, n2, n3)]);
+            }
+    }
+}
+
+// the deformation of doubly-fine cell l from the 27 values
+template <typename TV, int L>
+__device__ __forceinline__ void dfc_from27(const TV* v, TV* Fd) {
+    constexpr int lb[3] = {L & 1, (L >> 1) & 1, (L >> 2) & 1};
+#pragma unroll
+    for (int a0 = 0; a0 < 3; ++a0) Fd[4 * a0] = v[a0];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const int aa = pair_a(p), bb = pair_b(p);
+        Fd[3 * aa + bb] = v[3 + 4 * p + 2 * lb[aa] + lb[bb]];
+    }
+}
+
+template <typename T, int L>
+__device__ __forceinline__ void action_dfc(const DfmgActArgs<T>& a, int slot, double mu, double lam, const double* Fv,
+                                           const T* hv, T* own, T* part) {
+    constexpr int lb[3] = {L & 1, (L >> 1) & 1, (L >> 2) & 1};
+    T p[9], tau[9];
+    dfc_from27<T, L>(hv, p);
+    if (slot >= 0) {
+        const T* A = a.Ad + ((long long)slot * 8 + L) * 45;
+        T s[45];
+#pragma unroll
+        for (int r = 0; r < 45; ++r) s[r] = A[r];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            T acc = T(0);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int lo = r < q ? r : q, hi = r < q ? q : r;
+                acc += s[lo * 9 - (lo * (lo - 1)) / 2 + (hi - lo)] * p[q];
+            }
+            tau[r] = acc;
+        }
+    } else {
+        // Neo-Hooke tangent at the doubly-fine deformation: F^{-1} and m = mu - lambda ln J in FP64
+        double F[9], Fi[9];
+        dfc_from27<double, L>(Fv, F);
+        const double J = det3(F);
+        adj3(F, Fi);
+        double m = 0.0, iJ = 0.0;
+        if (J > 0.0) {
+            iJ = 1.0 / J;
+            m = mu - lam * log(J);
+        }
+        T fi[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) fi[c] = T(Fi[c] * iJ);
+        const T mt = T(m), mut = T(mu), lamt = T(lam);
+        // B = F^{-1} p, C = B F^{-1};  tau_iJ = mu p_iJ + lam tr(B) Finv_Ji + m C_Ji
+        T B[9];
+#pragma unroll
+        for (int J2 = 0; J2 < 3; ++J2)
+#pragma unroll
+            for (int Lc = 0; Lc < 3; ++Lc)
+                B[3 * J2 + Lc] = fi[3 * J2 + 0] * p[0 + Lc] + fi[3 * J2 + 1] * p[3 + Lc] + fi[3 * J2 + 2] * p[6 + Lc];
+        const T tr = B[0] + B[4] + B[8];
+        T C[9];
+#pragma unroll
+        for (int J2 = 0; J2 < 3; ++J2)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                C[3 * J2 + i] = B[3 * J2 + 0] * fi[0 + i] + B[3 * J2 + 1] * fi[3 + i] + B[3 * J2 + 2] * fi[6 + i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int J2 = 0; J2 < 3; ++J2)
+                tau[3 * i + J2] = mut * p[3 * i + J2] + lamt * tr * fi[3 * J2 + i] + mt * C[3 * J2 + i];
+    }
+    // destinations: diagonal -> own; (a, b) -> offset l_a e_a + (l_b - 1) e_b
+#pragma unroll
+    for (int a0 = 0; a0 < 3; ++a0) own[4 * a0] += T(0.125) * tau[4 * a0];
+#pragma unroll
+    for (int pr = 0; pr < 6; ++pr) {
+        const int aa = pair_a(pr), bb = pair_b(pr);
+        const T v = T(0.125) * tau[3 * aa + bb];
+        if (lb[aa] == 0 && lb[bb] == 1) own[3 * aa + bb] += v;       // offset 0
+        else if (lb[aa] == 1 && lb[bb] == 1) part[3 * pr + 0] += v;  // +e_a
+        else if (lb[aa] == 0) part[3 * pr + 1] += v;                 // -e_b
+        else part[3 * pr + 2] += v;                                  // e_a - e_b
+    }
+}
+
+// tangent action per cell, summed per destination (thread per cell; dfmg.h).  The
+// 27 values of the deformation and of dH that the cell's doubly-fine cells use are
+// loaded once, then the eight doubly-fine cells are evaluated from registers.
 template <typename T>
 __global__ void __launch_bounds__(256) k_dfmg_action(DfmgActArgs<T> a) {
     if (a.st && a.st->done) return;
@@ -229,52 +336,61 @@ __global__ void __launch_bounds__(256) k_dfmg_action(DfmgActArgs<T> a) {
          cell += (long long)gridDim.x * blockDim.x) {
         const int slot = a.slot[cell];
         const CellIdx ci = cell_of(cell, a.n1, a.n2);
-        for (int l = 0; l < 8; ++l) {
-            T p[9], tau[9];
-            gather_dfc<T>(a.dH, a.n, ci, l, a.n1, a.n2, a.n3, p);
-            if (slot >= 0) {
-                const T* A = a.Ad + ((long long)slot * 8 + l) * 45;
-                T s[45];
+        T hv[27];
+        double Fv[27];
+        load27<T>(a.dH, a.n, ci, a.n1, a.n2, a.n3, hv);
+        if (slot < 0) {
+            load27<double>(a.F, a.n, ci, a.n1, a.n2, a.n3, Fv);
+        } else {
 #pragma unroll
-                for (int r = 0; r < 45; ++r) s[r] = A[r];
+            for (int c = 0; c < 27; ++c) Fv[c] = 0.0;
+        }
+        const int ph = (slot == -1) ? 0 : 1;
+        const double mu = a.mu[ph], lam = a.lam[ph];
+        T own[9], part[18];
 #pragma unroll
-                for (int r = 0; r < 9; ++r) {
-                    T acc = T(0);
+        for (int c = 0; c < 9; ++c) own[c] = T(0);
 #pragma unroll
-                    for (int q = 0; q < 9; ++q) {
-                        const int lo = r < q ? r : q, hi = r < q ? q : r;
-                        acc += s[lo * 9 - (lo * (lo - 1)) / 2 + (hi - lo)] * p[q];
-                    }
-                    tau[r] = acc;
-                }
-            } else {
-                const int ph = (slot == -1) ? 0 : 1;
-                const T mu = a.mu[ph], lam = a.lam[ph];
-                T fi[9];
+        for (int c = 0; c < 18; ++c) part[c] = T(0);
+        action_dfc<T, 0>(a, slot, mu, lam, Fv, hv, own, part);
+        action_dfc<T, 1>(a, slot, mu, lam, Fv, hv, own, part);
+        action_dfc<T, 2>(a, slot, mu, lam, Fv, hv, own, part);
+        action_dfc<T, 3>(a, slot, mu, lam, Fv, hv, own, part);
+        action_dfc<T, 4>(a, slot, mu, lam, Fv, hv, own, part);
+        action_dfc<T, 5>(a, slot, mu, lam, Fv, hv, own, part);
+        action_dfc<T, 6>(a, slot, mu, lam, Fv, hv, own, part);
+        action_dfc<T, 7>(a, slot, mu, lam, Fv, hv, own, part);
 #pragma unroll
-                for (int c = 0; c < 9; ++c) fi[c] = a.Sd[(long long)(c * 8 + l) * a.n + cell];
-                const T m = a.Sd[(long long)(9 * 8 + l) * a.n + cell];
-                // B = F^{-1} p, C = B F^{-1};  tau_iJ = mu p_iJ + lam tr(B) Finv_Ji + m C_Ji
-                T B[9];
+        for (int c = 0; c < 9; ++c) a.own[(long long)c * a.n + cell] = own[c];
 #pragma unroll
-                for (int J = 0; J < 3; ++J)
+        for (int c = 0; c < 18; ++c) a.part[(long long)c * a.n + cell] = part[c];
+    }
+}
+
+// Q = own + neighbours' parts (thread per cell)
+template <typename T>
+__global__ void __launch_bounds__(256) k_dfmg_sum(DfmgSumArgs<T> a) {
+    if (a.st && a.st->done) return;
+    for (long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x; cell < a.n;
+         cell += (long long)gridDim.x * blockDim.x) {
+        const CellIdx ci = cell_of(cell, a.n1, a.n2);
 #pragma unroll
-                    for (int L = 0; L < 3; ++L)
-                        B[3 * J + L] = fi[3 * J + 0] * p[0 + L] + fi[3 * J + 1] * p[3 + L] + fi[3 * J + 2] * p[6 + L];
-                const T tr = B[0] + B[4] + B[8];
-                T C[9];
+        for (int a0 = 0; a0 < 3; ++a0) a.Q[(long long)(4 * a0) * a.n + cell] = a.own[(long long)(4 * a0) * a.n + cell];
 #pragma unroll
-                for (int J = 0; J < 3; ++J)
-#pragma unroll
-                    for (int i = 0; i < 3; ++i)
-                        C[3 * J + i] = B[3 * J + 0] * fi[0 + i] + B[3 * J + 1] * fi[3 + i] + B[3 * J + 2] * fi[6 + i];
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int J = 0; J < 3; ++J) tau[3 * i + J] = mu * p[3 * i + J] + lam * tr * fi[3 * J + i] + m * C[3 * J + i];
-            }
-#pragma unroll
-            for (int c = 0; c < 9; ++c) a.dPd[(long long)(c * 8 + l) * a.n + cell] = tau[c];
+        for (int pr = 0; pr < 6; ++pr) {
+            const int aa = pr / 2, bb = (pr % 2 == 0) ? (aa == 0 ? 1 : 0) : (aa == 2 ? 1 : 2);
+            const int c = 3 * aa + bb;
+            // contributions written at cell - offset by the cells that own them
+            int d0[3] = {0, 0, 0}, d1[3] = {0, 0, 0}, d2[3] = {0, 0, 0};
+            d0[aa] = -1;             // written with offset +e_a at cell - e_a
+            d1[bb] = +1;             // offset -e_b at cell + e_b
+            d2[aa] = -1;
+            d2[bb] = +1;             // offset e_a - e_b at cell - e_a + e_b
+            T v = a.own[(long long)c * a.n + cell];
+            v += a.part[(long long)(3 * pr + 0) * a.n + cell_at(ci, d0[0], d0[1], d0[2], a.n1, a.n2, a.n3)];
+            v += a.part[(long long)(3 * pr + 1) * a.n + cell_at(ci, d1[0], d1[1], d1[2], a.n1, a.n2, a.n3)];
+            v += a.part[(long long)(3 * pr + 2) * a.n + cell_at(ci, d2[0], d2[1], d2[2], a.n1, a.n2, a.n3)];
+            a.Q[(long long)c * a.n + cell] = v;
         }
     }
 }
@@ -372,6 +488,12 @@ hipError_t launch_dfmg_action(const DfmgActArgs<T>& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_dfmg_sum(const DfmgSumArgs<T>& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_dfmg_sum<T>, dim3(grid_for(a.n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 template <typename TI>
 hipError_t launch_dfmg_gather(const DfmgGatherArgs<TI>& a, hipStream_t s) {
     hipLaunchKernelGGL(k_dfmg_gather<TI>, dim3(grid_for(a.n)), dim3(256), 0, s, a);
@@ -390,7 +512,8 @@ template hipError_t launch_dfmg_law<float>(const DfmgArgs<float>&, double*, hipS
 template hipError_t launch_dfmg_law<double>(const DfmgArgs<double>&, double*, hipStream_t);
 template hipError_t launch_dfmg_action<float>(const DfmgActArgs<float>&, hipStream_t);
 template hipError_t launch_dfmg_action<double>(const DfmgActArgs<double>&, hipStream_t);
-template hipError_t launch_dfmg_gather<float>(const DfmgGatherArgs<float>&, hipStream_t);
+template hipError_t launch_dfmg_sum<float>(const DfmgSumArgs<float>&, hipStream_t);
+template hipError_t launch_dfmg_sum<double>(const DfmgSumArgs<double>&, hipStream_t);
 template hipError_t launch_dfmg_gather<double>(const DfmgGatherArgs<double>&, hipStream_t);
 
 }  // namespace combo

@@ -200,8 +200,13 @@ __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int n
 #pragma unroll
                 for (int c = 0; c < 9; ++c) p[c] = T(a.E[c]);
             } else if (MODE == X_FWD_REAL) {
+                if (a.real_in_t) {
 #pragma unroll
-                for (int c = 0; c < 9; ++c) p[c] = T(a.real_in[c * a.g.n + vox]);
+                    for (int c = 0; c < 9; ++c) p[c] = a.real_in_t[c * a.g.n + vox];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) p[c] = T(a.real_in[c * a.g.n + vox]);
+                }
             } else {
 #pragma unroll
                 for (int s = 0; s < 5; ++s) {
@@ -211,8 +216,13 @@ __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int n
                 }
             }
             if (MODE == X_INV_REAL) {
+                if (a.real_out_t) {
 #pragma unroll
-                for (int c = 0; c < 9; ++c) a.real_out[c * a.g.n + vox] = double(p[c]) * a.scale;
+                    for (int c = 0; c < 9; ++c) a.real_out_t[c * a.g.n + vox] = T(double(p[c]) * a.scale);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) a.real_out[c * a.g.n + vox] = double(p[c]) * a.scale;
+                }
                 continue;
             }
             if (MODE == X_AVG) {
@@ -479,6 +489,7 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
     constexpr int FLD = (10 * R * L * (int)sizeof(T) + (int)sizeof(C) - 1) / (int)sizeof(C);
     constexpr int BUFC = cmax3(S::EXA, S::EXN, FLD);
     if (MODE == X_CG && a.st->done) return;
+    if (MODE != X_CG && a.skip_done && a.st->done) return;
     __shared__ C buf[BUFC];   // exchange, natural rows and real rows in turn
     // stored x frequencies: the Nyquist bin is dropped (Moulinec-Suquet) or kept (rotated
     // scheme, whose rows may be padded: row stride ld >= nh)
@@ -513,6 +524,8 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
     // 0, and invalid bins read bin 0 of the row and scale it by 0.
     T* fa = fld + (ca * R + r) * L;
     T* fb = fld + ((s < 4 ? cb : 9) * R + r) * L;   // row 9 of fld is a write-only sink
+    C y[P];
+    if constexpr (MODE != X_FWD_REAL) {
     if (col_ok && j < P) {
         const long long rowc = live ? row : 0;
         const C* pa = a.in + ca * nspec + rowc * ld;
@@ -536,16 +549,24 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
             const int kk = conj ? L - k : k;
             const T m = (live && kk < nh) ? T(1) : T(0);
             T ma, mb;
-            if constexpr (DISC) {
-                const T d1 = fx[kk], a1 = fx[nh + kk];
-                ma = m * (sa ? d1 : a1);
-                mb = mb0 * m * (sb ? d1 : a1);
+            C A, B;
+            if constexpr (DISC == 2) {   // staggered grid: components (i, 1) times f_1
+                const C f1 = mk<T>(fx[kk], fx[nh + kk]);
+                A = cscale(sa ? cmul(ha[j2], f1) : ha[j2], m);
+                B = cscale(sb ? cmul(hb[j2], f1) : hb[j2], mb0 * m);
             } else {
-                const T x1 = xs1 * T(kk);
-                ma = sa ? m * x1 : m;
-                mb = sb ? mb0 * m * x1 : mb0 * m;
+                if constexpr (DISC) {
+                    const T d1 = fx[kk], a1 = fx[nh + kk];
+                    ma = m * (sa ? d1 : a1);
+                    mb = mb0 * m * (sb ? d1 : a1);
+                } else {
+                    const T x1 = xs1 * T(kk);
+                    ma = sa ? m * x1 : m;
+                    mb = sb ? mb0 * m * x1 : mb0 * m;
+                }
+                A = cscale(ha[j2], ma);
+                B = cscale(hb[j2], mb);
             }
-            const C A = cscale(ha[j2], ma), B = cscale(hb[j2], mb);
             const C zc = conj ? mk<T>(A.x + B.y, B.x - A.y) : mk<T>(A.x - B.y, A.y + B.x);
             x[j2] = (k == 0 || 2 * k == L) ? mk<T>(A.x, B.x) : zc;   // self-conjugate bins (L/2: zero unless stored)
         }
@@ -562,7 +583,6 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
         }
     }
     __syncthreads();
-    C y[P];
     if (col_ok && j < Q) {
 #pragma unroll
         for (int j1 = 0; j1 < P; ++j1) y[j1] = buf[(t * P + j1) * QP + j];
@@ -577,12 +597,35 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
         }
     }
     __syncthreads();
+    }   // MODE != X_FWD_REAL
+
+    // ---- real fields in the precision of the pass (staggered-grid CG operator)
+    if constexpr (MODE == X_INV_REAL) {
+        const T sc = T(a.scale);
+        for (int v = tid; v < R * L; v += blockDim.x) {
+            const int rr = v / L, xx = v - rr * L;
+            const long long rw = row0 + rr;
+            if (rw >= nrows) continue;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) a.real_out_t[c * a.g.n + rw * L + xx] = fld[(c * R + rr) * L + xx] * sc;
+        }
+        return;
+    }
+    if constexpr (MODE == X_FWD_REAL) {
+        for (int v = tid; v < R * L; v += blockDim.x) {
+            const int rr = v / L, xx = v - rr * L;
+            const long long rw = row0 + rr;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) fld[(c * R + rr) * L + xx] = rw < nrows ? a.real_in_t[c * a.g.n + rw * L + xx] : T(0);
+        }
+        __syncthreads();
+    }
 
     // ---- tangent action per voxel (X_AVG: averaged instead of stored)
     double acc[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) acc[c] = 0.0;
-    for (int v = tid; v < R * L; v += blockDim.x) {
+    for (int v = (MODE == X_FWD_REAL) ? R * L : tid; v < R * L; v += blockDim.x) {
         const int rr = v / L, xx = v - rr * L;
         const long long rw = row0 + rr;
         if (rw >= nrows) continue;
@@ -610,7 +653,7 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
         }
         return;
     }
-    __syncthreads();
+    if (MODE != X_FWD_REAL) __syncthreads();
 
     // ---- forward: real rows -> packed complex rows -> half spectra
     C x2[Q];
@@ -655,7 +698,12 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
         C ha = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
         C hb = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
         const int c1 = 2 * ss, c2 = 2 * ss + 1;
-        if constexpr (DISC) {
+        if constexpr (DISC == 2) {   // staggered grid: components (i, 1) times conj(f_1)
+            const bool pad = k >= nh;
+            const C f1c = pad ? mk<T>(0, 0) : mk<T>(fx[k], -fx[nh + k]);
+            ha = xi1_comp(c1) ? cmul(ha, f1c) : (pad ? mk<T>(0, 0) : ha);
+            hb = xi1_comp(c2) ? cmul(hb, f1c) : (pad ? mk<T>(0, 0) : hb);
+        } else if constexpr (DISC) {
             const bool pad = k >= nh;   // row padding: zero modes
             const T d1 = pad ? T(0) : fx[k], a1 = pad ? T(0) : fx[nh + k];
             ha = cscale(ha, xi1_comp(c1) ? d1 : a1);
@@ -1744,7 +1792,7 @@ __device__ __forceinline__ void k_y2_fwd_body(const YArgs<T>& a, int tile_, int 
                 if (sub == 0) {
 #pragma unroll
                     for (int k2 = 0; k2 < P; ++k2)
-                        acc[k2] = DISC ? cscale(y[k2], fy[L + k1 + Q * k2]) : y[k2];
+                        acc[k2] = (DISC == 1) ? cscale(y[k2], fy[L + k1 + Q * k2]) : y[k2];
                 } else if (colB) {
                     const int oc = (sub == 1) ? i : 3 + i;
                     C* dst = a.out + oc * a.g.nspec + zoff + kx0;   // uniform
@@ -1752,8 +1800,12 @@ __device__ __forceinline__ void k_y2_fwd_body(const YArgs<T>& a, int tile_, int 
                     for (int k2 = 0; k2 < P; ++k2) {
                         const int ky = k1 + Q * k2;
                         C v = y[k2];
-                        if (sub == 1) v = cadd(acc[k2], cscale(v, DISC ? fy[ky] : xs2 * T(freq_of(ky, L))));
-                        else if (DISC) v = cscale(v, fy[L + ky]);
+                        if (DISC == 2) {   // staggered grid: times conj(f_2)
+                            if (sub == 1) v = cadd(acc[k2], cmul(v, mk<T>(fy[ky], -fy[L + ky])));
+                        } else {
+                            if (sub == 1) v = cadd(acc[k2], cscale(v, DISC ? fy[ky] : xs2 * T(freq_of(ky, L))));
+                            else if (DISC) v = cscale(v, fy[L + ky]);
+                        }
                         dst[tB + ky * nh] = v;
                     }
                 }
@@ -1812,7 +1864,8 @@ __device__ __forceinline__ void k_y2_inv_body(const YArgs<T>& a, int tile_, int 
 #pragma unroll
             for (int j2 = 0; j2 < Q; ++j2) {
                 const int y = j1 + P * j2;
-                if (DISC) x[j2] = cscale(nx[j2], fy[sub == 1 ? y : L + y]);
+                if (DISC == 2) x[j2] = (sub == 1) ? cmul(nx[j2], mk<T>(fy[y], fy[L + y])) : nx[j2];
+                else if (DISC) x[j2] = cscale(nx[j2], fy[sub == 1 ? y : L + y]);
                 else x[j2] = (sub == 1) ? cscale(nx[j2], xs2 * T(freq_of(y, L))) : nx[j2];
             }
             if (3 * i + sub + 1 < 9) load(3 * i + sub + 1);
@@ -1888,7 +1941,10 @@ __device__ __forceinline__ void k_z2_fwd_body(const ZArgs<T, TU>& a, int tile_, 
 #pragma unroll
                 for (int k2 = 0; k2 < P; ++k2) {
                     const int zz = k1 + Q * k2;
-                    if constexpr (DISC) {
+                    if constexpr (DISC == 2) {   // staggered grid: times conj(f_3)
+                        if (sub == 0) v[i][k2] = y[k2];
+                        else v[i][k2] = cadd(v[i][k2], cmul(y[k2], mk<T>(fz[zz], -fz[L + zz])));
+                    } else if constexpr (DISC) {
                         if (sub == 0) v[i][k2] = cscale(y[k2], fz[L + zz]);
                         else v[i][k2] = cadd(v[i][k2], cscale(y[k2], fz[zz]));
                     } else {
@@ -1902,7 +1958,15 @@ __device__ __forceinline__ void k_z2_fwd_body(const ZArgs<T, TU>& a, int tile_, 
     }
     double s1 = 0.0, s2 = 0.0;
     if (hasB && colB) {
-        if constexpr (DISC) {
+        if constexpr (DISC == 2) {
+            const int m = (int)(m0 + tB), ky = m / a.g.nh, kx = m - ky * a.g.nh;   // one column per thread
+#pragma unroll
+            for (int k2 = 0; k2 < P; ++k2) {
+                const int zz = k1 + Q * k2;
+                C vv[3] = {v[0][k2], v[1][k2], v[2][k2]};
+                z_epilogue_stag<T, TU, MODE>(a, freqc_k(a.g, ky, kx, zz), (long long)zz * M + m, vv, s1, s2);
+            }
+        } else if constexpr (DISC) {
             const int m = (int)(m0 + tB), ky = m / a.g.nh, kx = m - ky * a.g.nh;   // one column per thread
             const ColFreq cf = col_freq_rot(a.g, ky, kx);
 #pragma unroll
@@ -2008,7 +2072,8 @@ __device__ __forceinline__ void k_z2_inv_body(const ZArgs<T, TU>& a, int tile_, 
 #pragma unroll
                 for (int j2 = 0; j2 < Q; ++j2) {
                     const int zz = j1 + P * j2;
-                    if (DISC) x[j2] = cscale(u[j2], fz[sub ? zz : L + zz]);
+                    if (DISC == 2) x[j2] = sub ? cmul(u[j2], mk<T>(fz[zz], fz[L + zz])) : u[j2];
+                    else if (DISC) x[j2] = cscale(u[j2], fz[sub ? zz : L + zz]);
                     else x[j2] = sub ? cscale(u[j2], xs3 * T(freq_of(zz, L))) : u[j2];
                 }
                 fft2_stageA<P, Q, TX, +1, T>(x, tA, j1, ex, tw);
@@ -2090,14 +2155,14 @@ int fft2_tx(int L, int v) {
 
 template <typename T>
 int y_tile(const Grid& g) {
-    const int tx = g.disc == 2 ? 0 : fft2_tx<T>(g.n2, g.yv);   // the staggered grid runs the LDS passes
+    const int tx = fft2_tx<T>(g.n2, g.yv);
     if (tx) return tx;
     return std::max(1, std::min(g.nh, max_elems<T>() / g.n2));
 }
 
 template <typename T>
 int z_tile(const Grid& g) {
-    const int tx = g.disc == 2 ? 0 : fft2_tx<T>(g.n3, g.zv);
+    const int tx = fft2_tx<T>(g.n3, g.zv);
     if (tx) return tx;
     return (int)std::max<long long>(1, std::min<long long>((long long)g.n2 * g.nh, max_elems<T>() / g.n3));
 }
@@ -2190,6 +2255,21 @@ hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const B
     const long long nrows = (long long)a.g.n2 * a.g.n3;
     // the staggered grid transforms real fields only (its tangent action is a separate stencil)
     if (a.g.disc == 2 && mode != X_FWD_REAL && mode != X_INV_REAL) return hipErrorInvalidValue;
+    if (a.g.disc == 2 && (a.real_in_t || a.real_out_t)) {   // real fields in the pass's precision: two-stage kernel
+#define COMBO_XS_CASE(LL, PP, QQ, RR, VV)                                                                    \
+        if constexpr (VV == 0) {                                                                             \
+            if (a.g.n1 == LL) {                                                                              \
+                using SH = XLdsShape<PP, QQ, RR>;                                                            \
+                const int nblk = (int)((nrows + SH::R - 1) / SH::R);                                         \
+                if (nb) *nb = nblk;                                                                          \
+                if (mode == X_INV_REAL) COMBO_LAUNCH(k_xlds, (T, X_INV_REAL, PP, QQ, RR, 2), XA, nblk, SH::NTH, 0); \
+                else COMBO_LAUNCH(k_xlds, (T, X_FWD_REAL, PP, QQ, RR, 2), XA, nblk, SH::NTH, 0);             \
+                return hipGetLastError();                                                                    \
+            }                                                                                                \
+        }
+        COMBO_XLDS_CONFIGS(COMBO_XS_CASE)
+#undef COMBO_XS_CASE
+    }
     if (a.g.disc != 2 && (mode == X_CG || mode == X_AVG)) {
         const int vv = xpass_lds_pick(a.g.n1, a.g.xv, std::is_same<T, float>::value);
 #define COMBO_XL_CASE(LL, PP, QQ, RR, VV)                                                                    \
@@ -2257,17 +2337,13 @@ hipError_t launch_y(int dir, const YArgs<T>& a0, hipStream_t s, const BatchLaunc
     y_fill_tiles(a);
     const int nblk = a.g.n3 * a.ntile;
     const int vv = fft2_pick<T>(a.g.n2, a.g.yv);
-    if (a.g.disc == 2) {   // staggered grid: LDS Stockham passes with complex multipliers
-        const size_t lds2 = sizeof(cpx<T>) * ((size_t)a.g.n2 + (size_t)a.g.n2 * a.TX);
-        if (dir < 0) COMBO_LAUNCH(k_ypass_fwd, (T, 2), YA, nblk, kBlock, lds2);
-        else COMBO_LAUNCH(k_ypass_inv, (T, 2), YA, nblk, kBlock, lds2);
-        return hipGetLastError();
-    }
 #define COMBO_Y_CASE(TT, LL, PP, QQ, TXX, VV)                                                                   \
     if constexpr (std::is_same<T, TT>::value) {                                                               \
         if (a.g.n2 == LL && vv == VV) {                                                                        \
             constexpr int nt = fft2_threads<PP, QQ, TXX>();                                                    \
-            if (dir < 0 && a.g.disc) COMBO_LAUNCH(k_y2_fwd, (PP, QQ, TXX, T, 1), YA, nblk, nt, 0);       \
+            if (dir < 0 && a.g.disc == 2) COMBO_LAUNCH(k_y2_fwd, (PP, QQ, TXX, T, 2), YA, nblk, nt, 0);  \
+            else if (dir > 0 && a.g.disc == 2) COMBO_LAUNCH(k_y2_inv, (PP, QQ, TXX, T, 2), YA, nblk, nt, 0); \
+            else if (dir < 0 && a.g.disc) COMBO_LAUNCH(k_y2_fwd, (PP, QQ, TXX, T, 1), YA, nblk, nt, 0);  \
             else if (dir < 0) COMBO_LAUNCH(k_y2_fwd, (PP, QQ, TXX, T, 0), YA, nblk, nt, 0);              \
             else if (a.g.disc) COMBO_LAUNCH(k_y2_inv, (PP, QQ, TXX, T, 1), YA, nblk, nt, 0);             \
             else COMBO_LAUNCH(k_y2_inv, (PP, QQ, TXX, T, 0), YA, nblk, nt, 0);                           \
@@ -2277,6 +2353,11 @@ hipError_t launch_y(int dir, const YArgs<T>& a0, hipStream_t s, const BatchLaunc
     COMBO_FFT2_CONFIGS(COMBO_Y_CASE)
 #undef COMBO_Y_CASE
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n2 + (size_t)a.g.n2 * a.TX);
+    if (a.g.disc == 2) {   // staggered grid without a two-stage pass: LDS Stockham with complex multipliers
+        if (dir < 0) COMBO_LAUNCH(k_ypass_fwd, (T, 2), YA, nblk, kBlock, lds);
+        else COMBO_LAUNCH(k_ypass_inv, (T, 2), YA, nblk, kBlock, lds);
+        return hipGetLastError();
+    }
     if (dir < 0 && a.g.disc) COMBO_LAUNCH(k_ypass_fwd, (T, 1), YA, nblk, kBlock, lds);
     else if (dir < 0) COMBO_LAUNCH(k_ypass_fwd, (T, 0), YA, nblk, kBlock, lds);
     else if (a.g.disc) COMBO_LAUNCH(k_ypass_inv, (T, 1), YA, nblk, kBlock, lds);
@@ -2295,40 +2376,34 @@ hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb, co
     const int nblk = blocks_z(a.g, a.TX);
     if (nb) *nb = nblk;
     const int vv = fft2_pick<T>(a.g.n3, a.g.zv);
-    if (a.g.disc == 2) {   // staggered grid: LDS Stockham passes with complex multipliers
-        const size_t lds2 = sizeof(cpx<T>) * ((size_t)a.g.n3 + (size_t)a.g.n3 * a.TX);
-        switch (mode) {
-            case Z_CG: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_CG, 2), ZA, nblk, kBlock, lds2); break;
-            case Z_RHS: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_RHS, 2), ZA, nblk, kBlock, lds2); break;
-            case Z_PROJ: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_PROJ, 2), ZA, nblk, kBlock, lds2); break;
-            case Z_INV_CG: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_CG, 2), ZA, nblk, kBlock, lds2); break;
-            default: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_PLAIN, 2), ZA, nblk, kBlock, lds2); break;
-        }
-        return hipGetLastError();
-    }
 #define COMBO_Z_CASE(TT, LL, PP, QQ, TXX, VV)                                                                  \
     if constexpr (std::is_same<T, TT>::value) {                                                              \
         if (a.g.n3 == LL && vv == VV) {                                                                       \
             constexpr int nt = fft2_threads<PP, QQ, TXX>();                                                   \
             switch (mode) {                                                                                   \
                 case Z_CG:                                                                                    \
-                    if (a.g.disc) COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_CG, 1), ZA, nblk, nt, 0);     \
+                    if (a.g.disc == 2) COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_CG, 2), ZA, nblk, nt, 0);  \
+                    else if (a.g.disc) COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_CG, 1), ZA, nblk, nt, 0);     \
                     else COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_CG, 0), ZA, nblk, nt, 0);              \
                     break;                                                                                    \
                 case Z_RHS:                                                                                   \
-                    if (a.g.disc) COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_RHS, 1), ZA, nblk, nt, 0);    \
+                    if (a.g.disc == 2) COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_RHS, 2), ZA, nblk, nt, 0);  \
+                    else if (a.g.disc) COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_RHS, 1), ZA, nblk, nt, 0);    \
                     else COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_RHS, 0), ZA, nblk, nt, 0);             \
                     break;                                                                                    \
                 case Z_PROJ:                                                                                  \
-                    if (a.g.disc) COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_PROJ, 1), ZA, nblk, nt, 0);   \
+                    if (a.g.disc == 2) COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_PROJ, 2), ZA, nblk, nt, 0);  \
+                    else if (a.g.disc) COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_PROJ, 1), ZA, nblk, nt, 0);   \
                     else COMBO_LAUNCH(k_z2_fwd, (PP, QQ, TXX, T, TU, Z_PROJ, 0), ZA, nblk, nt, 0);            \
                     break;                                                                                    \
                 case Z_INV_CG:                                                                                \
-                    if (a.g.disc) COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_CG, 1), ZA, nblk, nt, 0); \
+                    if (a.g.disc == 2) COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_CG, 2), ZA, nblk, nt, 0);  \
+                    else if (a.g.disc) COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_CG, 1), ZA, nblk, nt, 0); \
                     else COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_CG, 0), ZA, nblk, nt, 0);          \
                     break;                                                                                    \
                 default:                                                                                      \
-                    if (a.g.disc) COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_PLAIN, 1), ZA, nblk, nt, 0); \
+                    if (a.g.disc == 2) COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_PLAIN, 2), ZA, nblk, nt, 0);  \
+                    else if (a.g.disc) COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_PLAIN, 1), ZA, nblk, nt, 0); \
                     else COMBO_LAUNCH(k_z2_inv, (PP, QQ, TXX, T, TU, Z_INV_PLAIN, 0), ZA, nblk, nt, 0);       \
                     break;                                                                                    \
             }                                                                                                 \
@@ -2338,6 +2413,16 @@ hipError_t launch_z(int mode, const ZArgs<T, TU>& a0, hipStream_t s, int* nb, co
     COMBO_FFT2_CONFIGS(COMBO_Z_CASE)
 #undef COMBO_Z_CASE
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n3 + (size_t)a.g.n3 * a.TX);
+    if (a.g.disc == 2) {   // staggered grid without a two-stage pass: LDS Stockham with complex multipliers
+        switch (mode) {
+            case Z_CG: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_CG, 2), ZA, nblk, kBlock, lds); break;
+            case Z_RHS: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_RHS, 2), ZA, nblk, kBlock, lds); break;
+            case Z_PROJ: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_PROJ, 2), ZA, nblk, kBlock, lds); break;
+            case Z_INV_CG: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_CG, 2), ZA, nblk, kBlock, lds); break;
+            default: COMBO_LAUNCH(k_zpass_inv, (T, TU, Z_INV_PLAIN, 2), ZA, nblk, kBlock, lds); break;
+        }
+        return hipGetLastError();
+    }
     if (a.g.disc) {
         switch (mode) {
             case Z_CG: COMBO_LAUNCH(k_zpass_fwd, (T, TU, Z_CG, 1), ZA, nblk, kBlock, lds); break;

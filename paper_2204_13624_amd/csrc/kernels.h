@@ -50,6 +50,8 @@ struct XArgs {
     cpx<T>* out;                // [9][n3*n2][nh]
     const double* real_in;      // [9][n]
     double* real_out;           // [9][n]
+    const T* real_in_t;         // [9][n] in the pass's precision (used instead of real_in if set)
+    T* real_out_t;              // [9][n] in the pass's precision (used instead of real_out if set)
     double scale;               // 1/n for X_AVG and X_INV_REAL
     TangentState<T> ts;
     double E[9];

@@ -253,9 +253,8 @@ int ensure_work(combo_ctx* ctx) {
     if (ctx->g.disc == COMBO_DISC_STAGGERED) {
         const size_t n8 = 8 * (size_t)n;
         HIP_OR_FAIL(ctx->dfmg_Pd.ensure(sizeof(double) * 9 * n8));
-        HIP_OR_FAIL(ctx->dfmg_Sd.ensure(sizeof(double) * 10 * n8));
         HIP_OR_FAIL(ctx->dfmg_Ad.ensure(sizeof(double) * 45 * 8 * (size_t)std::max(ctx->nc, 1)));
-        HIP_OR_FAIL(ctx->dfmg_dPd.ensure(sizeof(double) * 9 * n8));
+        HIP_OR_FAIL(ctx->dfmg_act.ensure(sizeof(double) * 27 * (size_t)n));   // own [9][n] + parts [18][n]
         HIP_OR_FAIL(ctx->dfmg_dH.ensure(f9));
         HIP_OR_FAIL(ctx->dfmg_dQ.ensure(f9));
         HIP_OR_FAIL(ctx->stag_tmp.ensure(f9));
@@ -424,7 +423,6 @@ int material_dfmg(combo_ctx* ctx, const double* F_old, const double* dF, double 
         d.lam[p] = ctx->mats[p].lambda;
     }
     d.Pd = ctx->dfmg_Pd.as<double>();
-    d.Sd = ctx->dfmg_Sd.as<T>();
     d.Ad = ctx->dfmg_Ad.as<T>();
     d.partials = ctx->part1.as<double>();
     d.partials2 = ctx->part2.as<double>();
@@ -440,6 +438,7 @@ int material_dfmg(combo_ctx* ctx, const double* F_old, const double* dF, double 
     HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
     prof_harvest(ctx);
     ctx->state_prec = sizeof(T) == 4 ? COMBO_MIXED : COMBO_FP64;
+    ctx->dfmg_Feval = F_new;   // pure doubly-fine tangents are recomputed from it
     return COMBO_OK;
 }
 
@@ -539,13 +538,14 @@ int residual(combo_ctx* ctx, double mu0, double kappa0, double tol_cg, double& e
 
 // The tangent action of the staggered grid on the spectrum in specB (after the y
 // inverse pass): inverse x pass to the shifted-layout field dH, per doubly-fine
-// cell A : dF, their DFMG sum dQ, forward x pass into specA.  Kernels skip once
-// the CG state says done.
+// cell A : dF summed per destination, the DFMG sum dQ, forward x pass into specA;
+// real fields in the precision of the CG.  Kernels skip once the CG state says done.
 template <typename T>
 int stag_tangent_x(combo_ctx* ctx, hipStream_t s) {
+    const long long n = ctx->g.n;
     XArgs<T> xi = xargs<T>(ctx);
     xi.in = ctx->specB.as<cpx<T>>();
-    xi.real_out = ctx->dfmg_dH.as<double>();
+    xi.real_out_t = ctx->dfmg_dH.as<T>();
     xi.scale = 1.0;   // the 1/n of the operator is applied by the z pass
     xi.skip_done = 1;
     HIP_OR_FAIL(launch_x<T>(X_INV_REAL, xi, s));
@@ -553,23 +553,24 @@ int stag_tangent_x(combo_ctx* ctx, hipStream_t s) {
     act.n1 = ctx->g.n1;
     act.n2 = ctx->g.n2;
     act.n3 = ctx->g.n3;
-    act.n = ctx->g.n;
-    act.dH = ctx->dfmg_dH.as<double>();
-    act.dPd = ctx->dfmg_dPd.as<T>();
+    act.n = n;
+    act.dH = ctx->dfmg_dH.as<T>();
+    act.F = ctx->dfmg_Feval;
+    act.own = ctx->dfmg_act.as<T>();
+    act.part = ctx->dfmg_act.as<T>() + 9 * n;
     act.slot = ctx->slot.as<int>();
-    act.Sd = ctx->dfmg_Sd.as<T>();
     act.Ad = ctx->dfmg_Ad.as<T>();
     for (int p = 0; p < 2; ++p) {
-        act.mu[p] = T(ctx->mats[p].mu);
-        act.lam[p] = T(ctx->mats[p].lambda);
+        act.mu[p] = ctx->mats[p].mu;
+        act.lam[p] = ctx->mats[p].lambda;
     }
     act.st = ctx->cgst.as<CGState>();
     HIP_OR_FAIL(launch_dfmg_action<T>(act, s));
-    DfmgGatherArgs<T> ga{ctx->g.n1, ctx->g.n2, ctx->g.n3, ctx->g.n, ctx->dfmg_dPd.as<T>(), ctx->dfmg_dQ.as<double>(),
-                         ctx->cgst.as<CGState>()};
-    HIP_OR_FAIL(launch_dfmg_gather<T>(ga, s));
+    DfmgSumArgs<T> sm{ctx->g.n1, ctx->g.n2, ctx->g.n3, n, act.own, act.part, ctx->dfmg_dQ.as<T>(),
+                      ctx->cgst.as<CGState>()};
+    HIP_OR_FAIL(launch_dfmg_sum<T>(sm, s));
     XArgs<T> xf = xargs<T>(ctx);
-    xf.real_in = ctx->dfmg_dQ.as<double>();
+    xf.real_in_t = ctx->dfmg_dQ.as<T>();
     xf.out = ctx->specA.as<cpx<T>>();
     xf.skip_done = 1;
     HIP_OR_FAIL(launch_x<T>(X_FWD_REAL, xf, s));
