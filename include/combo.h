@@ -27,7 +27,7 @@
  *     N = unit interface normal pointing out of the inclusion (Sec. 2, 5.1).
  *     c and N are read only where phase == 2.
  *   - Materials: index 0 = matrix, 1 = inclusion, each (mu, lambda).
- *   - Every grid axis must be 1 or a product of 2s and 3s, at most 384
+ *   - Every grid axis must be 1 or a product of 2s and 3s, at most 512
  *     (COMBO_E_SIZE otherwise).
  *
  * Ownership: the caller owns every pointer it passes.  set_* calls copy their
@@ -155,7 +155,7 @@ void combo_default_options(combo_options* opt);
  * msg_len bytes) receives a description of the first problem. */
 int combo_validate_microstructure(int n1, int n2, int n3, const uint8_t* phase, const double* c,
                                   const double* N, char* msg, int msg_len);
-/* Returns COMBO_OK if n is 1 or a product of 2s and 3s not above 384. */
+/* Returns COMBO_OK if n is 1 or a product of 2s and 3s not above 512. */
 int combo_check_size(int n);
 
 /* Context ------------------------------------------------------------------ */

@@ -17,7 +17,8 @@ BUILD_DIR = os.path.join(HERE, "_build")
 
 # (source, defines): the FFT kernel file is compiled once per part, in parallel
 SOURCES = [("fft_kernels.hip", ["-DCOMBO_PART=%d" % k]) for k in range(1, 7)] + [
-    ("material_kernels.hip", []), ("dfmg_kernels.hip", []), ("boxels.hip", []), ("solver.hip", [])]
+    ("material_kernels.hip", []), ("dfmg_kernels.hip", []), ("boxels.hip", []), ("setup_kernels.hip", []),
+    ("solver.hip", [])]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -35,6 +35,8 @@ hipError_t launch_boxel_count(const BoxelArgs& a, hipStream_t s);
 // ints, list: nb ints; the count goes to counter[0]).
 int boxel_blocks(long long nb);
 hipError_t launch_boxel_list(const BoxelArgs& a, int* blockcnt, int* list, hipStream_t s);
+// Exclusive prefix of nblk ints in place (one workgroup); the total goes to total[0].
+hipError_t launch_block_scan(int* cnt, int nblk, int* total, hipStream_t s);
 // Pass 2b: moments (16 lanes per list entry, mom: 13 doubles per entry) and normals of the ncomp entries.
 hipError_t launch_boxel_normals(const BoxelArgs& a, const int* list, double* mom, int ncomp, hipStream_t s);
 

@@ -483,6 +483,11 @@ hipError_t launch_boxel_list(const BoxelArgs& a, int* blockcnt, int* list, hipSt
     return hipGetLastError();
 }
 
+hipError_t launch_block_scan(int* cnt, int nblk, int* total, hipStream_t s) {
+    hipLaunchKernelGGL(k_boxel_scan, dim3(1), dim3(1024), 0, s, cnt, nblk, total);
+    return hipGetLastError();
+}
+
 hipError_t launch_boxel_normals(const BoxelArgs& a, const int* list, double* mom, int ncomp, hipStream_t s) {
     if (ncomp <= 0) return hipSuccess;
     const long long blocks = std::min<long long>(((long long)ncomp * kTeam + 255) / 256, 65536);

@@ -11,7 +11,11 @@ namespace combo {
 constexpr int kBlock = 256;          // threads per workgroup of the FFT passes
 // complex elements held in LDS by one FFT workgroup (32 KiB of data either way)
 template <typename T> __host__ __device__ constexpr int max_elems() { return sizeof(T) == 4 ? 4096 : 2048; }
-constexpr int kMaxAxis = 768;        // largest supported grid axis
+constexpr int kMaxAxis = 512;        // largest supported grid axis
+// elements the generic x pass holds in LDS: five packed sequences of a row of up to kMaxAxis
+template <typename T> __host__ __device__ constexpr int xpass_cap() {
+    return 5 * kMaxAxis > max_elems<T>() ? 5 * kMaxAxis : max_elems<T>();
+}
 constexpr int kMaxPasses = 8;
 
 template <typename T> struct cpx_t;

@@ -175,7 +175,7 @@ __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int n
             if (2 * nk == L && k == nk - 1 && L > 1) col[L / 2] = mk<T>(0, 0);
         }
         __syncthreads();
-        fft_lds<+1, true, T>(buf, a.plan, 5 * R, tw);
+        fft_lds<+1, true, T, xpass_cap<T>()>(buf, a.plan, 5 * R, tw);
     }
 
     // pointwise stage
@@ -255,7 +255,7 @@ __device__ __forceinline__ void k_xpass_body(const XArgs<T>& a, int tile_, int n
     }
     if (!HAS_FWD) return;
     __syncthreads();
-    fft_lds<-1, true, T>(buf, a.plan, 5 * R, tw);
+    fft_lds<-1, true, T, xpass_cap<T>()>(buf, a.plan, 5 * R, tw);
     // pack: half spectra of both real components of every sequence
     const int items = 5 * R * nh;
     for (int it = tid; it < items; it += kBlock) {
@@ -2306,6 +2306,7 @@ hipError_t launch_x(int mode, const XArgs<T>& a, hipStream_t s, int* nb, const B
     }
     COMBO_XWAVE_CONFIGS(COMBO_XW_CASE)
 #undef COMBO_XW_CASE
+    if ((long long)5 * a.R * a.g.n1 > xpass_cap<T>()) return hipErrorInvalidValue;   // rows beyond the pass's capacity
     const int nblk = blocks_x(a.g, a.R, X_FWD_REAL, std::is_same<T, float>::value);
     if (nb) *nb = nblk;
     const size_t lds = sizeof(cpx<T>) * ((size_t)a.g.n1 + (size_t)5 * a.R * a.g.n1);

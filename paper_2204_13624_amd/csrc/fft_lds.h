@@ -145,9 +145,10 @@ __device__ __forceinline__ void dftR(C* v) {
     else dft16<DIR>(v);
 }
 
-template <int R, int DIR, bool COLMAJOR, typename T>
+// CAP: most elements (L TX) a call may hold; it sets the butterflies each thread keeps in flight.
+template <int R, int DIR, bool COLMAJOR, typename T, int CAP>
 __device__ __forceinline__ void stockham_pass(cpx<T>* buf, int L, int TX, int Ns, const cpx<T>* tw) {
-    constexpr int NB = (max_elems<T>() / R + kBlock - 1) / kBlock;
+    constexpr int NB = (CAP / R + kBlock - 1) / kBlock;
     const int tid = threadIdx.x;
     const int LR = L / R;
     const int nbf = LR * TX;
@@ -201,17 +202,18 @@ __device__ __forceinline__ void stockham_pass(cpx<T>* buf, int L, int TX, int Ns
 }
 
 // Transform TX columns of length plan.L held in buf; tw = forward twiddles of plan.L.
-template <int DIR, bool COLMAJOR, typename T>
+// plan.L * TX must not exceed CAP (callers size their tiles for it).
+template <int DIR, bool COLMAJOR, typename T, int CAP = max_elems<T>()>
 __device__ __forceinline__ void fft_lds(cpx<T>* buf, const AxisPlan& plan, int TX, const cpx<T>* tw) {
     int Ns = 1;
     for (int p = 0; p < plan.npass; ++p) {
         const int R = plan.radix[p];
         switch (R) {
-            case 2: stockham_pass<2, DIR, COLMAJOR, T>(buf, plan.L, TX, Ns, tw); break;
-            case 3: stockham_pass<3, DIR, COLMAJOR, T>(buf, plan.L, TX, Ns, tw); break;
-            case 4: stockham_pass<4, DIR, COLMAJOR, T>(buf, plan.L, TX, Ns, tw); break;
-            case 8: stockham_pass<8, DIR, COLMAJOR, T>(buf, plan.L, TX, Ns, tw); break;
-            default: stockham_pass<16, DIR, COLMAJOR, T>(buf, plan.L, TX, Ns, tw); break;
+            case 2: stockham_pass<2, DIR, COLMAJOR, T, CAP>(buf, plan.L, TX, Ns, tw); break;
+            case 3: stockham_pass<3, DIR, COLMAJOR, T, CAP>(buf, plan.L, TX, Ns, tw); break;
+            case 4: stockham_pass<4, DIR, COLMAJOR, T, CAP>(buf, plan.L, TX, Ns, tw); break;
+            case 8: stockham_pass<8, DIR, COLMAJOR, T, CAP>(buf, plan.L, TX, Ns, tw); break;
+            default: stockham_pass<16, DIR, COLMAJOR, T, CAP>(buf, plan.L, TX, Ns, tw); break;
         }
         Ns *= R;
     }

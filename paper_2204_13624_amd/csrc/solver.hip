@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -39,6 +40,7 @@
 
 #include "combo.h"
 #include "boxels.h"
+#include "setup.h"
 #include "context.h"
 #include "dfmg.h"
 
@@ -80,7 +82,7 @@ using clk = std::chrono::steady_clock;
 double ms_since(clk::time_point t0) { return std::chrono::duration<double, std::milli>(clk::now() - t0).count(); }
 
 bool size_ok(int n) {
-    if (n < 1 || n > 384) return false;
+    if (n < 1 || n > kMaxAxis) return false;
     while (n % 2 == 0) n /= 2;
     while (n % 3 == 0) n /= 3;
     return n == 1;
@@ -1963,6 +1965,24 @@ void combo_default_options(combo_options* o) {
 
 int combo_check_size(int n) { return size_ok(n) ? COMBO_OK : COMBO_E_SIZE; }
 
+}  // extern "C"
+
+namespace {
+// The problem with one voxel's values, or an empty string.
+std::string voxel_problem(long long v, int ph, double cv, double a, double b, double d) {
+    if (ph > 2) return "phase id " + std::to_string(ph) + " at voxel " + std::to_string(v) + " (must be 0, 1, 2)";
+    if (ph != 2) return std::string();
+    if (!(cv > 0.0 && cv < 1.0)) return "composite voxel " + std::to_string(v) + " has c outside (0, 1)";
+    if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(d))
+        return "composite voxel " + std::to_string(v) + " has a non-finite normal";
+    const double nn = std::sqrt(a * a + b * b + d * d);
+    if (std::fabs(nn - 1.0) > 1e-6) return "composite voxel " + std::to_string(v) + " normal is not unit length";
+    return std::string();
+}
+}  // namespace
+
+extern "C" {
+
 int combo_validate_microstructure(int n1, int n2, int n3, const uint8_t* phase, const double* c, const double* N,
                                   char* msg, int msg_len) {
     auto say = [&](const std::string& s) {
@@ -1977,15 +1997,10 @@ int combo_validate_microstructure(int n1, int n2, int n3, const uint8_t* phase, 
     const long long n = (long long)n1 * n2 * n3;
     for (long long v = 0; v < n; ++v) {
         const int ph = phase[v];
-        if (ph > 2) return say("phase id " + std::to_string(ph) + " at voxel " + std::to_string(v) + " (must be 0, 1, 2)");
-        if (ph != 2) continue;
-        const double cv = c[v];
-        if (!(cv > 0.0 && cv < 1.0)) return say("composite voxel " + std::to_string(v) + " has c outside (0, 1)");
-        const double a = N[v], b = N[n + v], d = N[2 * n + v];
-        if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(d))
-            return say("composite voxel " + std::to_string(v) + " has a non-finite normal");
-        const double nn = std::sqrt(a * a + b * b + d * d);
-        if (std::fabs(nn - 1.0) > 1e-6) return say("composite voxel " + std::to_string(v) + " normal is not unit length");
+        if (ph < 2) continue;
+        const std::string e = ph == 2 ? voxel_problem(v, ph, c[v], N[v], N[n + v], N[2 * n + v])
+                                      : voxel_problem(v, ph, 0.0, 0.0, 0.0, 0.0);
+        if (!e.empty()) return say(e);
     }
     if (msg && msg_len > 0) msg[0] = 0;
     return COMBO_OK;
@@ -2037,7 +2052,7 @@ const char* combo_last_error(const combo_ctx* ctx) { return ctx ? ctx->err.c_str
 int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2, double l3) {
     if (!ctx) return COMBO_E_INVAL;
     if (!size_ok(n1) || !size_ok(n2) || !size_ok(n3))
-        return set_err(ctx, COMBO_E_SIZE, "each grid axis must be 1 or 2^a 3^b <= 384");
+        return set_err(ctx, COMBO_E_SIZE, "each grid axis must be 1 or 2^a 3^b <= 512");
     if (!(l1 > 0 && l2 > 0 && l3 > 0) || !std::isfinite(l1) || !std::isfinite(l2) || !std::isfinite(l3))
         return set_err(ctx, COMBO_E_INVAL, "box lengths must be positive and finite");
     HIP_OR_FAIL(hipSetDevice(ctx->device));
@@ -2401,72 +2416,86 @@ int combo_set_microstructure(combo_ctx* ctx, const uint8_t* phase, const double*
     if (!phase || !c || !N) return set_err(ctx, COMBO_E_INVAL, "null microstructure pointer");
     if (mem_kind != COMBO_MEM_HOST && mem_kind != COMBO_MEM_DEVICE) return set_err(ctx, COMBO_E_INVAL, "bad mem_kind");
     HIP_OR_FAIL(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
     const long long n = ctx->g.n;
-    std::vector<uint8_t> hp;
-    std::vector<double> hc, hN;
+    // host fields are uploaded once; everything below runs on the device
+    DevBuf up;
     const uint8_t* P = phase;
     const double* C = c;
     const double* NN = N;
-    if (mem_kind == COMBO_MEM_DEVICE) {
-        hp.resize(n);
-        hc.resize(n);
-        hN.resize(3 * n);
-        HIP_OR_FAIL(hipMemcpy(hp.data(), phase, n, hipMemcpyDeviceToHost));
-        HIP_OR_FAIL(hipMemcpy(hc.data(), c, sizeof(double) * n, hipMemcpyDeviceToHost));
-        HIP_OR_FAIL(hipMemcpy(hN.data(), N, sizeof(double) * 3 * n, hipMemcpyDeviceToHost));
-        P = hp.data();
-        C = hc.data();
-        NN = hN.data();
+    if (mem_kind == COMBO_MEM_HOST) {
+        HIP_OR_FAIL(up.ensure(sizeof(double) * 4 * n + (size_t)n));   // c, N, then the phase bytes
+        double* cd = static_cast<double*>(up.p);
+        HIP_OR_FAIL(hipMemcpyAsync(cd, c, sizeof(double) * n, hipMemcpyHostToDevice, s));
+        HIP_OR_FAIL(hipMemcpyAsync(cd + n, N, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+        HIP_OR_FAIL(hipMemcpyAsync(cd + 4 * n, phase, n, hipMemcpyHostToDevice, s));
+        C = cd;
+        NN = cd + n;
+        P = reinterpret_cast<const uint8_t*>(cd + 4 * n);
     }
-    char msg[256];
-    if (combo_validate_microstructure(ctx->g.n1, ctx->g.n2, ctx->g.n3, P, C, NN, msg, sizeof(msg)) != COMBO_OK)
-        return set_err(ctx, COMBO_E_INVAL, msg);
-    std::vector<int> slot(n);
-    std::vector<int> vox;
-    std::vector<double> cc, nrm;
-    double nm = 0, ni = 0, sc = 0;
-    for (long long v = 0; v < n; ++v) {
-        if (P[v] == 0) {
-            slot[v] = -1;
-            nm += 1;
-        } else if (P[v] == 1) {
-            slot[v] = -2;
-            ni += 1;
-        } else {
-            slot[v] = (int)vox.size();
-            vox.push_back((int)v);
-            cc.push_back(C[v]);
-            sc += C[v];
+    const int nblk = setup_blocks(n);
+    DevBuf wk;   // cnt2[nblk] cnt01[2 nblk] flags[2] | sumc[nblk]
+    const size_t ints = (size_t)3 * nblk + 2, off_d = (ints * sizeof(int) + 255) / 256 * 256;
+    HIP_OR_FAIL(wk.ensure(off_d + sizeof(double) * nblk));
+    SetupArgs a{};
+    a.phase = P;
+    a.c = C;
+    a.N = NN;
+    a.n = n;
+    a.cnt2 = static_cast<int*>(wk.p);
+    a.cnt01 = a.cnt2 + nblk;
+    a.flags = a.cnt2 + 3 * nblk;
+    a.sumc = reinterpret_cast<double*>(static_cast<char*>(wk.p) + off_d);
+    HIP_OR_FAIL(launch_setup_reset(a.flags, s));
+    HIP_OR_FAIL(launch_setup_count(a, s));
+    int fl[2];
+    std::vector<int> c01((size_t)2 * nblk);
+    std::vector<double> sc(nblk);
+    HIP_OR_FAIL(hipMemcpyAsync(fl, a.flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipMemcpyAsync(c01.data(), a.cnt01, sizeof(int) * 2 * nblk, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipMemcpyAsync(sc.data(), a.sumc, sizeof(double) * nblk, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    if (fl[0] != INT_MAX) {   // the first invalid voxel: its values make the message
+        const long long v = fl[0];
+        uint8_t ph = 0;
+        double vals[4] = {0, 0, 0, 0};
+        HIP_OR_FAIL(hipMemcpy(&ph, P + v, 1, hipMemcpyDeviceToHost));
+        if (ph == 2) {
+            HIP_OR_FAIL(hipMemcpy(&vals[0], C + v, sizeof(double), hipMemcpyDeviceToHost));
+            for (int d = 0; d < 3; ++d)
+                HIP_OR_FAIL(hipMemcpy(&vals[1 + d], NN + d * n + v, sizeof(double), hipMemcpyDeviceToHost));
         }
+        std::string e = voxel_problem(v, ph, vals[0], vals[1], vals[2], vals[3]);
+        if (e.empty()) e = "voxel " + std::to_string(v) + " failed validation";
+        return set_err(ctx, COMBO_E_INVAL, e);
     }
-    const int nc = (int)vox.size();
-    nrm.resize(3 * (size_t)std::max(nc, 1));
-    for (int i = 0; i < nc; ++i) {
-        const long long v = vox[i];
-        double a = NN[v], b = NN[n + v], d = NN[2 * n + v];
-        const double s = 1.0 / std::sqrt(a * a + b * b + d * d);
-        nrm[i] = a * s;
-        nrm[nc + i] = b * s;
-        nrm[2 * nc + i] = d * s;
+    double nm = 0, ni = 0, sumc = 0;
+    for (int b = 0; b < nblk; ++b) {
+        nm += c01[2 * (size_t)b];
+        ni += c01[2 * (size_t)b + 1];
+        sumc += sc[b];
     }
-    ctx->nc = nc;
-    ctx->n_mat = nm;
-    ctx->n_incl = ni;
-    ctx->sum_c = sc;
-    std::vector<int> slot_s(n);
-    for (long long v = 0; v < n; ++v) slot_s[state_pos(v, ctx->g.n1, ctx->g.xm, ctx->g.xwbits)] = slot[v];
+    const int nc = fl[1];
     HIP_OR_FAIL(ctx->slot_s.ensure(sizeof(int) * n));
-    HIP_OR_FAIL(hipMemcpy(ctx->slot_s.p, slot_s.data(), sizeof(int) * n, hipMemcpyHostToDevice));
     HIP_OR_FAIL(ctx->slot.ensure(sizeof(int) * n));
     HIP_OR_FAIL(ctx->comp_vox.ensure(sizeof(int) * std::max(nc, 1)));
     HIP_OR_FAIL(ctx->comp_c.ensure(sizeof(double) * std::max(nc, 1)));
     HIP_OR_FAIL(ctx->comp_N.ensure(sizeof(double) * 3 * std::max(nc, 1)));
-    HIP_OR_FAIL(hipMemcpy(ctx->slot.p, slot.data(), sizeof(int) * n, hipMemcpyHostToDevice));
-    if (nc) {
-        HIP_OR_FAIL(hipMemcpy(ctx->comp_vox.p, vox.data(), sizeof(int) * nc, hipMemcpyHostToDevice));
-        HIP_OR_FAIL(hipMemcpy(ctx->comp_c.p, cc.data(), sizeof(double) * nc, hipMemcpyHostToDevice));
-        HIP_OR_FAIL(hipMemcpy(ctx->comp_N.p, nrm.data(), sizeof(double) * 3 * nc, hipMemcpyHostToDevice));
-    }
+    a.n1 = ctx->g.n1;
+    a.xm = ctx->g.xm;
+    a.xwbits = ctx->g.xwbits;
+    a.nc = nc;
+    a.slot = ctx->slot.as<int>();
+    a.slot_s = ctx->slot_s.as<int>();
+    a.comp_vox = ctx->comp_vox.as<int>();
+    a.comp_c = ctx->comp_c.as<double>();
+    a.comp_N = ctx->comp_N.as<double>();
+    HIP_OR_FAIL(launch_setup_compact(a, s));
+    HIP_OR_FAIL(hipStreamSynchronize(s));   // the uploads and work buffers are freed on return
+    ctx->nc = nc;
+    ctx->n_mat = nm;
+    ctx->n_incl = ni;
+    ctx->sum_c = sumc;
     int st = ensure_work(ctx);
     if (st) return st;
     for (auto& gr : ctx->graph) gr.reset();

@@ -41,9 +41,9 @@ def test_host_only_calls():
     o = combo.combo_default_options()
     assert o.tol_newton == 1e-8 and o.max_laminate == 50 and o.warm_start_laminate == 1
     assert o.law == combo.COMBO_LAW_NEO_HOOKE and o.line_search == 1
-    for n in (1, 2, 3, 6, 9, 16, 48, 96, 256, 384):
+    for n in (1, 2, 3, 6, 9, 16, 48, 96, 256, 384, 432, 486, 512):
         assert combo.combo_check_size(n) == combo.COMBO_OK
-    for n in (0, 5, 7, 10, 11, 768, 512):
+    for n in (0, 5, 7, 10, 11, 576, 648, 768, 1024):
         assert combo.combo_check_size(n) == combo.COMBO_E_SIZE
 
 
