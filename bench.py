@@ -238,6 +238,98 @@ def batch_bench(combo, synth, steps):
             "one_by_one_time_s": seq, "one_by_one_value": seq_it / seq, "speedup_vs_one_by_one": seq / wall}
 
 
+def fibres_bench(combo, synth, seconds):
+    """The fibre workload (256^3, 60 random straight fibres, near-incompressible matrix,
+    fibre contrast 1000, simple shear 0.3 e1 (x) e2 in 30 increments), mixed precision
+    (FP64 det F, ln J, laminates, residual).  The load path is walked with an adaptive
+    step: from the converged state at fraction t one solve to t + dt (one increment, no
+    internal cutbacks); a converged step doubles dt up to 1/30, a failed one halves it.
+    The walk ends when dt drops below 1/(32 x 30) (the solver's own cutback limit), at
+    the end of the path, or after `seconds`.  The effective tangent Abar is computed at
+    the last converged load."""
+    import torch
+    t = time.time()
+    ms, lc = synth.workload_fibres_256()
+    gen_s = time.time() - t
+    dev = torch.device("cuda:0")
+    ctx = combo.combo_create(0)
+    combo.combo_set_grid(ctx, *ms.n, *ms.l)
+    combo.combo_set_materials(ctx, lc.mats)
+    combo.combo_set_microstructure(ctx, torch.from_numpy(ms.phase).to(dev), torch.from_numpy(ms.c).to(dev),
+                                   torch.from_numpy(np.ascontiguousarray(ms.N)).to(dev))
+    o = combo.combo_default_options()
+    o.precision = combo.COMBO_MIXED
+    o.tol_newton = 1e-6
+    o.tol_cg = 1e-4
+    o.max_cg = 4000
+    o.max_newton = 15
+    o.n_increments = 1
+    o.max_cutbacks = 0
+    combo.combo_set_options(ctx, o)
+    H = lc.Fbar - np.eye(3)
+    K = lc.n_increments
+    F = torch.zeros((9,) + ms.phase.shape, dtype=torch.float64, device=dev)
+    F[0] = F[4] = F[8] = 1.0
+    Fn = torch.empty_like(F)
+    tt, dt = 0.0, 1.0 / K
+    tot = dict(newton=0, cg=0, trunc=0, attempts=0, converged=0)
+    walk = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stop = "end of load path"
+    while tt < 1.0 - 1e-12:
+        if dt < 1.0 / (32 * K):
+            stop = "step below 1/32 of an increment"
+            break
+        if time.perf_counter() - t0 > seconds:
+            stop = "time cap"
+            break
+        tn = min(1.0, tt + dt)
+        try:
+            r = combo.combo_solve(ctx, np.eye(3) + tn * H, F_init=F, F_out=Fn)
+            ok = True
+        except combo.ComboError as e:
+            r, ok = e.result, False
+        s = r["stats"]
+        tot["newton"] += s["newton_iters"]
+        tot["cg"] += s["cg_iters_total"]
+        tot["trunc"] += s["cg_truncations"]
+        tot["attempts"] += 1
+        walk.append([round(0.3 * tn, 6), int(ok)])
+        if ok:
+            F, Fn = Fn, F
+            tt = tn
+            tot["converged"] += 1
+            Pbar_last = r["Pbar"]
+            dt = min(1.0 / K, 2 * dt)
+        else:
+            dt *= 0.5
+    torch.cuda.synchronize()
+    walk_s = time.perf_counter() - t0
+    res = {"workload": "fibres_256: 256^3, 60 fibres r=0.025 L (c=%.3f after overlaps), %d composites, "
+                       "matrix (mu, lambda) = (1, 1000), fibres (1000, 1e6), simple shear 0.3 e1 (x) e2 in 30 "
+                       "increments" % (ms.info.get("c_total", float(ms.c.mean())), ms.n_composite),
+           "precision": "mixed (FP64 det F, ln J, laminates, residual), eta<=1e-6, tol_cg 1e-4",
+           "generation_s": round(gen_s, 1), "walk_s": walk_s, "stop": stop,
+           "last_converged_shear": 0.3 * tt, "attempts": tot["attempts"], "converged_steps": tot["converged"],
+           "newton_iters": tot["newton"], "cg_iters": tot["cg"], "cg_truncations": tot["trunc"],
+           "voxel_cg_iters_per_s": ms.nvox * tot["cg"] / walk_s, "walk": walk}
+    if tt > 0:
+        o.want_tangent = 1
+        combo.combo_set_options(ctx, o)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = combo.combo_solve(ctx, np.eye(3) + tt * H, F_init=F, F_out=Fn, want_tangent=True)
+        torch.cuda.synchronize()
+        res["tangent_s"] = time.perf_counter() - t1
+        res["tangent_cg_iters"] = r["stats"]["cg_iters_tangent"]
+        res["Pbar_last"] = [[float("%.6g" % v) for v in row] for row in Pbar_last]
+        res["Abar_last"] = [[float("%.6g" % v) for v in row] for row in r["Abar"]]
+    combo.combo_destroy(ctx)
+    log("fibres: %s at shear %.5f after %d attempts, %.1f s" % (stop, 0.3 * tt, tot["attempts"], walk_s))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +347,9 @@ def main():
     ap.add_argument("--no-image", action="store_true")
     ap.add_argument("--no-willot", action="store_true")
     ap.add_argument("--no-staggered", action="store_true")
+    ap.add_argument("--no-fibres", action="store_true")
+    ap.add_argument("--fibre-seconds", type=float, default=120.0,
+                    help="time cap of the fibre workload's load walk")
     ap.add_argument("--increments", type=int, default=0,
                     help="override the workload's load increments (shorter runs for counter collection)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -445,11 +540,12 @@ def main():
         ps = combo.combo_profile_all(ctx)
         combo.combo_profile_enable(ctx, False)
         cg_st = rs["stats"]["cg_iters_total"]
-        # algorithmic bytes of one CG iteration's tangent part (x passes, DFMG action, DFMG sum):
-        # real FP64 field out and in (2 x 72 B), DFMG action: dH (72 B) + state (80 s) + dP (72 s) per cell,
-        # DFMG sum: dP (72 s) in + dQ (72 B) out; s = 4
+        # algorithmic bytes of one CG iteration's tangent part, FP32 fields: x inverse (9 complex
+        # half spectra in, dH 36 B/voxel out), DFMG action (dH 36 B, F in FP64 72 B, slot 4 B in;
+        # own + parts 108 B out; 8 packed 45-entry tangents, 1440 B, per composite), DFMG sum
+        # (108 B in, dQ 36 B out), x forward (dQ 36 B in, 9 complex half spectra out)
         nspec_st = (ms.n[0] // 2 + 1) * ms.n[1] * ms.n[2]
-        xb = n * (72 * 2 + 72 + 80 * 4 + 72 * 4 + 72 * 4 + 72) + 2 * 9 * 8 * nspec_st
+        xb = 2 * 9 * 8 * nspec_st + n * (36 + 36 + 72 + 4 + 108 + 108 + 36 + 36) + 1440 * ms.n_composite
         xms, xcnt = ps.get("xpass_cg", (0.0, 0))
         out["staggered"] = {"discretization": "staggered grid, DFMG law (8 doubly-fine cells per cell), mixed",
                             "load": "first %d of %d increments (%.0f %% stretch)" % (
@@ -489,6 +585,7 @@ def main():
     combo.combo_destroy(ctx)
     out["image_to_boxels"] = None if args.no_image else image_bench(combo, synth, ms, args.steps)
     out["batch"] = None if args.no_batch else batch_bench(combo, synth, args.steps)
+    out["fibres"] = None if args.no_fibres else fibres_bench(combo, synth, args.fibre_seconds)
     if not args.no_cpu:
         t = time.time()
         out["cpu_baseline"] = cpu_baseline(ms, lc)

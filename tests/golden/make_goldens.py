@@ -19,7 +19,17 @@ Cases (python tests/golden/make_goldens.py CASE [CASE ...]; "all" runs every one
                    one core, so the whole grid is out of reach);
   batch_b<k>       member k of the 64-RVE batch workload, for the first member of
                    each (grid size, inclusion kind) pair: its own materials, Fbar
-                   and load increments.
+                   and load increments;
+  fibres_32        the fibre workload (60 random straight fibres, near-incompressible
+                   matrix, fibre contrast 1000, simple shear 0.3 e1 (x) e2 in 30
+                   increments) on a 32^3 grid, walked with the adaptive load-step rule
+                   below for its first WALK_ATTEMPTS attempts: which attempts converge,
+                   and Pbar where they do.
+
+Load-step rule of fibres_32 (the same rule drives the GPU side of its test): from the
+converged state at load fraction t, one solve to t + dt with one increment and no
+internal cutbacks (max_newton 20, max_cg 4000); if it converges, t += dt and dt is
+doubled up to 1/30, else dt is halved.
 
 Tolerances: Newton eta <= 1e-10 and CG |r|/|b| <= 1e-8; Newton converges
 quadratically from the last inexact step, so the stored Pbar is the discrete
@@ -92,7 +102,55 @@ def case_inputs(name):
     raise KeyError(name)
 
 
+WALK_ATTEMPTS = 4
+WALK_OPTS = dict(tol_newton=1e-8, tol_cg=1e-8, n_increments=1, max_cutbacks=0, max_newton=20, max_cg=4000)
+
+
+def run_walk(name):
+    n = int(name[len("fibres_"):])
+    ms, lc = synth.workload_fibres_256(n)
+    prob = osol.Problem(ms.n, ms.l, ms.phase, ms.c, ms.N, lc.mats)
+    opts = osol.Options(**WALK_OPTS)
+    H = lc.Fbar - np.eye(3)
+    K = lc.n_increments
+    F = np.broadcast_to(np.eye(3)[:, :, None, None, None], (3, 3) + ms.phase.shape).copy()
+    t, dt = 0.0, 1.0 / K
+    attempts = []
+    t0 = time.time()
+    for _ in range(WALK_ATTEMPTS):
+        tn = min(1.0, t + dt)
+        a0 = time.time()
+        rec = {"t_from": t, "t_to": tn}
+        try:
+            r = osol.solve(prob, np.eye(3) + tn * H, opts, F_init=F)
+        except osol.SolveError as e:
+            rec.update(ok=False, status=int(e.status))
+            dt *= 0.5
+        else:
+            st = r["stats"]
+            rec.update(ok=True, Pbar=r["Pbar"].reshape(9).tolist(), newton_iters=st["newton_iters"],
+                       cg_iters=st["cg_iters"], cg_truncations=st["cg_truncations"], eta_final=st["eta"][-1])
+            F = r["F"]
+            t = tn
+            dt = min(1.0 / K, 2 * dt)
+        rec["wall_s"] = round(time.time() - a0, 1)
+        attempts.append(rec)
+        print("  shear %.5f -> %.5f %s %.0f s" % (0.3 * rec["t_from"], 0.3 * rec["t_to"],
+                                                 "ok" if rec["ok"] else "FAIL", rec["wall_s"]), flush=True)
+    out = {"case": name, "inputs": "synth.workload_fibres_256(%d): 60 fibres r = 0.025 L, c = 0.35, "
+                                    "shear 0.3 e1 (x) e2 in 30 increments" % n,
+           "n": list(ms.n), "l": list(ms.l), "mats": [list(m) for m in lc.mats],
+           "H": H.reshape(9).tolist(), "n_increments": K, "n_composite": int((ms.phase == 2).sum()),
+           "walk_options": WALK_OPTS, "attempts": attempts, "wall_s": round(time.time() - t0, 1)}
+    path = os.path.join(HERE, "oracle_%s.json" % name)
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("%s -> %s" % (name, path), flush=True)
+
+
 def run(name):
+    if name.startswith("fibres_"):
+        return run_walk(name)
     ms, mats, Fbar, K, desc = case_inputs(name)
     prob = osol.Problem(ms.n, ms.l, ms.phase, ms.c, ms.N, mats)
     opts = osol.Options(tol_newton=TOL_NEWTON, tol_cg=TOL_CG, n_increments=K, max_cg=20000)
@@ -119,9 +177,9 @@ def run(name):
 if __name__ == "__main__":
     names = sys.argv[1:]
     if names == ["all"]:
-        names = ["spheres_64", "spheres_256_crop"] + ["batch_b%d" % k for k in batch_subset()]
+        names = ["spheres_64", "spheres_256_crop", "fibres_32"] + ["batch_b%d" % k for k in batch_subset()]
     if names == ["list"]:
-        print(" ".join(["spheres_64", "spheres_256_crop"] + ["batch_b%d" % k for k in batch_subset()]))
+        print(" ".join(["spheres_64", "spheres_256_crop", "fibres_32"] + ["batch_b%d" % k for k in batch_subset()]))
         sys.exit(0)
     for nm in names:
         run(nm)
