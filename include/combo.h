@@ -116,7 +116,7 @@ typedef struct {
     int line_search;          /* 1 (default): a Newton step F + s dF is taken only if the residual decreases,
                                  eta(s) <= (1 - 1e-4 s) eta, halving s otherwise (max_step_halvings) */
     int law;                  /* COMBO_LAW_NEO_HOOKE (default) or COMBO_LAW_LINEAR */
-    int batch_streams;        /* batches: at most this many lanes (streams), 0 = 4, at most 16; see combo_batch_solve */
+    int batch_streams;        /* batches: at most this many lanes (streams), 0 = 8, at most 16; see combo_batch_solve */
 } combo_options;
 
 typedef struct {
@@ -146,7 +146,7 @@ const char* combo_strerror(int status);
 /* Fill opt with the defaults: FP64, tol_newton 1e-8, tol_cg 1e-10, max_newton 30,
  * max_cg 5000, max_laminate 50, 1 increment, default C0, warm start on,
  * no tangent, 10 step halvings, 5 cutbacks, graph_chunk 0, no autotuning,
- * line search on, Neo-Hooke law, batch_streams 0 (4 lanes). */
+ * line search on, Neo-Hooke law, batch_streams 0 (8 lanes). */
 void combo_default_options(combo_options* opt);
 
 /* Host-only validation of a microstructure (no GPU needed).  Checks phase ids,
@@ -340,8 +340,9 @@ int combo_profile_read_idle(combo_ctx* ctx, int kernel, double* ms_total, long l
  * Many independent RVEs, each with its own grid, box, materials and
  * microstructure, solved together on one GPU (the many-RVE workloads of
  * multiscale FE^2-type use, paper Sec. 1).  The members are split into lanes
- * (at most options.batch_streams, default 4): members of one grid shape share a
- * lane, lanes hold contiguous ranges of grid sizes, and each lane runs on a
+ * (at most options.batch_streams, default 8): members of one grid shape share a
+ * lane, lanes hold contiguous ranges of grid sizes (with fewer shapes than
+ * lanes, the most populated shapes are split), and each lane runs on a
  * stream of its own (lane 0 on the batch's stream, the others on streams the
  * batch creates and owns).  Within a lane every pass runs as one launch over
  * all members that share its kernel shape (axis length), each workgroup

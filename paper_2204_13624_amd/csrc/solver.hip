@@ -1640,7 +1640,8 @@ struct Lane {
 
 // Members -> at most L lanes.  Members of one grid shape (n1, n2, n3, discretization)
 // share a lane; shapes are ordered by voxel count and cut into contiguous lanes of
-// about nm / L members each.  Returns member lists in ascending grid size.
+// about nm / L members each.  With fewer shapes than L, the most populated shapes are
+// split over the spare lanes.  Returns member lists in ascending grid size.
 std::vector<std::vector<int>> assign_lanes(const std::vector<combo_ctx*>& mem, int L) {
     const int nm = (int)mem.size();
     std::vector<int> order(nm);
@@ -1655,7 +1656,21 @@ std::vector<std::vector<int>> assign_lanes(const std::vector<combo_ctx*>& mem, i
         if (k == 0 || key(order[k]) != key(order[k - 1])) shapes.emplace_back();
         shapes.back().push_back(order[k]);
     }
-    if ((int)shapes.size() <= L) return shapes;
+    if ((int)shapes.size() <= L) {
+        // spare lanes: split the most populated lanes (members dealt alternately), so that a long
+        // Newton-CG chain of one member holds up fewer of its shape's members
+        while ((int)shapes.size() < L) {
+            size_t big = 0;
+            for (size_t k = 1; k < shapes.size(); ++k)
+                if (shapes[k].size() > shapes[big].size()) big = k;
+            if (shapes[big].size() < 2) break;
+            std::vector<int> a, b;
+            for (size_t k = 0; k < shapes[big].size(); ++k) (k % 2 ? b : a).push_back(shapes[big][k]);
+            shapes[big] = a;
+            shapes.insert(shapes.begin() + big + 1, b);
+        }
+        return shapes;
+    }
     std::vector<std::vector<int>> lanes;
     const double target = (double)nm / L;
     for (const auto& sh : shapes) {
@@ -2975,7 +2990,7 @@ int combo_batch_solve(combo_batch* B, const double* Fbar, const int* n_increment
         }
     }
     // lanes: members of similar grid size share launches on a stream of their own
-    const int nlanes_max = B->opt.batch_streams > 0 ? B->opt.batch_streams : 4;
+    const int nlanes_max = B->opt.batch_streams > 0 ? B->opt.batch_streams : 8;
     const std::vector<std::vector<int>> lane_members = assign_lanes(B->members, nlanes_max);
     while (B->lane_streams.size() + 1 < lane_members.size()) {
         hipStream_t ls = nullptr;
