@@ -195,7 +195,8 @@ int combo_set_grid(combo_ctx* ctx, int n1, int n2, int n3, double l1, double l2,
  *   out.  Fields passed in or out (F_init, F_out, P_out, combo_eval_law,
  *   combo_apply_green, combo_apply_operator) hold the staggered values: component
  *   (a, b) at index xi is the value at cell xi's own position of that component.
- *   Finite-strain law only; no effective tangent (want_tangent) and no batches.
+ *   Finite-strain law only, no batches.  The effective tangent (want_tangent) is the
+ *   derivative of <P> with P the DFMG stress: nine CG solves with the DFMG tangent.
  * Rebuilds the grid's frequency data like combo_set_grid and therefore resets the
  * microstructure: call after combo_set_grid, before combo_set_microstructure. */
 #define COMBO_DISC_MS 0

@@ -103,6 +103,15 @@ struct DfmgGatherArgs {
 };
 template <typename TI> hipError_t launch_dfmg_gather(const DfmgGatherArgs<TI>& a, hipStream_t s);
 
+// A uniform tensor E as a [9][n] field (add = 1: added to f); the same in both layouts.
+struct UniformE {
+    double v[9];
+};
+template <typename T> hipError_t launch_stag_uniform(T* f, long long n, const double E[9], int add, hipStream_t s);
+// Per-workgroup FP64 sums of the nine components of a [9][n] field: partials [stag_sum_blocks(n)][9].
+int stag_sum_blocks(long long n);
+template <typename T> hipError_t launch_stag_field_sums(const T* f, long long n, double* partials, hipStream_t s);
+
 // Natural staggered layout <-> shifted layout of a [9][n] field:
 // dir = +1: out_aJ[xi] = in_aJ[xi + e_J] (natural -> shifted), dir = -1 the inverse;
 // diagonal components are copied.  in and out must not overlap.

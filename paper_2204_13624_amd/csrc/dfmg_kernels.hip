@@ -443,6 +443,34 @@ __global__ void __launch_bounds__(256) k_stag_shift(const double* in, double* ou
     }
 }
 
+// f[c][v] = E_c (add = 0) or f[c][v] += E_c (add = 1): a uniform tensor field, the same in
+// the natural and the shifted layout
+template <typename T>
+__global__ void __launch_bounds__(256) k_stag_uniform(T* f, long long n, UniformE E, int add) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < 9 * n;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(e / n);
+        f[e] = add ? T(double(f[e]) + E.v[c]) : T(E.v[c]);
+    }
+}
+
+// per-workgroup sums of the nine components of a [9][n] field, in FP64 and a fixed order
+template <typename T>
+__global__ void __launch_bounds__(256) k_stag_field_sums(const T* f, long long n, double* partials) {
+    __shared__ double red[4];
+    for (int c = 0; c < 9; ++c) {
+        double acc = 0.0;
+        for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+             v += (long long)gridDim.x * blockDim.x)
+            acc += double(f[(long long)c * n + v]);
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) partials[(long long)blockIdx.x * 9 + c] = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
+    }
+}
+
 unsigned grid_for(long long items) {
     const long long b = (items + 255) / 256;
     return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
@@ -515,5 +543,29 @@ template hipError_t launch_dfmg_action<double>(const DfmgActArgs<double>&, hipSt
 template hipError_t launch_dfmg_sum<float>(const DfmgSumArgs<float>&, hipStream_t);
 template hipError_t launch_dfmg_sum<double>(const DfmgSumArgs<double>&, hipStream_t);
 template hipError_t launch_dfmg_gather<double>(const DfmgGatherArgs<double>&, hipStream_t);
+
+template <typename T>
+hipError_t launch_stag_uniform(T* f, long long n, const double E[9], int add, hipStream_t s) {
+    UniformE u;
+    for (int c = 0; c < 9; ++c) u.v[c] = E[c];
+    hipLaunchKernelGGL(k_stag_uniform<T>, dim3(grid_for(9 * n)), dim3(256), 0, s, f, n, u, add);
+    return hipGetLastError();
+}
+
+int stag_sum_blocks(long long n) {
+    const long long b = (n + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+template <typename T>
+hipError_t launch_stag_field_sums(const T* f, long long n, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_stag_field_sums<T>, dim3(stag_sum_blocks(n)), dim3(256), 0, s, f, n, partials);
+    return hipGetLastError();
+}
+
+template hipError_t launch_stag_uniform<float>(float*, long long, const double*, int, hipStream_t);
+template hipError_t launch_stag_uniform<double>(double*, long long, const double*, int, hipStream_t);
+template hipError_t launch_stag_field_sums<float>(const float*, long long, double*, hipStream_t);
+template hipError_t launch_stag_field_sums<double>(const double*, long long, double*, hipStream_t);
 
 }  // namespace combo

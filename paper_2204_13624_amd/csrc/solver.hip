@@ -542,15 +542,11 @@ int residual(combo_ctx* ctx, double mu0, double kappa0, double tol_cg, double& e
 // inverse pass): inverse x pass to the shifted-layout field dH, per doubly-fine
 // cell A : dF summed per destination, the DFMG sum dQ, forward x pass into specA;
 // real fields in the precision of the CG.  Kernels skip once the CG state says done.
+// dQ = the DFMG sum of A : dH per doubly-fine cell (dH and dQ in the shifted layout, in
+// the precision T); st: skip once the CG state says done (null: always run)
 template <typename T>
-int stag_tangent_x(combo_ctx* ctx, hipStream_t s) {
+int stag_action_sum(combo_ctx* ctx, hipStream_t s, const CGState* st) {
     const long long n = ctx->g.n;
-    XArgs<T> xi = xargs<T>(ctx);
-    xi.in = ctx->specB.as<cpx<T>>();
-    xi.real_out_t = ctx->dfmg_dH.as<T>();
-    xi.scale = 1.0;   // the 1/n of the operator is applied by the z pass
-    xi.skip_done = 1;
-    HIP_OR_FAIL(launch_x<T>(X_INV_REAL, xi, s));
     DfmgActArgs<T> act{};
     act.n1 = ctx->g.n1;
     act.n2 = ctx->g.n2;
@@ -566,11 +562,23 @@ int stag_tangent_x(combo_ctx* ctx, hipStream_t s) {
         act.mu[p] = ctx->mats[p].mu;
         act.lam[p] = ctx->mats[p].lambda;
     }
-    act.st = ctx->cgst.as<CGState>();
+    act.st = st;
     HIP_OR_FAIL(launch_dfmg_action<T>(act, s));
-    DfmgSumArgs<T> sm{ctx->g.n1, ctx->g.n2, ctx->g.n3, n, act.own, act.part, ctx->dfmg_dQ.as<T>(),
-                      ctx->cgst.as<CGState>()};
+    DfmgSumArgs<T> sm{ctx->g.n1, ctx->g.n2, ctx->g.n3, n, act.own, act.part, ctx->dfmg_dQ.as<T>(), st};
     HIP_OR_FAIL(launch_dfmg_sum<T>(sm, s));
+    return COMBO_OK;
+}
+
+template <typename T>
+int stag_tangent_x(combo_ctx* ctx, hipStream_t s) {
+    XArgs<T> xi = xargs<T>(ctx);
+    xi.in = ctx->specB.as<cpx<T>>();
+    xi.real_out_t = ctx->dfmg_dH.as<T>();
+    xi.scale = 1.0;   // the 1/n of the operator is applied by the z pass
+    xi.skip_done = 1;
+    HIP_OR_FAIL(launch_x<T>(X_INV_REAL, xi, s));
+    const int st = stag_action_sum<T>(ctx, s, ctx->cgst.as<CGState>());
+    if (st) return st;
     XArgs<T> xf = xargs<T>(ctx);
     xf.real_in_t = ctx->dfmg_dQ.as<T>();
     xf.out = ctx->specA.as<cpx<T>>();
@@ -870,8 +878,64 @@ int newton_direction(combo_ctx* ctx) {
 }
 
 // effective tangent column by column (precision T of the linear solves)
+// Effective tangent on the staggered grid (same steps as below): for E = e_kL, the
+// right-hand side -Gamma0[A : E] from the DFMG action of the uniform field E, the CG
+// solve, then <A : (E + dF)> as the mean of the DFMG action of E + dF.
+template <typename T>
+int effective_tangent_stag(combo_ctx* ctx, double mu0, double kappa0, double tol_cg, double Abar[81],
+                           int& cg_total) {
+    const long long n = ctx->g.n;
+    hipStream_t s = ctx->stream;
+    T* dH = ctx->dfmg_dH.as<T>();
+    cg_total = 0;
+    for (int kL = 0; kL < 9; ++kL) {
+        double E[9];
+        for (int c = 0; c < 9; ++c) E[c] = (c == kL) ? 1.0 : 0.0;
+        HIP_OR_FAIL(launch_stag_uniform<T>(dH, n, E, 0, s));
+        int st = stag_action_sum<T>(ctx, s, nullptr);
+        if (st) return st;
+        XArgs<T> xf = xargs<T>(ctx);
+        xf.real_in_t = ctx->dfmg_dQ.as<T>();
+        xf.out = ctx->specA.as<cpx<T>>();
+        HIP_OR_FAIL(launch_x<T>(X_FWD_REAL, xf, s));
+        HIP_OR_FAIL(launch_y<T>(-1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, false), s));
+        ZArgs<T, T> za = zargs<T, T>(ctx, mu0, kappa0);
+        za.in = ctx->specB.as<cpx<T>>();
+        int nb = 0;
+        HIP_OR_FAIL(launch_z<T, T>(Z_RHS, za, s, &nb));
+        HIP_OR_FAIL(launch_antiherm<T>(uargs<T>(ctx, mu0, kappa0), s));
+        HIP_OR_FAIL(launch_finalize(FIN_RHS, finargs(ctx, ctx->part1.as<double>(), ctx->part2.as<double>(), nb,
+                                                     tol_cg * tol_cg, ctx->opt.max_cg), s));
+        int it = 0;
+        st = cg_solve<T>(ctx, mu0, kappa0, it);
+        if (st == kNegCurv) return COMBO_E_NUMERIC;   // message set by cg_solve
+        if (st) return st;
+        cg_total += it;
+        ZArgs<T, T> zi = zargs<T, T>(ctx, mu0, kappa0);
+        zi.out = ctx->specA.as<cpx<T>>();
+        HIP_OR_FAIL(launch_z<T, T>(Z_INV_PLAIN, zi, s));
+        HIP_OR_FAIL(launch_y<T>(+1, yargs<T>(ctx, ctx->specA.p, ctx->specB.p, false), s));
+        XArgs<T> xi = xargs<T>(ctx);   // scale 1/n: the inverse transforms are unnormalised
+        xi.in = ctx->specB.as<cpx<T>>();
+        xi.real_out_t = dH;
+        HIP_OR_FAIL(launch_x<T>(X_INV_REAL, xi, s));
+        HIP_OR_FAIL(launch_stag_uniform<T>(dH, n, E, 1, s));
+        st = stag_action_sum<T>(ctx, s, nullptr);
+        if (st) return st;
+        HIP_OR_FAIL(launch_stag_field_sums<T>(ctx->dfmg_dQ.as<T>(), n, ctx->part1.as<double>(), s));
+        double* col = ctx->sums.as<double>() + kSumsLen;
+        HIP_OR_FAIL(launch_reduce_columns(ctx->part1.as<double>(), stag_sum_blocks(n), 9, col, s));
+        double h[9];
+        HIP_OR_FAIL(hipMemcpyAsync(h, col, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_OR_FAIL(hipStreamSynchronize(s));
+        for (int r = 0; r < 9; ++r) Abar[9 * r + kL] = h[r] / (double)n;
+    }
+    return COMBO_OK;
+}
+
 template <typename T>
 int effective_tangent(combo_ctx* ctx, double mu0, double kappa0, double tol_cg, double Abar[81], int& cg_total) {
+    if (staggered(ctx)) return effective_tangent_stag<T>(ctx, mu0, kappa0, tol_cg, Abar, cg_total);
     cg_total = 0;
     for (int kL = 0; kL < 9; ++kL) {
         XArgs<T> xa = xargs<T>(ctx);
@@ -2536,8 +2600,6 @@ int combo_solve(combo_ctx* ctx, const double Fbar[9], const double* F_init, doub
     }
     if (staggered(ctx) && ctx->opt.law != COMBO_LAW_NEO_HOOKE)
         return set_err(ctx, COMBO_E_INVAL, "the staggered grid takes the finite-strain law");
-    if (staggered(ctx) && ctx->opt.want_tangent && Abar)
-        return set_err(ctx, COMBO_E_INVAL, "no effective tangent on the staggered grid");
     HIP_OR_FAIL(hipSetDevice(ctx->device));
     const long long n = ctx->g.n;
     const size_t f9 = sizeof(double) * 9 * (size_t)n;
