@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define COMBO_ABI_VERSION 6
+#define COMBO_ABI_VERSION 7
 
 typedef struct combo_ctx combo_ctx;
 typedef struct combo_batch combo_batch;
@@ -327,6 +327,11 @@ enum combo_kernel {
     COMBO_K_COUNT = 12
 };
 int combo_profile_enable(combo_ctx* ctx, int enable);
+/* Which classes profiling times: bit (1u << kernel) set = timed (default: all).
+ * Each timed launch adds an event pair to the stream, a few microseconds per
+ * launch; timing only the class of interest keeps a measured solve close to an
+ * untimed one.  Takes effect for launches made after the call. */
+int combo_profile_select(combo_ctx* ctx, unsigned mask);
 /* Accumulated milliseconds and number of timed launches of one kernel class.
  * CG iterations run in chunks (8, or graph_chunk) between host checks; the
  * launches of a chunk's iterations after the one that finished the CG find it

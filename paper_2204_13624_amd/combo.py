@@ -119,6 +119,7 @@ _SIGS = {
     "combo_apply_green": (_I, [_P, _I, _I, _P, _P, _I]),
     "combo_apply_operator": (_I, [_P, _I, _P, _P, _I]),
     "combo_profile_enable": (_I, [_P, _I]),
+    "combo_profile_select": (_I, [_P, ctypes.c_uint]),
     "combo_profile_read": (_I, [_P, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
     "combo_profile_read_idle": (_I, [_P, _I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]),
     "combo_autotune": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -395,6 +396,12 @@ def combo_apply_operator(ctx, precision, p, q):
 
 def combo_profile_enable(ctx, enable=True):
     _check(ctx, load_library().combo_profile_enable(ctx, 1 if enable else 0))
+
+
+def combo_profile_select(ctx, kernels=None):
+    """Time only these kernel classes while profiling (None: all)."""
+    mask = 0xFFFFFFFF if kernels is None else sum(1 << int(k) for k in kernels)
+    _check(ctx, load_library().combo_profile_select(ctx, mask))
 
 
 def combo_profile_read(ctx, kernel):

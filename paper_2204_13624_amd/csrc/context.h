@@ -115,6 +115,7 @@ struct combo_ctx {
 
     // per-kernel event timing
     bool profile = false;
+    unsigned prof_mask = ~0u;   // kernel classes timed while profiling (bit k: class k)
     // iter: position of the launch's CG iteration in its chunk (-1 outside a chunk);
     // launches of iterations after the one that finished the CG return at once and
     // are counted apart (prof_idle_*), so the averages cover launches that did work

@@ -171,7 +171,7 @@ hipEvent_t prof_event(combo_ctx* ctx) {
 }
 
 int prof_begin(combo_ctx* ctx, int kernel) {
-    if (!ctx->profile) return -1;
+    if (!ctx->profile || !((ctx->prof_mask >> kernel) & 1u)) return -1;
     combo_ctx::ProfRec r{kernel, prof_event(ctx), prof_event(ctx), ctx->prof_iter};
     if (!r.start || !r.stop) return -1;
     (void)hipEventRecord(r.start, ctx->stream);
@@ -2912,6 +2912,14 @@ int combo_profile_enable(combo_ctx* ctx, int enable) {
         ctx->prof_idle_ms[k] = 0.0;
         ctx->prof_idle_n[k] = 0;
     }
+    return COMBO_OK;
+}
+
+int combo_profile_select(combo_ctx* ctx, unsigned mask) {
+    if (!ctx) return COMBO_E_INVAL;
+    HIP_OR_FAIL(hipStreamSynchronize(ctx->stream));
+    prof_harvest(ctx);
+    ctx->prof_mask = mask;
     return COMBO_OK;
 }
 

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_function():
 
 
 def test_host_only_calls():
-    assert combo.combo_abi_version() == 6
+    assert combo.combo_abi_version() == 7
     assert combo.combo_strerror(combo.COMBO_E_SIZE) == "unsupported grid size"
     o = combo.combo_default_options()
     assert o.tol_newton == 1e-8 and o.max_laminate == 50 and o.warm_start_laminate == 1

@@ -304,3 +304,23 @@ def test_error_paths(ctx):
     with pytest.raises(combo.ComboError) as e:
         combo.combo_solve(ctx, FBAR)
     assert e.value.status == combo.COMBO_E_NOCONV
+
+
+def test_profile_select_times_only_the_chosen_classes(ctx):
+    ms = synth.single_sphere((16, 16, 16), radius=0.3)
+    setup(ctx, ms, precision=combo.COMBO_MIXED, tol_newton=1e-8, tol_cg=1e-6)
+    r0 = combo.combo_solve(ctx, FBAR)
+    combo.combo_profile_select(ctx, [0])   # the x pass of the CG operator only
+    combo.combo_profile_enable(ctx, True)
+    r1 = combo.combo_solve(ctx, FBAR)
+    prof = combo.combo_profile_all(ctx)
+    combo.combo_profile_enable(ctx, False)
+    assert prof["xpass_cg"][1] > 0 and prof["xpass_cg"][0] > 0
+    assert all(v[1] == 0 for k, v in prof.items() if k != "xpass_cg")
+    assert np.array_equal(r0["Pbar"], r1["Pbar"])
+    combo.combo_profile_select(ctx, None)
+    combo.combo_profile_enable(ctx, True)
+    combo.combo_solve(ctx, FBAR)
+    prof = combo.combo_profile_all(ctx)
+    combo.combo_profile_enable(ctx, False)
+    assert prof["ypass_fwd"][1] > 0 and prof["cg_update"][1] > 0 and prof["material"][1] > 0
