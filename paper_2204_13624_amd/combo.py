@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcombo.so")
+# COMBO_LIBRARY names another build of the library (e.g. a variant under test); default: the in-tree build
+LIB_PATH = os.environ.get("COMBO_LIBRARY") or os.path.join(HERE, "libcombo.so")
 
 COMBO_OK = 0
 COMBO_E_INVAL = -1
