@@ -28,7 +28,9 @@ import make_goldens as mg  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-FIXTURES = sorted(glob.glob(os.path.join(HERE, "golden", "oracle_*.json")))
+# single-solve fixtures (the fibre load walk, oracle_fibres_*.json, has a test of its own)
+FIXTURES = sorted(f for f in glob.glob(os.path.join(HERE, "golden", "oracle_*.json"))
+                  if not os.path.basename(f).startswith("oracle_fibres_"))
 BATCH_FIXTURES = [f for f in FIXTURES if os.path.basename(f).startswith("oracle_batch_")]
 BAR = {combo.COMBO_FP64: 1e-8, combo.COMBO_MIXED: 1e-6}
 
