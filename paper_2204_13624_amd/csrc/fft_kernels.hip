@@ -112,6 +112,46 @@ __device__ __forceinline__ void tangent_apply(const TangentState<T>& ts, long lo
         for (int J = 0; J < 3; ++J) tau[3 * i + J] = mu * p[3 * i + J] + lam * tr * fi[3 * J + i] + m * C[3 * J + i];
 }
 
+// the same with the pure-voxel state (slot, F^{-1}, mu - lambda ln J) already loaded
+template <typename T>
+__device__ __forceinline__ void tangent_apply_loaded(const TangentState<T>& ts, int slot, const T* fi, T m,
+                                                     const T* p, T* tau) {
+    if (slot >= 0) {
+        const T* A = ts.Acomp + (long long)slot * 45;
+        T a[45];
+#pragma unroll
+        for (int i = 0; i < 45; ++i) a[i] = A[i];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            T acc = T(0);
+#pragma unroll
+            for (int s = 0; s < 9; ++s) {
+                const int lo = r < s ? r : s, hi = r < s ? s : r;
+                acc += a[lo * 9 - (lo * (lo - 1)) / 2 + (hi - lo)] * p[s];
+            }
+            tau[r] = acc;
+        }
+        return;
+    }
+    const int ph = (slot == -1) ? 0 : 1;
+    const T mu = ts.mu[ph], lam = ts.lam[ph];
+    T B[9];
+#pragma unroll
+    for (int J = 0; J < 3; ++J)
+#pragma unroll
+        for (int L = 0; L < 3; ++L) B[3 * J + L] = fi[3 * J + 0] * p[0 + L] + fi[3 * J + 1] * p[3 + L] + fi[3 * J + 2] * p[6 + L];
+    const T tr = B[0] + B[4] + B[8];
+    T C[9];
+#pragma unroll
+    for (int J = 0; J < 3; ++J)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) C[3 * J + i] = B[3 * J + 0] * fi[0 + i] + B[3 * J + 1] * fi[3 + i] + B[3 * J + 2] * fi[6 + i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) tau[3 * i + J] = mu * p[3 * i + J] + lam * tr * fi[3 * J + i] + m * C[3 * J + i];
+}
+
 // ------------------------------------------------------------------------------
 // x pass
 // ------------------------------------------------------------------------------
@@ -621,28 +661,71 @@ __device__ __forceinline__ void k_xlds_body(const XArgs<T>& a, int tile_, int nt
         __syncthreads();
     }
 
-    // ---- tangent action per voxel (X_AVG: averaged instead of stored)
+    // ---- tangent action per voxel (X_AVG: averaged instead of stored).  Moulinec-Suquet:
+    // the state of all of a thread's voxels is requested first (slot, F^{-1} and
+    // mu - lambda ln J, read for every voxel: in bounds, unused for composites), so
+    // that one memory round trip serves them all instead of two dependent ones per voxel.
     double acc[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) acc[c] = 0.0;
-    for (int v = (MODE == X_FWD_REAL) ? R * L : tid; v < R * L; v += blockDim.x) {
-        const int rr = v / L, xx = v - rr * L;
-        const long long rw = row0 + rr;
-        if (rw >= nrows) continue;
-        T p[9], tau[9];
+    if constexpr ((MODE == X_CG || MODE == X_AVG) && DISC == 0) {
+        constexpr int NTH = S::NTH;
+        constexpr int VPT = (R * L + NTH - 1) / NTH;   // voxels per thread
+        int sl[VPT];
+        T fis[VPT][9], mss[VPT];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) p[c] = fld[(c * R + rr) * L + xx];
-        if (MODE == X_AVG) {
+        for (int q = 0; q < VPT; ++q) {
+            const int v = tid + q * NTH;
+            const int rr = v / L, xx = v - rr * L;
+            const bool ok = v < R * L && row0 + rr < nrows;
+            const long long sidx = ok ? (row0 + rr) * L + xx : 0;
+            sl[q] = a.ts.slot[sidx];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) p[c] = T(double(p[c]) * a.scale + a.E[c]);
+            for (int c = 0; c < 9; ++c) fis[q][c] = a.ts.Sinv[c * a.ts.n + sidx];
+            mss[q] = a.ts.sm[sidx];
         }
-        tangent_apply<T>(a.ts, rw * L + xx, p, tau);
-        if (MODE == X_AVG) {
 #pragma unroll
-            for (int c = 0; c < 9; ++c) acc[c] += double(tau[c]);
-        } else {
+        for (int q = 0; q < VPT; ++q) {
+            const int v = tid + q * NTH;
+            const int rr = v / L, xx = v - rr * L;
+            if (v >= R * L || row0 + rr >= nrows) continue;
+            T p[9], tau[9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) fld[(c * R + rr) * L + xx] = tau[c];
+            for (int c = 0; c < 9; ++c) p[c] = fld[(c * R + rr) * L + xx];
+            if (MODE == X_AVG) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) p[c] = T(double(p[c]) * a.scale + a.E[c]);
+            }
+            tangent_apply_loaded<T>(a.ts, sl[q], fis[q], mss[q], p, tau);
+            if (MODE == X_AVG) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) acc[c] += double(tau[c]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) fld[(c * R + rr) * L + xx] = tau[c];
+            }
+        }
+    } else {
+        // rotated scheme: voxel by voxel (its x pass has fewer registers to spare)
+        for (int v = (MODE == X_FWD_REAL) ? R * L : tid; v < R * L; v += blockDim.x) {
+            const int rr = v / L, xx = v - rr * L;
+            const long long rw = row0 + rr;
+            if (rw >= nrows) continue;
+            T p[9], tau[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) p[c] = fld[(c * R + rr) * L + xx];
+            if (MODE == X_AVG) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) p[c] = T(double(p[c]) * a.scale + a.E[c]);
+            }
+            tangent_apply<T>(a.ts, rw * L + xx, p, tau);
+            if (MODE == X_AVG) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) acc[c] += double(tau[c]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) fld[(c * R + rr) * L + xx] = tau[c];
+            }
         }
     }
     if (MODE == X_AVG) {
