@@ -93,7 +93,7 @@ def host_cpu():
     return model, nproc
 
 
-def cpu_baseline(ms, lc, sub=128, iters=3):
+def cpu_baseline(ms, lc, sub=128, iters=8):
     """Time the FP64 oracle's CG iterations on a sub-block of the same workload."""
     from oracle import solver as osol
     from oracle import spectral as ospec
