@@ -58,7 +58,9 @@ def compatible(n, l, seed, amp=0.05):
 
 @pytest.mark.parametrize("n,l", [((8, 6, 4), (1.0, 0.9, 0.7)), ((9, 8, 6), (1.2, 1.0, 0.8)),
                                  ((16, 12, 9), (1.0, 1.0, 1.0)), ((32, 8, 9), (2.0, 0.5, 0.6)),
-                                 ((1, 4, 6), (0.3, 1.0, 1.0)), ((128, 6, 4), (1.0, 0.2, 0.1))])
+                                 ((1, 4, 6), (0.3, 1.0, 1.0)), ((128, 6, 4), (1.0, 0.2, 0.1)),
+                                 ((4, 128, 3), (0.2, 1.0, 0.3)), ((3, 4, 128), (0.2, 0.3, 1.0)),
+                                 ((2, 96, 48), (0.1, 1.0, 0.5)), ((2, 64, 256), (0.1, 0.3, 1.0))])
 @pytest.mark.parametrize("which", [combo.COMBO_GREEN_GAMMA0, combo.COMBO_GREEN_G])
 def test_staggered_green_operators_match_oracle(ctx, n, l, which):
     rng = np.random.default_rng(3)
@@ -95,7 +97,9 @@ def test_dfmg_law_matches_oracle(ctx, n, seed, amp):
     assert rel(P, Po.reshape(P.shape)) <= 1e-11
 
 
-@pytest.mark.parametrize("n", [(8, 6, 4), (12, 9, 8), (32, 16, 8)])
+# rows of 48, 96, 128 and 256 run the two-stage x passes on real fields (8x6, 8x12, 8x16, 16x16)
+@pytest.mark.parametrize("n", [(8, 6, 4), (12, 9, 8), (32, 16, 8), (48, 6, 4), (96, 4, 3), (128, 4, 3), (256, 3, 2),
+                               (4, 128, 3), (3, 4, 128), (2, 64, 48)])
 @pytest.mark.parametrize("precision,tol", [(combo.COMBO_FP64, 1e-11), (combo.COMBO_MIXED, 3e-6)])
 def test_staggered_cg_operator_matches_oracle(ctx, n, precision, tol):
     ms = synth.random_composite_field(n, 5, frac_composite=0.3)
