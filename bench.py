@@ -6,11 +6,19 @@ rescaled to c = 0.30), composite boxels from 4^3 subsamples, Neo-Hooke matrix
 10 increments, Newton tolerance eta <= 1e-6.  One step = one full solve.
 
 value = voxel-CG-iterations per second of the mixed-precision solve (FP32
-linear solves, FP64 law and residual); the FP64 solve's time-to-solution is
-reported beside it.  Per-kernel durations come from HIP events the library
-records on its stream around every launch during the timed steps.
+linear solves, FP64 law and residual) over the K timed solves (default 3, after
+one warm-up); time-to-solution is their median, and the FP64 solve's is reported
+beside it.  Per-kernel durations come from HIP event pairs the library records
+on its stream: around the x pass (the roofline kernel) in the timed solves, and
+around every kernel class in the last warm-up solve.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64]
+Further sections of the same JSON line (each can be switched off): the rotated
+scheme and the staggered grid on the same RVE, the small-strain law, composite
+boxels from the 1024^3 image, the 64-RVE batch, the fibre workload's load walk
+with its effective tangent, and the CPU oracle's CG throughput.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64] [--no-willot]
+       [--no-staggered] [--no-small-strain] [--no-image] [--no-batch] [--no-fibres]
 """
 import argparse
 import json
