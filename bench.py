@@ -15,7 +15,7 @@ around every kernel class in the last warm-up solve.
 Further sections of the same JSON line (each can be switched off): the rotated
 scheme and the staggered grid on the same RVE, the small-strain law, composite
 boxels from the 1024^3 image, the 64-RVE batch, the fibre workload's load walk
-with its effective tangent, and the CPU oracle's CG throughput.
+with its effective tangent and stability, and the CPU oracle's CG throughput.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64] [--no-willot]
        [--no-staggered] [--no-small-strain] [--no-image] [--no-batch] [--no-fibres]
@@ -252,6 +252,47 @@ def batch_bench(combo, synth, steps):
             "one_by_one_time_s": seq, "one_by_one_value": seq_it / seq, "speedup_vs_one_by_one": seq / wall}
 
 
+def lowest_eigenvalue(combo, ctx, shape, mu0, kappa0, steps, seed=11):
+    """Smallest Ritz value of K = Gamma0[A:.] (the tangent state of the last
+    combo_eval_law) on compatible zero-mean fields, in the C0 inner product
+    mu0 x:y + kappa0 tr x tr y, after 2/3 of `steps` and after `steps` Lanczos steps.
+    K is self-adjoint in that product on those fields; each vector is projected with
+    G so that rounding does not leak it outside them."""
+    import torch
+    from scipy.linalg import eigvalsh_tridiagonal
+    dev = torch.device("cuda:0")
+
+    def ip(x, y):
+        return float(mu0 * torch.sum(x * y) + kappa0 * torch.sum((x[0] + x[4] + x[8]) * (y[0] + y[4] + y[8])))
+
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    r = torch.randn(shape, dtype=torch.float64, device=dev, generator=g)
+    v = torch.empty_like(r)
+    combo.combo_apply_green(ctx, combo.COMBO_GREEN_G, combo.COMBO_FP64, r, v)
+    del r
+    v /= np.sqrt(ip(v, v))
+    v_old = torch.zeros_like(v)
+    w = torch.empty_like(v)
+    wp = torch.empty_like(v)
+    alpha, beta, ritz = [], [], []
+    b = 0.0
+    for j in range(steps):
+        combo.combo_apply_operator(ctx, combo.COMBO_FP64, v, w)
+        w -= b * v_old
+        a = ip(w, v)
+        w -= a * v
+        combo.combo_apply_green(ctx, combo.COMBO_GREEN_G, combo.COMBO_FP64, w, wp)
+        b = np.sqrt(ip(wp, wp))
+        alpha.append(a)
+        beta.append(b)
+        v_old, v = v, wp / b
+        if j + 1 in (2 * steps // 3, steps):
+            ritz.append(float(eigvalsh_tridiagonal(np.array(alpha), np.array(beta[:-1]),
+                                                   select="i", select_range=(0, 0))[0]))
+    return ritz
+
+
 def fibres_bench(combo, synth, seconds):
     """The fibre workload (256^3, 60 random straight fibres, near-incompressible matrix,
     fibre contrast 1000, simple shear 0.3 e1 (x) e2 in 30 increments), mixed precision
@@ -260,7 +301,8 @@ def fibres_bench(combo, synth, seconds):
     internal cutbacks); a converged step doubles dt up to 1/30, a failed one halves it.
     The walk ends when dt drops below 1/(32 x 30) (the solver's own cutback limit), at
     the end of the path, or after `seconds`.  The effective tangent Abar is computed at
-    the last converged load."""
+    the last converged load, and so is the lowest eigenvalue of the Newton operator
+    there (how close the branch is to losing stability)."""
     import torch
     t = time.time()
     ms, lc = synth.workload_fibres_256()
@@ -339,6 +381,19 @@ def fibres_bench(combo, synth, seconds):
         res["tangent_cg_iters"] = r["stats"]["cg_iters_tangent"]
         res["Pbar_last"] = [[float("%.6g" % v) for v in row] for row in Pbar_last]
         res["Abar_last"] = [[float("%.6g" % v) for v in row] for row in r["Abar"]]
+        (mu_m, lam_m), (mu_p, lam_p) = lc.mats
+        mu0 = float(np.sqrt(mu_m * mu_p))
+        kappa0 = float(np.sqrt((lam_m + mu_m) * (lam_p + mu_p)))
+        o.precision = combo.COMBO_FP64
+        combo.combo_set_options(ctx, o)
+        t1 = time.perf_counter()
+        combo.combo_eval_law(ctx, F)
+        ritz = lowest_eigenvalue(combo, ctx, tuple(F.shape), mu0, kappa0, 1000)
+        res["stability"] = {
+            "what": "lowest eigenvalue of the Newton operator Gamma0[A:.] on compatible fields (C0 product, "
+                    "FP64, Lanczos with G re-projection) at the last converged load; unloaded it is mu_m/mu0",
+            "unloaded": mu_m / mu0, "last_converged": ritz[1], "after_2_3_of_steps": ritz[0],
+            "ratio": ritz[1] / (mu_m / mu0), "lanczos_steps": 1000, "seconds": time.perf_counter() - t1}
     combo.combo_destroy(ctx)
     log("fibres: %s at shear %.5f after %d attempts, %.1f s" % (stop, 0.3 * tt, tot["attempts"], walk_s))
     return res
