@@ -12,13 +12,14 @@ beside it.  Per-kernel durations come from HIP event pairs the library records
 on its stream: around the x pass (the roofline kernel) in the timed solves, and
 around every kernel class in the last warm-up solve.
 
-Further sections of the same JSON line (each can be switched off): the rotated
-scheme and the staggered grid on the same RVE, the small-strain law, composite
+Further sections of the same JSON line (each can be switched off): the same RVE
+twice in one batch (the batched form against the single mixed and FP64 solves), the
+rotated scheme and the staggered grid on the same RVE, the small-strain law, composite
 boxels from the 1024^3 image, the 64-RVE batch, the fibre workload's load walk
 with its effective tangent and stability, and the CPU oracle's CG throughput.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64] [--no-willot]
-       [--no-staggered] [--no-small-strain] [--no-image] [--no-batch] [--no-fibres]
+       [--no-staggered] [--no-small-strain] [--no-image] [--no-batch] [--no-batched-256] [--no-fibres]
 """
 import argparse
 import json
@@ -252,6 +253,44 @@ def batch_bench(combo, synth, steps):
             "one_by_one_time_s": seq, "one_by_one_value": seq_it / seq, "speedup_vs_one_by_one": seq / wall}
 
 
+def batched_256(combo, ms, lc, o, out, members=2):
+    """The 256^3 workload in the batched form: `members` copies of the RVE under the
+    same load in one batch (mixed precision, the main solve's options), one warm-up and
+    one timed batch solve.  The per-RVE time is compared with the single mixed and the
+    FP64 solves of the same workload; Pbar of every member against the FP64 solve."""
+    import torch
+    b = combo.combo_batch_create(0)
+    try:
+        combo.combo_batch_set_options(b, o)
+        for _ in range(members):
+            combo.combo_batch_add(b, ms.n, ms.l, lc.mats, ms.phase, ms.c, ms.N)
+        Fb = np.stack([lc.Fbar] * members)
+        K = [lc.n_increments] * members
+        combo.combo_batch_solve(b, Fb, n_increments=K)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = combo.combo_batch_solve(b, Fb, n_increments=K)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        combo.combo_batch_destroy(b)
+    cg = [st["cg_iters_total"] for st in r["stats"]]
+    per = wall / members
+    res = {"members": members, "wall_s": wall, "per_rve_s": per, "cg_iters": cg,
+           "value": ms.nvox * sum(cg) / wall, "unit": "voxel-CG-iters/s"}
+    tts_ = out.get("time_to_solution_s", {})
+    if "mixed" in tts_:
+        res["single_mixed_over_per_rve"] = tts_["mixed"] / per
+    if "fp64" in tts_:
+        res["fp64_over_per_rve"] = tts_["fp64"] / per
+    if out.get("_Pbar_fp64") is not None:
+        P64 = out["_Pbar_fp64"]
+        res["pbar_rel_diff_vs_fp64"] = float(max(np.abs(np.asarray(r["Pbar"][i]) - P64).max()
+                                                 for i in range(members)) / np.abs(P64).max())
+    log("batched 256^3: %d members %.2f s (%.2f s per RVE)" % (members, wall, per))
+    return res
+
+
 def lowest_eigenvalue(combo, ctx, shape, mu0, kappa0, steps, seed=11):
     """Smallest Ritz value of K = Gamma0[A:.] (the tangent state of the last
     combo_eval_law) on compatible zero-mean fields, in the C0 inner product
@@ -411,6 +450,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-batched-256", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-small-strain", action="store_true")
     ap.add_argument("--no-image", action="store_true")
@@ -589,7 +629,10 @@ def main():
         out["fp64_voxel_cg_iters_per_s"] = n * r64["stats"]["cg_iters_total"] / out["time_to_solution_s"]["fp64"]
         out["pbar_rel_diff_mixed_vs_fp64"] = float(np.abs(Pbar_mixed - r64["Pbar"]).max() /
                                                    np.abs(r64["Pbar"]).max())
+        out["_Pbar_fp64"] = r64["Pbar"]
         log("fp64: %.2f s, cg %d" % (out["time_to_solution_s"]["fp64"], r64["stats"]["cg_iters_total"]))
+    if not args.no_batched_256:
+        out["batched_256"] = batched_256(combo, ms, lc, options(combo.COMBO_MIXED), out)
     if not args.no_willot:
         # the same workload under Willot's rotated scheme
         combo.combo_set_discretization(ctx, combo.COMBO_DISC_WILLOT)
@@ -691,6 +734,7 @@ def main():
         log("cpu baseline in %.1f s" % (time.time() - t))
     else:
         out["cpu_baseline"] = None
+    out.pop("_Pbar_fp64", None)
     print(json.dumps(out), flush=True)
 
 
