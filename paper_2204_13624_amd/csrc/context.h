@@ -146,5 +146,6 @@ struct combo_batch {
     size_t hscal_bytes = 0;
     static constexpr size_t kScalStride = 1024;
     static constexpr size_t kScalSums = 128;
+    static_assert(sizeof(combo::CGState) <= kScalSums, "a member's CG state overlaps its sums");
 };
 
