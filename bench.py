@@ -165,11 +165,11 @@ def image_bench(combo, synth, ms, steps):
     ms1, n1 = prof["boxel_count"]
     ms2, n2 = prof["boxel_normals"]
     avg1, avg2 = ms1 / n1, ms2 / n2
-    # pass 1: the image once, phase (1 B) and c (8 B) of every boxel
-    b1 = img_bytes + nb * 9
-    # pass 2: phase (1 B) in and N (24 B) out for every boxel; per composite its 4^3 fine voxels once,
-    # the list entry (written, read twice) and its 13 FP64 moments (written and read)
-    b2 = nb * 25 + ncomp * (64 + 12 + 2 * 104)
+    # pass 1: the image once; phase (1 B), c (8 B) and the packed fine values (one 8-B word) of every boxel
+    b1 = img_bytes + nb * (9 + 8)
+    # pass 2: phase (1 B) in and N (24 B) out for every boxel; per composite the seven packed words of
+    # its boxel and the six face neighbours (56 B) and the list entry (written and read once)
+    b2 = nb * 25 + ncomp * (56 + 8)
     res = {"workload": "1024^3 image of spheres_256 -> 256^3 boxels (4^3 fine voxels each), Laplacian normals",
            "composites": ncomp, "phase_and_c_equal_generator": exact,
            "ms_per_call": el * 1e3,

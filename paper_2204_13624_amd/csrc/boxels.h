@@ -37,7 +37,8 @@ int boxel_blocks(long long nb);
 hipError_t launch_boxel_list(const BoxelArgs& a, int* blockcnt, int* list, hipStream_t s);
 // Exclusive prefix of nblk ints in place (one workgroup); the total goes to total[0].
 hipError_t launch_block_scan(int* cnt, int nblk, int* total, hipStream_t s);
-// Pass 2b: moments (16 lanes per list entry, mom: 13 doubles per entry) and normals of the ncomp entries.
+// Pass 2b: moments and normals of the ncomp entries.  Packed words: one lane per entry, mom unused;
+// byte path: 16 lanes per entry through mom (13 doubles per entry).
 hipError_t launch_boxel_normals(const BoxelArgs& a, const int* list, double* mom, int ncomp, hipStream_t s);
 
 }  // namespace combo

@@ -190,8 +190,9 @@ __device__ __forceinline__ X team_sum(X v) {
 //   k_boxel_blockcount: per block of kCompact boxels, the number of composites (and N = 0 for pure boxels);
 //   k_boxel_scan:       one workgroup, exclusive prefix of the block counts and the total;
 //   k_boxel_compact:    the composites of each block, in ascending order, into list[];
-//   k_boxel_moments:    16-lane teams per list entry: interface weights and moments -> mom[];
-//   k_boxel_eigen:      one thread per list entry: the normal from its moments.
+//   k_boxel_moments:    byte path: 16-lane teams per list entry, interface weights and moments -> mom[];
+//   k_boxel_eigen:      byte path: one thread per list entry, the normal from its moments;
+//   k_boxel_normals_packed: packed words: one lane per list entry, moments and normal together.
 constexpr int kCompact = 1024;   // boxels per compaction block (256 threads x 4)
 constexpr int kMom = 13;         // sw, sw xi (3), sw xi xi^T (6), sum_{chi=1} xi (3)
 
@@ -342,85 +343,9 @@ __global__ void __launch_bounds__(256) k_boxel_moments(BoxelArgs a, const int* l
     }
 }
 
-// moments from the packed boxel words (s1 = 4, s2 s3 <= 16): each lane of a team reads the
-// composite's word and those of its six face neighbours (periodic), then takes kPer voxels
-__device__ __forceinline__ int bitv(uint64_t w, int i) { return (int)((w >> i) & 1ull); }
-
-__global__ void __launch_bounds__(256, 3) k_boxel_moments_packed(BoxelArgs a, const int* list, double* mom,
-                                                              long long nteams) {
-    const int tl = threadIdx.x % kTeam;
-    const long long team = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kTeam;
-    const int ncomp = a.counter[0];
-    const int s2 = a.s2, s3 = a.s3;
-    const int V32 = 4 * s2 * s3;
-    const int n1 = a.n1, n2 = a.n2, n3 = a.n3;
-    for (long long idx = team; idx < ncomp; idx += nteams) {   // uniform over the team
-        const long long b = list[idx];
-        const int i = (int)(b % n1);
-        const long long tt = b / n1;
-        const int j = (int)(tt % n2), k = (int)(tt / n2);
-        const long long rowb = (long long)k * n2 + j;
-        const uint64_t w0 = a.packed[b];
-        const uint64_t wxm = a.packed[rowb * n1 + (i == 0 ? n1 - 1 : i - 1)];
-        const uint64_t wxp = a.packed[rowb * n1 + (i == n1 - 1 ? 0 : i + 1)];
-        const uint64_t wym = a.packed[((long long)k * n2 + (j == 0 ? n2 - 1 : j - 1)) * n1 + i];
-        const uint64_t wyp = a.packed[((long long)k * n2 + (j == n2 - 1 ? 0 : j + 1)) * n1 + i];
-        const uint64_t wzm = a.packed[((long long)(k == 0 ? n3 - 1 : k - 1) * n2 + j) * n1 + i];
-        const uint64_t wzp = a.packed[((long long)(k == n3 - 1 ? 0 : k + 1) * n2 + j) * n1 + i];
-        double acc[kMom];
-#pragma unroll
-        for (int q = 0; q < kMom; ++q) acc[q] = 0.0;
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int t = tl + u * kTeam;
-            if (t >= V32) continue;
-            const int x = t & 3, r = t >> 2;
-            const int z = r / s2, y = r - z * s2;
-            const int c0 = bitv(w0, t);
-            const int xm = x > 0 ? bitv(w0, t - 1) : bitv(wxm, t + 3);
-            const int xp = x < 3 ? bitv(w0, t + 1) : bitv(wxp, t - 3);
-            const int ym = y > 0 ? bitv(w0, t - 4) : bitv(wym, t + 4 * (s2 - 1));
-            const int yp = y < s2 - 1 ? bitv(w0, t + 4) : bitv(wyp, t - 4 * (s2 - 1));
-            const int zm = z > 0 ? bitv(w0, t - 4 * s2) : bitv(wzm, t + 4 * s2 * (s3 - 1));
-            const int zp = z < s3 - 1 ? bitv(w0, t + 4 * s2) : bitv(wzp, t - 4 * s2 * (s3 - 1));
-            const int a1 = abs(xm + xp - 2 * c0), a2 = abs(ym + yp - 2 * c0), a3 = abs(zm + zp - 2 * c0);
-            const int xi0 = 2 * x - 3, xi1 = 2 * y + 1 - s2, xi2 = 2 * z + 1 - s3;
-            if (c0) {
-                acc[10] += xi0;
-                acc[11] += xi1;
-                acc[12] += xi2;
-            }
-            if (a1 | a2 | a3) {
-                const double w = a.r[0] * a1 + a.r[1] * a2 + a.r[2] * a3;
-                const double wx = w * xi0, wy = w * xi1, wz = w * xi2;
-                acc[0] += w;
-                acc[1] += wx;
-                acc[2] += wy;
-                acc[3] += wz;
-                acc[4] += wx * xi0;
-                acc[5] += wx * xi1;
-                acc[6] += wx * xi2;
-                acc[7] += wy * xi1;
-                acc[8] += wy * xi2;
-                acc[9] += wz * xi2;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kMom; ++q) acc[q] = team_sum(acc[q]);
-#pragma unroll
-        for (int q = 0; q < kMom; ++q)
-            if (tl == q) mom[idx * kMom + q] = acc[q];
-    }
-}
-
-__global__ void __launch_bounds__(256) k_boxel_eigen(BoxelArgs a, const int* list, const double* mom) {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.counter[0]) return;
+// the normal of a composite boxel from its 13 moments, written to N at boxel b
+__device__ __forceinline__ void normal_from_moments(const BoxelArgs& a, long long b, const double* mm) {
     const long long nb = (long long)a.n1 * a.n2 * a.n3;
-    const long long b = list[idx];
-    double mm[kMom];
-#pragma unroll
-    for (int q = 0; q < kMom; ++q) mm[q] = mom[idx * kMom + q];
     // sum_{chi=1} xi holds integers (exact in double); N~ ~ -h (.) that sum
     const double nt[3] = {-a.h[0] * mm[10], -a.h[1] * mm[11], -a.h[2] * mm[12]};
     double out[3];
@@ -450,6 +375,100 @@ __global__ void __launch_bounds__(256) k_boxel_eigen(BoxelArgs a, const int* lis
     a.N[b] = out[0];
     a.N[nb + b] = out[1];
     a.N[2 * nb + b] = out[2];
+}
+
+__global__ void __launch_bounds__(256) k_boxel_eigen(BoxelArgs a, const int* list, const double* mom) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.counter[0]) return;
+    double mm[kMom];
+#pragma unroll
+    for (int q = 0; q < kMom; ++q) mm[q] = mom[idx * kMom + q];
+    normal_from_moments(a, list[idx], mm);
+}
+
+// moments and normal from the packed boxel words (s1 = 4, s2 s3 <= 16), one composite per lane.  Fine
+// voxel t = x + 4 (y + s2 z) is bit t of its boxel's word.  The lane reads the composite's word
+// and those of its six face neighbours (periodic) and forms, with shifts and masks, the six
+// words whose bit t is the neighbour of voxel t along -x, +x, -y, +y, -z, +z.  The stencil
+// term of axis m at t is |chi(t - e_m) + chi(t + e_m) - 2 chi(t)|, i.e. the number of the two
+// neighbours that differ from chi(t): bit t of (XM ^ W) plus bit t of (XP ^ W).  Only the
+// voxels where some term is non-zero carry weight, and the lane visits just those bits.
+__device__ __forceinline__ uint64_t shl64(uint64_t w, int k) { return k >= 64 ? 0ull : w << k; }
+__device__ __forceinline__ uint64_t shr64(uint64_t w, int k) { return k >= 64 ? 0ull : w >> k; }
+__device__ __forceinline__ int bitv(uint64_t w, int i) { return (int)((w >> i) & 1ull); }
+
+__global__ void __launch_bounds__(256) k_boxel_normals_packed(BoxelArgs a, const int* list) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.counter[0]) return;
+    const int s2 = a.s2, s3 = a.s3;
+    const int V32 = 4 * s2 * s3;
+    const int n1 = a.n1, n2 = a.n2, n3 = a.n3;
+    const long long b = list[idx];
+    const int i = (int)(b % n1);
+    const long long tt = b / n1;
+    const int j = (int)(tt % n2), k = (int)(tt / n2);
+    const long long rowb = (long long)k * n2 + j;
+    const uint64_t w0 = a.packed[b];
+    const uint64_t wxm = a.packed[rowb * n1 + (i == 0 ? n1 - 1 : i - 1)];
+    const uint64_t wxp = a.packed[rowb * n1 + (i == n1 - 1 ? 0 : i + 1)];
+    const uint64_t wym = a.packed[((long long)k * n2 + (j == 0 ? n2 - 1 : j - 1)) * n1 + i];
+    const uint64_t wyp = a.packed[((long long)k * n2 + (j == n2 - 1 ? 0 : j + 1)) * n1 + i];
+    const uint64_t wzm = a.packed[((long long)(k == 0 ? n3 - 1 : k - 1) * n2 + j) * n1 + i];
+    const uint64_t wzp = a.packed[((long long)(k == n3 - 1 ? 0 : k + 1) * n2 + j) * n1 + i];
+    // masks of the voxels with x = 0, x = 3, y = 0, y = s2 - 1, z = 0, z = s3 - 1
+    const uint64_t vm = V32 >= 64 ? ~0ull : ((1ull << V32) - 1ull);
+    const uint64_t mx0 = 0x1111111111111111ull & vm, mx3 = mx0 << 3;
+    uint64_t my0 = 0;
+    for (int z = 0; z < s3; ++z) my0 |= 0xFull << (4 * s2 * z);
+    const uint64_t myl = my0 << (4 * (s2 - 1));
+    const int pz = 4 * s2;                       // bits per z plane
+    const uint64_t mz0 = pz >= 64 ? ~0ull : ((1ull << pz) - 1ull);
+    const uint64_t mzl = shl64(mz0, pz * (s3 - 1));
+    const uint64_t XM = ((w0 << 1) & ~mx0) | ((wxm >> 3) & mx0);
+    const uint64_t XP = ((w0 >> 1) & ~mx3) | ((wxp << 3) & mx3);
+    const uint64_t YM = ((w0 << 4) & ~my0) | (shr64(wym, 4 * (s2 - 1)) & my0);
+    const uint64_t YP = ((w0 >> 4) & ~myl) | (shl64(wyp, 4 * (s2 - 1)) & myl);
+    const uint64_t ZM = (shl64(w0, pz) & ~mz0) | (shr64(wzm, pz * (s3 - 1)) & mz0);
+    const uint64_t ZP = (shr64(w0, pz) & ~mzl) | (shl64(wzp, pz * (s3 - 1)) & mzl);
+    const uint64_t d1a = XM ^ w0, d1b = XP ^ w0, d2a = YM ^ w0, d2b = YP ^ w0, d3a = ZM ^ w0, d3b = ZP ^ w0;
+    const unsigned inv2 = (65536u + (unsigned)s2 - 1u) / (unsigned)s2;   // r / s2 = (r inv2) >> 16 for r < 16
+    double acc[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) acc[q] = 0.0;
+    for (uint64_t m = (d1a | d1b | d2a | d2b | d3a | d3b) & vm; m; m &= m - 1ull) {
+        const int t = __builtin_ctzll(m);
+        const int x = t & 3, r = t >> 2;
+        const int z = (int)(((unsigned)r * inv2) >> 16), y = r - z * s2;
+        const int a1 = bitv(d1a, t) + bitv(d1b, t), a2 = bitv(d2a, t) + bitv(d2b, t), a3 = bitv(d3a, t) + bitv(d3b, t);
+        const double xi0 = 2 * x - 3, xi1 = 2 * y + 1 - s2, xi2 = 2 * z + 1 - s3;
+        const double w = a.r[0] * a1 + a.r[1] * a2 + a.r[2] * a3;
+        const double wx = w * xi0, wy = w * xi1, wz = w * xi2;
+        acc[0] += w;
+        acc[1] += wx;
+        acc[2] += wy;
+        acc[3] += wz;
+        acc[4] += wx * xi0;
+        acc[5] += wx * xi1;
+        acc[6] += wx * xi2;
+        acc[7] += wy * xi1;
+        acc[8] += wy * xi2;
+        acc[9] += wz * xi2;
+    }
+    // sums of xi over the inclusion voxels (integers): popcounts of the word under the masks of
+    // equal x, equal y and equal z
+    const uint64_t win = w0 & vm;
+    int c0 = 0, c1 = 0, c2 = 0;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) c0 += (2 * x - 3) * __popcll(win & (mx0 << x));
+    for (int y = 0; y < s2; ++y) c1 += (2 * y + 1 - s2) * __popcll(win & (my0 << (4 * y)));
+    for (int z = 0; z < s3; ++z) c2 += (2 * z + 1 - s3) * __popcll(win & shl64(mz0, pz * z));
+    double mm[kMom];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) mm[q] = acc[q];
+    mm[10] = c0;
+    mm[11] = c1;
+    mm[12] = c2;
+    normal_from_moments(a, b, mm);
 }
 
 }  // namespace
@@ -490,12 +509,13 @@ hipError_t launch_block_scan(int* cnt, int nblk, int* total, hipStream_t s) {
 
 hipError_t launch_boxel_normals(const BoxelArgs& a, const int* list, double* mom, int ncomp, hipStream_t s) {
     if (ncomp <= 0) return hipSuccess;
+    if (a.packed) {
+        hipLaunchKernelGGL(k_boxel_normals_packed, dim3((unsigned)((ncomp + 255) / 256)), dim3(256), 0, s, a, list);
+        return hipGetLastError();
+    }
     const long long blocks = std::min<long long>(((long long)ncomp * kTeam + 255) / 256, 65536);
     const long long nteams = blocks * 256 / kTeam;
-    if (a.packed)
-        hipLaunchKernelGGL(k_boxel_moments_packed, dim3((unsigned)blocks), dim3(256), 0, s, a, list, mom, nteams);
-    else
-        hipLaunchKernelGGL(k_boxel_moments, dim3((unsigned)blocks), dim3(256), 0, s, a, list, mom, nteams);
+    hipLaunchKernelGGL(k_boxel_moments, dim3((unsigned)blocks), dim3(256), 0, s, a, list, mom, nteams);
     hipLaunchKernelGGL(k_boxel_eigen, dim3((unsigned)((ncomp + 255) / 256)), dim3(256), 0, s, a, list,
                        (const double*)mom);
     return hipGetLastError();
