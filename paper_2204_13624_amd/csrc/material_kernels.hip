@@ -223,11 +223,11 @@ __global__ void __launch_bounds__(128) k_material_laminate_b(const MatArgs<T>* _
 // ------------------------------------------------------------------------------
 // reductions of the per-block material sums (fixed order)
 // ------------------------------------------------------------------------------
+// column c of the sums: out[0..19) over pure blocks, out[19..50) over laminate blocks (49 = max)
 __device__ __forceinline__ void material_reduce_body(const double* pp, int nbp, const double* pl, int nbl,
-                                                     double* out) {
-    // out[0..19) = sums over pure blocks, out[19..50) = sums over laminate blocks (index 49 = max)
+                                                     double* out, int c) {
     __shared__ double sh[4];
-    for (int c = 0; c < 19 + 31; ++c) {
+    {
         const bool lam = c >= 19;
         const int cc = lam ? c - 19 : c;
         const int rows = lam ? nbl : nbp;
@@ -254,15 +254,16 @@ __device__ __forceinline__ void material_reduce_body(const double* pp, int nbp, 
     }
 }
 
+// one workgroup per column of the sums
 __global__ void __launch_bounds__(256) k_material_reduce(const double* pp, int nbp, const double* pl, int nbl,
                                                          double* out) {
-    material_reduce_body(pp, nbp, pl, nbl, out);
+    material_reduce_body(pp, nbp, pl, nbl, out, blockIdx.x);
 }
 
-// one workgroup per RVE
+// one workgroup per RVE and column
 __global__ void __launch_bounds__(256) k_material_reduce_b(const MatReduceArgs* __restrict__ red) {
     const MatReduceArgs r = red[blockIdx.x];
-    material_reduce_body(r.pp, r.nbp, r.pl, r.nbl, r.out);
+    material_reduce_body(r.pp, r.nbp, r.pl, r.nbl, r.out, blockIdx.y);
 }
 
 int material_blocks_pure(long long n) {
@@ -274,6 +275,8 @@ int material_blocks_laminate(int nc) {
     return b < 1 ? 1 : (b < 4096 ? b : 4096);
 }
 
+// The laminate kernel reads F at its composites from the pure kernel's output, so the two run
+// in order; the reduction takes one workgroup per column of the sums.
 template <typename T>
 hipError_t launch_material(const MatArgs<T>& a, int nbp, int nbl, double* sums_out, hipStream_t s) {
     hipLaunchKernelGGL(k_material_pure<T>, dim3(nbp), dim3(256), 0, s, a);
@@ -281,10 +284,9 @@ hipError_t launch_material(const MatArgs<T>& a, int nbp, int nbl, double* sums_o
     if (e != hipSuccess) return e;
     if (a.nc > 0) {
         hipLaunchKernelGGL(k_material_laminate<T>, dim3(nbl), dim3(128), 0, s, a);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_material_reduce, dim3(1), dim3(256), 0, s, a.partials, nbp, a.partials2,
+    hipLaunchKernelGGL(k_material_reduce, dim3(19 + 31), dim3(256), 0, s, a.partials, nbp, a.partials2,
                        a.nc > 0 ? nbl : 0, sums_out);
     return hipGetLastError();
 }
@@ -302,7 +304,7 @@ hipError_t launch_material_batch(const MatArgs<T>* dev_args, const BatchLaunch& 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_material_reduce_b, dim3(nrve), dim3(256), 0, s, dev_red);
+    hipLaunchKernelGGL(k_material_reduce_b, dim3(nrve, 19 + 31), dim3(256), 0, s, dev_red);
     return hipGetLastError();
 }
 
