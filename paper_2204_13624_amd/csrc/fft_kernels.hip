@@ -2194,6 +2194,8 @@ __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_inv_b(const Z
 #define COMBO_FFT2_CONFIGS(X)           \
     X(float, 256, 16, 16, 16, 0)        \
     X(float, 256, 16, 16, 8, 1)         \
+    X(float, 192, 16, 12, 16, 0)        \
+    X(float, 192, 12, 16, 16, 1)        \
     X(float, 128, 8, 16, 16, 0)         \
     X(float, 128, 16, 8, 16, 1)         \
     X(float, 96, 8, 12, 16, 0)          \
@@ -2205,6 +2207,7 @@ __global__ void __launch_bounds__((fft2_threads<P, Q, TX>())) k_z2_inv_b(const Z
     X(float, 32, 4, 8, 32, 0)           \
     X(float, 32, 8, 4, 32, 1)           \
     X(double, 256, 16, 16, 8, 0)        \
+    X(double, 192, 16, 12, 8, 0)        \
     X(double, 128, 8, 16, 8, 0)         \
     X(double, 96, 8, 12, 16, 0)         \
     X(double, 64, 8, 8, 16, 0)          \

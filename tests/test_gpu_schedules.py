@@ -45,7 +45,7 @@ def setup(ctx, ms, **opt):
 
 # every axis of these grids has two variants of its pass (x 256 and 64: rows per
 # workgroup; the others: radix order or tile width)
-GRIDS = [(64, 48, 32), (256, 32, 16), (32, 128, 96), (128, 96, 32)]
+GRIDS = [(64, 48, 32), (256, 32, 16), (32, 128, 96), (128, 96, 32), (32, 192, 48), (32, 48, 192)]
 
 
 @pytest.mark.parametrize("n", GRIDS)
